@@ -1,0 +1,161 @@
+"""Independent q-space Newton solvers (oracle parts O2 and O3), FP64.
+
+O2 -- Moreau-envelope FEM.  Minimizing the separated energy (eq. separated)
+over F and q jointly is the same as minimizing over q alone
+
+    Ehat(q) = sum_i e_i(G_i q),  e_i(A) = min_X vol_i Psi_i(X) + 1/2 beta_i |A - X|^2,
+
+because the ACAP term (eq. ACAPEnergy) is the only coupling and min_F min_q =
+min_q min_F.  So a plain Newton solve of Ehat reaches EMU's minimizer without
+sharing any of EMU's algorithm (no deformation-gradient iterates, no low-rank
+Hessian, no Woodbury).  grad_A e = beta (A - X*), and by the implicit function
+theorem on the prox condition vol P(X*) + beta (X* - A) = 0,
+hess_A e = beta I - beta^2 (vol d2Psi(X*) + beta I)^{-1}.
+
+O3 -- plain FEM on sum_i vol_i Psi_i(G_i q), the continuous problem of
+eq. continuum discretized with linear tets; EMU approaches it as alpha grows.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import material as mat
+from . import mesh as msh
+
+
+def _assemble(M, Hel):
+    """K = sum_i G_i^T H_i G_i for 9x9 element blocks (F coordinates), free DOFs."""
+    # K_i[(v,c),(v',c')] = sum_{d,d'} b[v,d] H[(c,d),(c',d')] b[v',d']
+    H4 = Hel.reshape(-1, 3, 3, 3, 3)
+    Ke = np.einsum("ivd,icdef,iwf->ivcwe", M.b, H4, M.b)       # [m,4,3,4,3]
+    dof = (3 * M.tets[:, :, None] + np.arange(3)[None, None, :]).reshape(-1, 12)
+    rows = np.repeat(dof, 12, axis=1).reshape(-1)
+    cols = np.tile(dof, (1, 12)).reshape(-1)
+    K = sp.coo_matrix((Ke.reshape(-1), (rows, cols)), shape=(3 * M.n, 3 * M.n)).tocsr()
+    fdof = (3 * M.free[:, None] + np.arange(3)[None, :]).reshape(-1)
+    return K[fdof][:, fdof].tocsc(), fdof
+
+
+def _scatter_grad(M, GA):
+    """sum_i G_i^T GA_i as [n,3]: out[v,c] = sum_i sum_d GA_i[c,d] b_{i,v}[d]."""
+    contrib = np.einsum("icd,ivd->ivc", GA, M.b)
+    out = np.zeros((M.n, 3))
+    np.add.at(out, M.tets.reshape(-1), contrib.reshape(-1, 3))
+    return out
+
+
+def prox(M, A, a_el, tol=1e-13, max_iters=100):
+    """X* = argmin_X vol Psi(X) + 1/2 beta |A - X|^2 per element (damped Newton from X = A)."""
+    X = A.copy()
+    vol, beta = M.vol, M.beta
+
+    def obj(X):
+        D = A - X
+        return vol * mat.psi(X, M.mu, M.lhat, a_el, M.kf, M.fiber) + 0.5 * beta * np.einsum("icd,icd->i", D, D)
+
+    scale = beta * (1.0 + np.sqrt(np.einsum("icd,icd->i", A, A)))
+    for _ in range(max_iters):
+        g = vol[:, None, None] * mat.pk1(X, M.mu, M.lhat, a_el, M.kf, M.fiber) + beta[:, None, None] * (X - A)
+        gn = np.sqrt(np.einsum("icd,icd->i", g, g))
+        if np.all(gn <= tol * scale):
+            break
+        H = vol[:, None, None] * mat.hess(X, M.mu, M.lhat, a_el, M.kf, M.fiber) + beta[:, None, None] * np.eye(9)
+        H = mat.clamp_psd(H) + 1e-300
+        step = -np.linalg.solve(H, g.reshape(-1, 9, 1)).reshape(-1, 3, 3)
+        f0 = obj(X)
+        t = np.ones(M.m)
+        for _ls in range(30):
+            f1 = obj(X + t[:, None, None] * step)
+            bad = f1 > f0 + 1e-4 * t * np.einsum("icd,icd->i", g, step) + 1e-15 * np.abs(f0)
+            if not bad.any():
+                break
+            t = np.where(bad, 0.5 * t, t)
+        X = X + t[:, None, None] * step
+    H = vol[:, None, None] * mat.hess(X, M.mu, M.lhat, a_el, M.kf, M.fiber) + beta[:, None, None] * np.eye(9)
+    return X, H
+
+
+def moreau_solve(M, a, q0=None, tol=1e-10, max_iters=200, history=False):
+    """O2: Newton on Ehat(q) with backtracking; returns q, the prox F = X* and stats."""
+    a_el = msh.activation_per_element(M, a)
+    q = M.rest.copy() if q0 is None else q0.copy()
+    q[M.pins] = M.pin_xyz
+    hist = []
+
+    def Ehat(q):
+        A = msh.gather_A(M, q)
+        X, H = prox(M, A, a_el)
+        D = A - X
+        e = M.vol * mat.psi(X, M.mu, M.lhat, a_el, M.kf, M.fiber) + 0.5 * M.beta * np.einsum("icd,icd->i", D, D)
+        return math.fsum(e), A, X, H
+
+    E, A, X, H = Ehat(q)
+    it = 0
+    while True:
+        GA = M.beta[:, None, None] * (A - X)
+        grad = _scatter_grad(M, GA)[M.free].reshape(-1)
+        gn = float(np.linalg.norm(grad))
+        if history:
+            hist.append((E, gn))
+        if gn <= tol or it >= max_iters:
+            break
+        Hinv = np.linalg.inv(H)
+        b2 = M.beta[:, None, None]
+        He = b2 * np.eye(9) - b2 ** 2 * Hinv
+        He = mat.clamp_psd(0.5 * (He + np.transpose(He, (0, 2, 1))))
+        K, _ = _assemble(M, He)
+        step = -spla.spsolve(K, grad)
+        t = 1.0
+        gs = float(grad @ step)
+        for _ls in range(60):
+            qt = q.copy()
+            qt[M.free] += t * step.reshape(-1, 3)
+            Et, At, Xt, Ht = Ehat(qt)
+            if Et <= E + 1e-4 * t * gs or abs(Et - E) <= 1e-15 * abs(E):
+                break
+            t *= 0.5
+        q, E, A, X, H = qt, Et, At, Xt, Ht
+        it += 1
+    out = dict(q=q, F=X, iters=it, gnorm=gn, energy=E)
+    if history:
+        out["history"] = hist
+    return out
+
+
+def fem_solve(M, a, q0=None, tol=1e-10, max_iters=200):
+    """O3: plain FEM Newton on sum_i vol_i Psi_i(G_i q) with clamped element Hessians."""
+    a_el = msh.activation_per_element(M, a)
+    q = M.rest.copy() if q0 is None else q0.copy()
+    q[M.pins] = M.pin_xyz
+
+    def energy(q):
+        A = msh.gather_A(M, q)
+        return math.fsum(M.vol * mat.psi(A, M.mu, M.lhat, a_el, M.kf, M.fiber)), A
+
+    E, A = energy(q)
+    it = 0
+    while True:
+        P = M.vol[:, None, None] * mat.pk1(A, M.mu, M.lhat, a_el, M.kf, M.fiber)
+        grad = _scatter_grad(M, P)[M.free].reshape(-1)
+        gn = float(np.linalg.norm(grad))
+        if gn <= tol or it >= max_iters:
+            break
+        He = mat.clamp_psd(M.vol[:, None, None] * mat.hess(A, M.mu, M.lhat, a_el, M.kf, M.fiber))
+        K, _ = _assemble(M, He)
+        step = -spla.spsolve(K, grad)
+        gs = float(grad @ step)
+        t = 1.0
+        for _ls in range(60):
+            qt = q.copy()
+            qt[M.free] += t * step.reshape(-1, 3)
+            Et, At = energy(qt)
+            if Et <= E + 1e-4 * t * gs or abs(Et - E) <= 1e-15 * abs(E):
+                break
+            t *= 0.5
+        q, E, A = qt, Et, At
+        it += 1
+    return dict(q=q, iters=it, gnorm=gn, energy=E)
