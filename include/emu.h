@@ -1,0 +1,182 @@
+/*
+ * emu.h -- C ABI of the MI355X (gfx950) EMU deformation-space quasi-static solver.
+ *
+ * Problem (the paper's problem statement, eq. continuum, with W = 0): given a
+ * tetrahedral rest mesh, per-tet stable Neo-Hookean materials, unit fiber
+ * directions and per-muscle-group activations a >= 0 (Sec. 3.1), and pinned
+ * vertices with target positions (Sec. 3.1: pins remove the rigid null space),
+ * find the deformed vertex positions q of the separated problem (eq. separated)
+ *
+ *   min_F  sum_i vol_i Psi_i(F_i) + alpha/2 sum_i w_i |A_i(q*(F)) - F_i|^2,
+ *   q*(F) = argmin_q ACAP(q, F)                       (eq. acap),
+ *
+ * with one free deformation gradient F_i per tet, A_i(q) the compatible
+ * gradient of eq. defograd and w_i the ACAP weights (Sec. 3.3 recommends
+ * stiffness-proportional weights).  The solver is the paper's quasi-Newton
+ * method (Sec. 3.2.1): exact gradient (eq. gradient), block-diagonal Hessian with
+ * a definiteness fix plus a k-mode low-rank coupling applied by the Woodbury
+ * identity (eq. Hessian-woodbury), and a backtracking Armijo line search
+ * (Algorithm 1).
+ *
+ * Conventions for every call:
+ *   - All arrays are row-major and use the caller's vertex and tet numbering.
+ *   - "host" pointers are read (or written) before the call returns; the
+ *     library keeps no reference to them.  "device" pointers are HIP device
+ *     memory on the mesh's device, accessed in stream order on `stream`.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *   - Calls never throw or abort.  They return EMU_OK (0) or an error code;
+ *     emu_last_error() returns a thread-local message for the last failure.
+ *   - A mesh handle is not thread-safe: calls on one handle must not overlap.
+ */
+#ifndef EMU_H
+#define EMU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct emu_mesh emu_mesh;
+
+typedef enum {
+  EMU_OK = 0,
+  EMU_E_INVALID = 1,        /* bad argument or mesh data                        */
+  EMU_E_SINGULAR = 2,       /* ACAP operator not positive definite (unpinned part) */
+  EMU_E_NOT_CONVERGED = 3,  /* max_iters reached; state and stats are kept      */
+  EMU_E_LINESEARCH = 4,     /* no Armijo step down to sigma0 * 2^-40            */
+  EMU_E_NONFINITE = 5,      /* NaN/Inf in energy, gradient or Woodbury system   */
+  EMU_E_OOM = 6,            /* device or host allocation failed                 */
+  EMU_E_HIP = 7,            /* a HIP runtime call failed                        */
+  EMU_E_STATE = 8,          /* call not valid in the current state              */
+  EMU_E_BUSY = 9            /* resource exhausted (serving slots or budget)     */
+} emu_status;
+
+enum { EMU_PRECISION_FP64 = 0, EMU_PRECISION_MIXED = 1 };
+enum { EMU_WEIGHT_STIFFNESS = 0, EMU_WEIGHT_VOLUME = 1 };
+
+/* Mesh description (host arrays, copied by emu_create_mesh). */
+typedef struct {
+  int32_t n_vertices;        /* n > 0                                             */
+  int32_t n_tets;            /* m > 0                                             */
+  int32_t n_groups;          /* muscle groups (>= 0)                              */
+  int32_t n_pins;            /* pinned vertices (>= 1 per connected component)    */
+  const double  *rest_xyz;   /* [n][3] rest positions (m)                         */
+  const int32_t *tets;       /* [m][4] vertex ids; orientation is fixed by the
+                                library (local vertices 1,2 swapped if the rest
+                                volume is negative, eq. defograd)                 */
+  const double  *youngs;     /* [m] Young's modulus (Pa), > 0                     */
+  const double  *poisson;    /* [m] Poisson ratio in (-1, 0.5)                    */
+  const double  *fiber;      /* [m][3] fiber direction u (Sec. 3.1), normalized by
+                                the library; ignored where group < 0              */
+  const int32_t *group;      /* [m] muscle group in [0, n_groups) or -1 (passive)  */
+  const int32_t *pins;       /* [n_pins] pinned vertex ids, unique                */
+  const double  *pin_xyz;    /* [n_pins][3] pin targets; NULL = rest positions    */
+  double alpha_hat;          /* alpha = alpha_hat * mu_ref (eq. separated); 0 -> 10 */
+  double mu_ref;             /* reference shear modulus; 0 -> smallest mu among
+                                tets with group >= 0 (all tets if none)          */
+  double fiber_k;            /* fiber stress scale k_f in Psi_fib = a k_f |F u|^2;
+                                0 -> mu_ref                                      */
+  int32_t weight_mode;       /* EMU_WEIGHT_STIFFNESS: w_i = vol_i mu_i / mu_ref;
+                                EMU_WEIGHT_VOLUME: w_i = vol_i                   */
+  int32_t n_modes;           /* k = 3 * (scalar modes), 0 <= k <= 48, k % 3 == 0;
+                                -1 -> 48 (eq. low-rank)                          */
+  int32_t precision;         /* EMU_PRECISION_FP64 or EMU_PRECISION_MIXED          */
+  int32_t leaf_size;         /* nested-dissection leaf size; 0 -> 64              */
+} emu_mesh_desc;
+
+/* Solve options.  Defaults (emu_solve_opts_default): grad_tol 1e-8,
+   max_iters 10000, sigma0 10, armijo_c 1e-4, rho 0.5, warm_start 1,
+   iters_per_sync 16 (Algorithm 1 constants). */
+typedef struct {
+  double grad_tol;           /* stop when |dE/dF|_2 <= grad_tol (J, absolute)      */
+  int32_t max_iters;
+  double sigma0, armijo_c, rho;
+  int32_t warm_start;        /* 1: start from the current state; 0: from rest     */
+  int32_t iters_per_sync;    /* iterations per host check of the stop flag       */
+  double stall_rel;          /* mixed precision only: also stop if no Armijo step
+                                exists and |g| <= stall_rel * |g_0|; 0 disables  */
+} emu_solve_opts;
+
+typedef struct {
+  int32_t status;            /* emu_status of the solve                           */
+  int32_t iters;             /* accepted quasi-Newton iterations                  */
+  int32_t ls_trials;         /* Armijo trials (each O(1): the energy change is an
+                                exact polynomial in sigma)                        */
+  int32_t acap_solves;       /* factored ACAP solves                              */
+  int32_t inverted;          /* tets with det F <= 0 at the end                   */
+  int32_t clamped;           /* element Hessian blocks clamped in the last pass   */
+  double energy;             /* E at the end (J)                                  */
+  double grad_norm;          /* |dE/dF|_2 at the end                              */
+  double grad_norm0;         /* |dE/dF|_2 at the start                            */
+  double ms_total;           /* device time of the call (hipEvent)                */
+} emu_solve_stats;
+
+/* Static information about a mesh. */
+typedef struct {
+  int32_t n_vertices, n_tets, n_free, n_modes;
+  int32_t n_supernodes, n_levels;
+  int64_t factor_nnz;        /* stored factor entries (dense supernode blocks)    */
+  int64_t device_bytes;      /* device memory held by the mesh                    */
+  double mu_ref, alpha, fiber_k;
+  double setup_ms;           /* host setup time (ordering, factor, modes, upload) */
+  double mode_captured;      /* sum_{j<=k/3} 1/nu_j / trace(L_ff^{-1}) estimate    */
+} emu_mesh_info;
+
+emu_solve_opts emu_solve_opts_default(void);
+const char* emu_last_error(void);
+
+/* Build a mesh: validate, orient, compute geometry and ACAP weights, assemble
+   the weighted Laplacian L_w (the q-Hessian of the ACAP energy, eq. ACAPEnergy,
+   is L_w (x) I_3), order it by nested dissection, factor L_ff once (Sec. 3.2:
+   prefactor the constant matrix), compute its k/3 lowest eigenpairs (eq.
+   low-rank) and upload everything to the current HIP device.  The state starts
+   at rest (F_i = I).  Errors: EMU_E_INVALID (see desc), EMU_E_SINGULAR (a
+   connected part without pins), EMU_E_OOM, EMU_E_HIP. */
+emu_status emu_create_mesh(const emu_mesh_desc* desc, emu_mesh** out);
+emu_status emu_destroy_mesh(emu_mesh* mesh);
+emu_status emu_mesh_get_info(const emu_mesh* mesh, emu_mesh_info* info);
+
+/* Per-group activations a(t) >= 0 (Sec. 3.1), host [n_groups]. */
+emu_status emu_set_activation(emu_mesh* mesh, const double* a);
+
+/* New pin targets (host [n_pins][3]) for scripted boundaries; the factor is
+   unchanged, only the constant pinned right-hand side is recomputed. */
+emu_status emu_set_pin_targets(emu_mesh* mesh, const double* pin_xyz);
+
+/* Replace the low-rank modes (eq. low-rank): k1 = k/3 scalar modes, nu host
+   [k1] > 0, phi host [k1][n] (values at pinned vertices are ignored). */
+emu_status emu_set_modes(emu_mesh* mesh, int32_t k1, const double* nu, const double* phi);
+/* Read the modes currently used (host nu [k1], phi [k1][n]; either may be NULL). */
+emu_status emu_get_modes(const emu_mesh* mesh, double* nu, double* phi);
+
+/* Run the quasi-Newton iteration until |dE/dF|_2 <= grad_tol.  q_out: device
+   [n][3] or NULL.  stats may be NULL.  Returns EMU_OK, EMU_E_NOT_CONVERGED,
+   EMU_E_LINESEARCH or EMU_E_NONFINITE; the state is kept in every case. */
+emu_status emu_solve(emu_mesh* mesh, const emu_solve_opts* opts, double* q_out,
+                     emu_solve_stats* stats, void* stream);
+
+/* Adjoint of the equilibrium w.r.t. the group activations at the current
+   (converged) state: given dL/dq (device [n][3]), write dL/da (host
+   [n_groups]).  Requires a converged emu_solve at the current activations
+   (EMU_E_STATE otherwise). */
+emu_status emu_solve_grad(emu_mesh* mesh, const double* dL_dq, double* dL_da,
+                          emu_solve_stats* stats, void* stream);
+
+/* State access: F device [m][9] (row-major 3x3 per tet), q device [n][3].
+   emu_set_state takes F, splits it as F = R S and re-solves q = q*(F). */
+emu_status emu_get_state(const emu_mesh* mesh, double* F, double* q, void* stream);
+emu_status emu_set_state(emu_mesh* mesh, const double* F, void* stream);
+
+/* Evaluate at a given state F (device [m][9]) without changing the mesh state:
+   q = q*(F) (device [n][3] or NULL), the energy E (eq. separated) and
+   |dE/dF|_2 (host scalars, either may be NULL), and the quasi-Newton direction
+   d = Htilde^{-1} dE/dF (device [m][9] in F coordinates, or NULL). */
+emu_status emu_evaluate(emu_mesh* mesh, const double* F, double* q, double* energy,
+                        double* grad_norm, double* direction, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EMU_H */

@@ -1,0 +1,668 @@
+// C ABI of the device library (include/emu.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/emu.h"
+#include "device.hpp"
+#include "host_setup.hpp"
+#include "kernels.hpp"
+
+namespace emu {
+const std::string& last_error_str();
+}
+
+#define HIPCHK(x)                                                                   \
+  do {                                                                              \
+    hipError_t e_ = (x);                                                            \
+    if (e_ != hipSuccess)                                                           \
+      throw emu::Error{EMU_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+namespace {
+
+__global__ void k_to_user_q(const double* q, const int32_t* vold, int n, double* out) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int u = vold[v];
+  out[3 * u] = q[3 * v];
+  out[3 * u + 1] = q[3 * v + 1];
+  out[3 * u + 2] = q[3 * v + 2];
+}
+__global__ void k_from_user_q(const double* in, const int32_t* vold, int n, double* q) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int u = vold[v];
+  q[3 * v] = in[3 * u];
+  q[3 * v + 1] = in[3 * u + 1];
+  q[3 * v + 2] = in[3 * u + 2];
+}
+
+}  // namespace
+
+struct emu_mesh {
+  emu::HostMesh hm;
+  emu::DevMesh d{};
+  emu::SolvePlan plan;
+  int device = 0;
+  hipStream_t st = nullptr;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
+  std::vector<void*> allocs;
+  int64_t bytes = 0;
+  int32_t* d_eold = nullptr;
+  int32_t* d_vold = nullptr;
+  emu::Ctl* h_ctl = nullptr;  // pinned host copy
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int graph_iters = 0;
+  std::vector<double> act;
+  bool converged = false;
+  // backup of the state for emu_evaluate
+  double *R_bak = nullptr, *S_bak = nullptr, *q_bak = nullptr;
+
+  template <typename T>
+  T* dalloc(size_t count) {
+    void* p = nullptr;
+    size_t nb = std::max<size_t>(1, count * sizeof(T));
+    hipError_t e = hipMalloc(&p, nb);
+    if (e != hipSuccess) throw emu::Error{EMU_E_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
+    allocs.push_back(p);
+    bytes += (int64_t)nb;
+    return (T*)p;
+  }
+  template <typename T>
+  T* upload(const std::vector<T>& v) {
+    T* p = dalloc<T>(v.size());
+    if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return p;
+  }
+  ~emu_mesh() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (void* p : allocs) (void)hipFree(p);
+    if (h_ctl) (void)hipHostFree(h_ctl);
+    if (ev_a) (void)hipEventDestroy(ev_a);
+    if (ev_b) (void)hipEventDestroy(ev_b);
+    if (ev_t0) (void)hipEventDestroy(ev_t0);
+    if (ev_t1) (void)hipEventDestroy(ev_t1);
+    if (st) (void)hipStreamDestroy(st);
+  }
+};
+
+namespace {
+
+emu_status fail_with(const emu::Error& e) {
+  emu::set_error(e.msg);
+  return e.code;
+}
+
+void upload_modes(emu_mesh* M) {
+  const auto& hm = M->hm;
+  std::vector<double> phi((size_t)emu::kMaxK1 * hm.n, 0.0), nu(emu::kMaxK1, 1.0);
+  for (int j = 0; j < hm.k1; ++j) {
+    nu[j] = hm.nu[j];
+    for (int32_t f = 0; f < hm.nf; ++f) phi[(size_t)emu::kMaxK1 * f + j] = hm.phi[(size_t)j * hm.nf + f];
+  }
+  HIPCHK(hipMemcpy((void*)M->d.phi, phi.data(), phi.size() * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy((void*)M->d.nu, nu.data(), nu.size() * 8, hipMemcpyHostToDevice));
+}
+
+void upload_pins(emu_mesh* M) {
+  const auto& hm = M->hm;
+  HIPCHK(hipMemcpy((void*)M->d.pin_rhs, hm.pin_rhs.data(), hm.pin_rhs.size() * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy((void*)M->d.pin_xyz, hm.pin_xyz.data(), hm.pin_xyz.size() * 8, hipMemcpyHostToDevice));
+}
+
+void build_device(emu_mesh* M) {
+  auto& hm = M->hm;
+  auto& d = M->d;
+  const int32_t n = hm.n, m = hm.m, nf = hm.nf;
+  const auto& fac = hm.fac;
+  for (int s = 0; s < fac.ns; ++s)
+    if (fac.w[s] > emu::kMaxFrontW)
+      throw emu::Error{EMU_E_INVALID, "separator wider than " + std::to_string(emu::kMaxFrontW) + " vertices"};
+  HIPCHK(hipGetDevice(&M->device));
+  HIPCHK(hipStreamCreateWithFlags(&M->st, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&M->ev_a, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&M->ev_b, hipEventDisableTiming));
+  HIPCHK(hipEventCreate(&M->ev_t0));
+  HIPCHK(hipEventCreate(&M->ev_t1));
+  HIPCHK(hipHostMalloc((void**)&M->h_ctl, sizeof(emu::Ctl), hipHostMallocDefault));
+  std::memset(M->h_ctl, 0, sizeof(emu::Ctl));
+
+  d.n = n;
+  d.nf = nf;
+  d.m = m;
+  d.k1 = hm.k1;
+  d.npins = hm.npins;
+  d.ngroups = hm.ngroups;
+  d.nb = std::max(1, std::min((m + emu::kBlock - 1) / emu::kBlock, 1024));
+  d.nbg = std::max(1, std::min((m + 63) / 64, 256));
+  d.mixed = hm.precision == EMU_PRECISION_MIXED;
+  d.alpha = hm.alpha;
+  d.kf = hm.kf;
+
+  // element arrays in internal order (structure of arrays)
+  std::vector<int32_t> vid(4 * (size_t)m);
+  std::vector<double> dminv(9 * (size_t)m), vol(m), mu(m), lhat(m), w(m), fib(3 * (size_t)m);
+  std::vector<int32_t> grp(m);
+  for (int32_t e = 0; e < m; ++e) {
+    const int32_t o = hm.eold[e];
+    for (int k = 0; k < 4; ++k) vid[(size_t)k * m + e] = hm.vnew[hm.tets[4 * (size_t)o + k]];
+    for (int k = 0; k < 9; ++k) dminv[(size_t)k * m + e] = hm.dminv[9 * (size_t)o + k];
+    vol[e] = hm.vol[o];
+    mu[e] = hm.mu[o];
+    lhat[e] = hm.lhat[o];
+    w[e] = hm.w[o];
+    for (int c = 0; c < 3; ++c) fib[(size_t)c * m + e] = hm.fiber[3 * (size_t)o + c];
+    grp[e] = hm.group[o];
+  }
+  d.vid = M->upload(vid);
+  d.dminv = M->upload(dminv);
+  d.vol = M->upload(vol);
+  d.mu = M->upload(mu);
+  d.lhat = M->upload(lhat);
+  d.w = M->upload(w);
+  d.fib = M->upload(fib);
+  d.grp = M->upload(grp);
+  d.R = M->dalloc<double>(9 * (size_t)m);
+  d.S = M->dalloc<double>(6 * (size_t)m);
+  const size_t tsz = d.mixed ? 4 : 8;
+  d.gbar = M->dalloc<char>(9 * (size_t)m * tsz);
+  d.Lf = M->dalloc<char>(27 * (size_t)m * tsz);
+  d.p = M->dalloc<double>(9 * (size_t)m);
+  d.contrib = M->dalloc<double>(12 * (size_t)m);
+  std::vector<double> zeros3(3 * (size_t)n, 0.0);
+  d.q = M->upload(zeros3);
+  d.dq = M->upload(zeros3);
+  d.uz = M->upload(zeros3);
+  d.phi = M->dalloc<double>((size_t)emu::kMaxK1 * n);
+  d.nu = M->dalloc<double>(emu::kMaxK1);
+  M->act.assign(std::max(1, hm.ngroups), 0.0);
+  d.act = M->upload(M->act);
+  d.pin_rhs = M->dalloc<double>(3 * (size_t)nf);
+  d.pin_xyz = M->dalloc<double>(3 * (size_t)hm.npins);
+  // incidence of free vertices (fixed element order)
+  {
+    std::vector<int32_t> cnt(nf + 1, 0);
+    for (int32_t e = 0; e < m; ++e)
+      for (int k = 0; k < 4; ++k) {
+        int32_t v = vid[(size_t)k * m + e];
+        if (v < nf) cnt[v + 1]++;
+      }
+    for (int32_t v = 0; v < nf; ++v) cnt[v + 1] += cnt[v];
+    std::vector<int32_t> inc(cnt[nf]);
+    std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int32_t e = 0; e < m; ++e)
+      for (int k = 0; k < 4; ++k) {
+        int32_t v = vid[(size_t)k * m + e];
+        if (v < nf) inc[pos[v]++] = 4 * e + k;
+      }
+    d.inc_ptr = M->upload(cnt);
+    d.inc = M->upload(inc);
+  }
+  // factor and level schedule
+  {
+    std::vector<int32_t> front(fac.ns + 1, 0);
+    for (int s = 0; s < fac.ns; ++s) front[s + 1] = front[s] + fac.h[s];
+    // children's update rows by destination position in the parent front
+    std::vector<std::vector<int32_t>> lists(front[fac.ns]);
+    for (int s = 0; s < fac.ns; ++s) {
+      const int w = fac.w[s], h = fac.h[s];
+      const int32_t c0 = fac.col0[s];
+      const int32_t* rs = fac.rows.data() + fac.rowoff[s];
+      for (int k = fac.child_ptr[s]; k < fac.child_ptr[s + 1]; ++k) {
+        const int c = fac.child_idx[k];
+        const int hb = fac.h[c] - fac.w[c];
+        for (int a = 0; a < hb; ++a) {
+          const int32_t v = fac.rows[fac.rowoff[c] + a];
+          int p = v < c0 + w ? v - c0 : w + (int)(std::lower_bound(rs, rs + (h - w), v) - rs);
+          lists[front[s] + p].push_back(fac.rowoff[c] + a);
+        }
+      }
+    }
+    std::vector<int32_t> gptr(front[fac.ns] + 1, 0), gsrc;
+    for (size_t i = 0; i < lists.size(); ++i) {
+      gsrc.insert(gsrc.end(), lists[i].begin(), lists[i].end());
+      gptr[i + 1] = (int32_t)gsrc.size();
+    }
+    std::vector<int2> fwd, bwd;
+    auto& pl = M->plan;
+    pl.nlevels = fac.nlevels;
+    pl.fwd_ptr.assign(fac.nlevels + 1, 0);
+    pl.bwd_ptr.assign(fac.nlevels + 1, 0);
+    for (int L = 0; L < fac.nlevels; ++L) {
+      for (int s = 0; s < fac.ns; ++s)
+        if (fac.level[s] == L)
+          for (int r = 0; r < fac.h[s]; r += emu::kTriRows) fwd.push_back(make_int2(s, r));
+      pl.fwd_ptr[L + 1] = (int)fwd.size();
+    }
+    for (int L = fac.nlevels - 1, k = 0; L >= 0; --L, ++k) {
+      for (int s = 0; s < fac.ns; ++s)
+        if (fac.level[s] == L)
+          for (int c = 0; c < fac.w[s]; c += emu::kTriRows) bwd.push_back(make_int2(s, c));
+      pl.bwd_ptr[k + 1] = (int)bwd.size();
+    }
+    d.sn_col0 = M->upload(fac.col0);
+    d.sn_w = M->upload(fac.w);
+    d.sn_h = M->upload(fac.h);
+    d.sn_rowoff = M->upload(fac.rowoff);
+    d.sn_valoff = M->upload(fac.valoff);
+    d.sn_front = M->upload(front);
+    d.rows = M->upload(fac.rows);
+    d.vals = M->upload(fac.vals);
+    d.gptr = M->upload(gptr);
+    d.gsrc = M->upload(gsrc);
+    d.fwd_items = M->upload(fwd);
+    d.bwd_items = M->upload(bwd);
+    d.rhs = M->dalloc<double>(3 * (size_t)nf);
+    d.ybuf = M->dalloc<double>(3 * (size_t)nf);
+    d.xbuf = M->dalloc<double>(3 * (size_t)nf);
+    d.upd = M->dalloc<double>(3 * (size_t)std::max<int32_t>(1, fac.rowoff[fac.ns]));
+  }
+  d.part_e = M->dalloc<double>(2 * (size_t)d.nb);
+  d.part_g = M->dalloc<double>(2 * (size_t)d.nb);
+  d.part_cnt = M->dalloc<int32_t>(2 * (size_t)d.nb);
+  d.part_gram = M->dalloc<double>((size_t)emu::kGramEntries * d.nbg);
+  d.gram = M->dalloc<double>(emu::kGramEntries);
+  {
+    std::vector<double> z(48, 0.0);
+    d.zbuf = M->upload(z);
+  }
+  d.part_ls = M->dalloc<double>(2 * (size_t)emu::kLsTerms * d.nb);
+  d.ctl = M->dalloc<emu::Ctl>(1);
+  M->d_eold = M->upload(hm.eold);
+  M->d_vold = M->upload(hm.vold);
+  upload_modes(M);
+  upload_pins(M);
+}
+
+void fresh_solve(emu_mesh* M) {
+  emu::launch_scatter_F(M->d, M->st);
+  emu::launch_solve(M->d, M->plan, 1, M->d.q, 0, M->st);
+  emu::launch_set_pins(M->d, M->st);
+}
+
+void init_ctl(emu_mesh* M, const emu_solve_opts& o, int eval_only) {
+  emu::Ctl& c = *M->h_ctl;
+  std::memset(&c, 0, sizeof(c));
+  c.max_iters = o.max_iters;
+  c.eval_only = eval_only;
+  c.tol2 = o.grad_tol * o.grad_tol;
+  c.gnorm0_2 = -1.0;
+  c.sigma0 = o.sigma0;
+  c.armijo_c = o.armijo_c;
+  c.rho = o.rho;
+  c.stall_rel = M->d.mixed ? o.stall_rel : 0.0;
+  c.solves = 1;
+  HIPCHK(hipMemcpyAsync(M->d.ctl, &c, sizeof(c), hipMemcpyHostToDevice, M->st));
+}
+
+void read_ctl(emu_mesh* M) {
+  HIPCHK(hipMemcpyAsync(M->h_ctl, M->d.ctl, sizeof(emu::Ctl), hipMemcpyDeviceToHost, M->st));
+  HIPCHK(hipStreamSynchronize(M->st));
+}
+
+void ensure_graph(emu_mesh* M, int iters) {
+  if (M->gexec && M->graph_iters == iters) return;
+  if (M->gexec) HIPCHK(hipGraphExecDestroy(M->gexec));
+  if (M->graph) HIPCHK(hipGraphDestroy(M->graph));
+  M->gexec = nullptr;
+  M->graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(M->st, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < iters; ++k) emu::launch_iteration(M->d, M->plan, M->st);
+  HIPCHK(hipStreamEndCapture(M->st, &M->graph));
+  HIPCHK(hipGraphInstantiate(&M->gexec, M->graph, nullptr, nullptr, 0));
+  M->graph_iters = iters;
+}
+
+void join_user_stream(emu_mesh* M, void* stream) {
+  HIPCHK(hipEventRecord(M->ev_a, (hipStream_t)stream));
+  HIPCHK(hipStreamWaitEvent(M->st, M->ev_a, 0));
+}
+void release_user_stream(emu_mesh* M, void* stream) {
+  HIPCHK(hipEventRecord(M->ev_b, M->st));
+  HIPCHK(hipStreamWaitEvent((hipStream_t)stream, M->ev_b, 0));
+}
+
+void fill_stats(emu_mesh* M, emu_solve_stats* s, float ms) {
+  if (!s) return;
+  const emu::Ctl& c = *M->h_ctl;
+  s->status = c.status;
+  s->iters = c.iter;
+  s->ls_trials = c.trials;
+  s->acap_solves = c.solves;
+  s->inverted = c.inverted;
+  s->clamped = c.clamped;
+  s->energy = c.energy;
+  s->grad_norm = std::sqrt(std::max(0.0, c.gnorm2));
+  s->grad_norm0 = std::sqrt(std::max(0.0, c.gnorm0_2));
+  s->ms_total = ms;
+}
+
+void backup_state(emu_mesh* M) {
+  const size_t m = M->hm.m, n = M->hm.n;
+  if (!M->R_bak) {
+    M->R_bak = M->dalloc<double>(9 * m);
+    M->S_bak = M->dalloc<double>(6 * m);
+    M->q_bak = M->dalloc<double>(3 * n);
+  }
+  HIPCHK(hipMemcpyAsync(M->R_bak, M->d.R, 72 * m, hipMemcpyDeviceToDevice, M->st));
+  HIPCHK(hipMemcpyAsync(M->S_bak, M->d.S, 48 * m, hipMemcpyDeviceToDevice, M->st));
+  HIPCHK(hipMemcpyAsync(M->q_bak, M->d.q, 24 * n, hipMemcpyDeviceToDevice, M->st));
+}
+void restore_state(emu_mesh* M) {
+  const size_t m = M->hm.m, n = M->hm.n;
+  HIPCHK(hipMemcpyAsync(M->d.R, M->R_bak, 72 * m, hipMemcpyDeviceToDevice, M->st));
+  HIPCHK(hipMemcpyAsync(M->d.S, M->S_bak, 48 * m, hipMemcpyDeviceToDevice, M->st));
+  HIPCHK(hipMemcpyAsync(M->d.q, M->q_bak, 24 * n, hipMemcpyDeviceToDevice, M->st));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* emu_last_error(void) { return emu::last_error_str().c_str(); }
+
+emu_solve_opts emu_solve_opts_default(void) {
+  emu_solve_opts o;
+  o.grad_tol = 1e-8;
+  o.max_iters = 10000;
+  o.sigma0 = 10.0;
+  o.armijo_c = 1e-4;
+  o.rho = 0.5;
+  o.warm_start = 1;
+  o.iters_per_sync = 16;
+  o.stall_rel = 1e-6;
+  return o;
+}
+
+emu_status emu_create_mesh(const emu_mesh_desc* desc, emu_mesh** out) {
+  if (!desc || !out) {
+    emu::set_error("NULL argument");
+    return EMU_E_INVALID;
+  }
+  *out = nullptr;
+  emu_mesh* M = nullptr;
+  try {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
+      throw emu::Error{EMU_E_HIP, "no HIP device available"};
+    M = new emu_mesh();
+    auto t0 = std::chrono::steady_clock::now();
+    emu::host_setup(*desc, M->hm, true);
+    build_device(M);
+    emu::launch_init_rest(M->d, M->st);
+    emu_solve_opts o = emu_solve_opts_default();
+    init_ctl(M, o, 0);
+    fresh_solve(M);
+    HIPCHK(hipStreamSynchronize(M->st));
+    HIPCHK(hipGetLastError());
+    M->hm.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = M;
+    return EMU_OK;
+  } catch (const emu::Error& e) {
+    delete M;
+    return fail_with(e);
+  } catch (const std::bad_alloc&) {
+    delete M;
+    emu::set_error("host allocation failed");
+    return EMU_E_OOM;
+  }
+}
+
+emu_status emu_destroy_mesh(emu_mesh* mesh) {
+  if (mesh) {
+    (void)hipStreamSynchronize(mesh->st);
+    delete mesh;
+  }
+  return EMU_OK;
+}
+
+emu_status emu_mesh_get_info(const emu_mesh* M, emu_mesh_info* info) {
+  if (!M || !info) {
+    emu::set_error("NULL argument");
+    return EMU_E_INVALID;
+  }
+  const auto& hm = M->hm;
+  std::memset(info, 0, sizeof(*info));
+  info->n_vertices = hm.n;
+  info->n_tets = hm.m;
+  info->n_free = hm.nf;
+  info->n_modes = 3 * hm.k1;
+  info->n_supernodes = hm.fac.ns;
+  info->n_levels = hm.fac.nlevels;
+  info->factor_nnz = hm.fac.nnz();
+  info->device_bytes = M->bytes;
+  info->mu_ref = hm.mu_ref;
+  info->alpha = hm.alpha;
+  info->fiber_k = hm.kf;
+  info->setup_ms = hm.setup_ms;
+  info->mode_captured = hm.mode_captured;
+  return EMU_OK;
+}
+
+emu_status emu_set_activation(emu_mesh* M, const double* a) {
+  if (!M || (!a && M->hm.ngroups > 0)) {
+    emu::set_error("NULL argument");
+    return EMU_E_INVALID;
+  }
+  try {
+    for (int g = 0; g < M->hm.ngroups; ++g)
+      if (!(a[g] >= 0.0) || !std::isfinite(a[g])) throw emu::Error{EMU_E_INVALID, "activations must be finite and >= 0"};
+    for (int g = 0; g < M->hm.ngroups; ++g) M->act[g] = a[g];
+    HIPCHK(hipMemcpyAsync((void*)M->d.act, M->act.data(), M->act.size() * 8, hipMemcpyHostToDevice, M->st));
+    HIPCHK(hipStreamSynchronize(M->st));
+    M->converged = false;
+    return EMU_OK;
+  } catch (const emu::Error& e) {
+    return fail_with(e);
+  }
+}
+
+emu_status emu_set_pin_targets(emu_mesh* M, const double* pin_xyz) {
+  if (!M || !pin_xyz) {
+    emu::set_error("NULL argument");
+    return EMU_E_INVALID;
+  }
+  try {
+    for (int i = 0; i < 3 * M->hm.npins; ++i)
+      if (!std::isfinite(pin_xyz[i])) throw emu::Error{EMU_E_INVALID, "non-finite pin target"};
+    M->hm.pin_xyz.assign(pin_xyz, pin_xyz + 3 * (size_t)M->hm.npins);
+    emu::recompute_pin_rhs(M->hm);
+    HIPCHK(hipStreamSynchronize(M->st));
+    upload_pins(M);
+    M->converged = false;
+    return EMU_OK;
+  } catch (const emu::Error& e) {
+    return fail_with(e);
+  }
+}
+
+emu_status emu_set_modes(emu_mesh* M, int32_t k1, const double* nu, const double* phi) {
+  if (!M || (k1 > 0 && (!nu || !phi))) {
+    emu::set_error("NULL argument");
+    return EMU_E_INVALID;
+  }
+  try {
+    auto& hm = M->hm;
+    if (k1 < 0 || k1 > emu::kMaxK1 || k1 >= hm.nf) throw emu::Error{EMU_E_INVALID, "k1 out of range"};
+    for (int j = 0; j < k1; ++j)
+      if (!(nu[j] > 0) || !std::isfinite(nu[j])) throw emu::Error{EMU_E_INVALID, "mode eigenvalues must be > 0"};
+    hm.k1 = k1;
+    hm.nu.assign(nu, nu + k1);
+    hm.phi.assign((size_t)k1 * hm.nf, 0.0);
+    for (int j = 0; j < k1; ++j)
+      for (int32_t f = 0; f < hm.nf; ++f) hm.phi[(size_t)j * hm.nf + f] = phi[(size_t)j * hm.n + hm.vold[f]];
+    HIPCHK(hipStreamSynchronize(M->st));
+    upload_modes(M);
+    M->d.k1 = k1;
+    if (M->gexec) {  // kernels take the mesh by value: rebuild the graph
+      HIPCHK(hipGraphExecDestroy(M->gexec));
+      HIPCHK(hipGraphDestroy(M->graph));
+      M->gexec = nullptr;
+      M->graph = nullptr;
+    }
+    return EMU_OK;
+  } catch (const emu::Error& e) {
+    return fail_with(e);
+  }
+}
+
+emu_status emu_get_modes(const emu_mesh* M, double* nu, double* phi) {
+  if (!M) {
+    emu::set_error("NULL argument");
+    return EMU_E_INVALID;
+  }
+  const auto& hm = M->hm;
+  if (nu)
+    for (int j = 0; j < hm.k1; ++j) nu[j] = hm.nu[j];
+  if (phi) {
+    std::memset(phi, 0, sizeof(double) * (size_t)hm.k1 * hm.n);
+    for (int j = 0; j < hm.k1; ++j)
+      for (int32_t f = 0; f < hm.nf; ++f) phi[(size_t)j * hm.n + hm.vold[f]] = hm.phi[(size_t)j * hm.nf + f];
+  }
+  return EMU_OK;
+}
+
+emu_status emu_solve(emu_mesh* M, const emu_solve_opts* opts, double* q_out, emu_solve_stats* stats,
+                     void* stream) {
+  if (!M) {
+    emu::set_error("NULL argument");
+    return EMU_E_INVALID;
+  }
+  try {
+    emu_solve_opts o = opts ? *opts : emu_solve_opts_default();
+    if (!(o.grad_tol >= 0) || o.max_iters < 0 || !(o.sigma0 > 0) || !(o.rho > 0 && o.rho < 1) ||
+        !(o.armijo_c > 0 && o.armijo_c < 1))
+      throw emu::Error{EMU_E_INVALID, "invalid solve options"};
+    const int per = o.iters_per_sync > 0 ? std::min(o.iters_per_sync, 256) : 16;
+    join_user_stream(M, stream);
+    HIPCHK(hipEventRecord(M->ev_t0, M->st));
+    if (!o.warm_start) emu::launch_init_rest(M->d, M->st);
+    init_ctl(M, o, 0);
+    fresh_solve(M);
+    ensure_graph(M, per);
+    const int max_launch = o.max_iters / per + 2;
+    for (int k = 0; k < max_launch; ++k) {
+      HIPCHK(hipGraphLaunch(M->gexec, M->st));
+      read_ctl(M);
+      if (M->h_ctl->done) break;
+    }
+    if (!M->h_ctl->done) {
+      // the iteration cap was reached between two checks
+      M->h_ctl->status = EMU_E_NOT_CONVERGED;
+    }
+    if (q_out) {
+      hipLaunchKernelGGL(k_to_user_q, dim3((M->hm.n + 255) / 256), dim3(256), 0, M->st, M->d.q, M->d_vold,
+                         M->hm.n, q_out);
+    }
+    HIPCHK(hipEventRecord(M->ev_t1, M->st));
+    HIPCHK(hipEventSynchronize(M->ev_t1));
+    HIPCHK(hipGetLastError());
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, M->ev_t0, M->ev_t1));
+    fill_stats(M, stats, ms);
+    release_user_stream(M, stream);
+    emu_status st = (emu_status)M->h_ctl->status;
+    M->converged = st == EMU_OK;
+    if (st != EMU_OK)
+      emu::set_error(st == EMU_E_NOT_CONVERGED ? "max_iters reached"
+                     : st == EMU_E_LINESEARCH  ? "line search found no Armijo step"
+                                               : "non-finite value in the iteration");
+    return st;
+  } catch (const emu::Error& e) {
+    return fail_with(e);
+  }
+}
+
+emu_status emu_get_state(const emu_mesh* Mc, double* F, double* q, void* stream) {
+  emu_mesh* M = const_cast<emu_mesh*>(Mc);
+  if (!M) {
+    emu::set_error("NULL argument");
+    return EMU_E_INVALID;
+  }
+  try {
+    join_user_stream(M, stream);
+    if (F) emu::launch_get_F(M->d, F, M->d_eold, M->st);
+    if (q)
+      hipLaunchKernelGGL(k_to_user_q, dim3((M->hm.n + 255) / 256), dim3(256), 0, M->st, M->d.q, M->d_vold,
+                         M->hm.n, q);
+    HIPCHK(hipGetLastError());
+    release_user_stream(M, stream);
+    return EMU_OK;
+  } catch (const emu::Error& e) {
+    return fail_with(e);
+  }
+}
+
+emu_status emu_set_state(emu_mesh* M, const double* F, void* stream) {
+  if (!M || !F) {
+    emu::set_error("NULL argument");
+    return EMU_E_INVALID;
+  }
+  try {
+    join_user_stream(M, stream);
+    emu::launch_set_F(M->d, F, M->d_eold, M->st);
+    fresh_solve(M);
+    HIPCHK(hipGetLastError());
+    release_user_stream(M, stream);
+    M->converged = false;
+    return EMU_OK;
+  } catch (const emu::Error& e) {
+    return fail_with(e);
+  }
+}
+
+emu_status emu_evaluate(emu_mesh* M, const double* F, double* q, double* energy, double* grad_norm,
+                        double* direction, void* stream) {
+  if (!M || !F) {
+    emu::set_error("NULL argument");
+    return EMU_E_INVALID;
+  }
+  try {
+    join_user_stream(M, stream);
+    backup_state(M);
+    emu::launch_set_F(M->d, F, M->d_eold, M->st);
+    emu_solve_opts o = emu_solve_opts_default();
+    init_ctl(M, o, 1);
+    fresh_solve(M);
+    emu::launch_evaluate(M->d, M->st);
+    if (q)
+      hipLaunchKernelGGL(k_to_user_q, dim3((M->hm.n + 255) / 256), dim3(256), 0, M->st, M->d.q, M->d_vold,
+                         M->hm.n, q);
+    if (direction) emu::launch_get_dir(M->d, direction, M->d_eold, M->st);
+    read_ctl(M);
+    restore_state(M);
+    HIPCHK(hipStreamSynchronize(M->st));
+    HIPCHK(hipGetLastError());
+    release_user_stream(M, stream);
+    if (energy) *energy = M->h_ctl->energy;
+    if (grad_norm) *grad_norm = std::sqrt(std::max(0.0, M->h_ctl->gnorm2));
+    return EMU_OK;
+  } catch (const emu::Error& e) {
+    return fail_with(e);
+  }
+}
+
+emu_status emu_solve_grad(emu_mesh* M, const double* dL_dq, double* dL_da, emu_solve_stats* stats,
+                          void* stream) {
+  (void)dL_dq;
+  (void)dL_da;
+  (void)stats;
+  (void)stream;
+  if (!M) {
+    emu::set_error("NULL argument");
+    return EMU_E_INVALID;
+  }
+  emu::set_error("emu_solve_grad: not available in this build");
+  return EMU_E_STATE;
+}
+
+}  // extern "C"

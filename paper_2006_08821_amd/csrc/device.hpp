@@ -1,0 +1,105 @@
+// Device-side data of one mesh and the control block of the iteration.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace emu {
+
+constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
+constexpr int kMaxK1 = 16;         // scalar low-rank modes (k = 3 * k1 <= 48)
+constexpr int kGramEntries = 6 * 256 + 48;   // 6 coordinate-pair 16x16 blocks + y
+constexpr int kLsTerms = 7;        // 6 polynomial coefficients + g.p
+constexpr int kTriRows = 64;       // rows (forward) / columns (backward) per work item
+constexpr int kMaxFrontW = 2048;   // largest supernode width held in LDS
+
+// Iteration control block (device memory, one per mesh).
+struct Ctl {
+  int32_t done;        // 1: every kernel of the iteration returns immediately
+  int32_t status;      // emu_status
+  int32_t iter;        // accepted iterations
+  int32_t trials;      // Armijo trials
+  int32_t solves;      // factored ACAP solves
+  int32_t max_iters;
+  int32_t eval_only;   // 1: never stop on convergence (single evaluation)
+  int32_t clamped;     // blocks clamped in the last element pass
+  int32_t inverted;    // tets with det F <= 0 in the last element pass
+  int32_t chol_fail;   // Woodbury systems that were not SPD (fallback z = 0)
+  int32_t pad0, pad1;
+  double sigma;        // accepted step of the previous iteration (0: none)
+  double tol2;         // grad_tol^2
+  double gnorm2;       // |dE/dF|^2 of the last element pass
+  double gnorm0_2;     // at the first pass of the solve
+  double energy;
+  double gtp;          // g . p of the last direction
+  double sigma0, armijo_c, rho;
+  double stall_rel;
+};
+
+// Plain pointers to every device array of a mesh (passed by value).
+struct DevMesh {
+  int32_t n, nf, m, k1, npins, ngroups;
+  int32_t nb;          // workgroups of the element passes (fixed: deterministic sums)
+  int32_t nbg;         // workgroups of the Woodbury Gram pass
+  int32_t mixed;       // FP32 element Hessian / Gram / direction
+  double alpha, kf;
+
+  // elements, internal order, structure of arrays
+  const int32_t* vid;     // [4][m] internal vertex ids
+  const double* dminv;    // [9][m] rows of D_m^{-1}
+  const double* vol;
+  const double* mu;
+  const double* lhat;
+  const double* w;        // ACAP weights (beta = alpha w)
+  const double* fib;      // [3][m]
+  const int32_t* grp;     // [m]
+  double* R;              // [9][m]
+  double* S;              // [6][m]
+  void* gbar;             // [9][m]  (double or float)
+  void* Lf;               // [27][m] Cholesky of the 6x6 and 3x3 blocks (packed)
+  double* p;              // [9][m]  step in the rotated (sym, skew) basis
+  double* contrib;        // [m][12] ACAP right-hand-side contributions
+
+  // vertices, internal order (free in factor order, then pinned)
+  double* q;              // [n][3]
+  double* dq;             // [n][3]
+  double* uz;             // [n][3]
+  const double* phi;      // [n][16]
+  const double* nu;       // [16]
+  const double* act;      // [ngroups]
+  const double* pin_rhs;  // [nf][3]
+  const double* pin_xyz;  // [npins][3]  (internal ids nf..n-1)
+  const int32_t* inc_ptr; // [nf+1]
+  const int32_t* inc;     // element*4 + local vertex
+
+  // factor (partitioned-inverse supernodes)
+  const int32_t* sn_col0;
+  const int32_t* sn_w;
+  const int32_t* sn_h;
+  const int32_t* sn_rowoff;
+  const int64_t* sn_valoff;
+  const int32_t* sn_front;   // offset of the supernode's positions in gptr
+  const int32_t* rows;
+  const double* vals;
+  const int32_t* gptr;       // [sum h + 1] children's update rows per front position
+  const int32_t* gsrc;
+  const int2* fwd_items;     // (supernode, first row)
+  const int2* bwd_items;     // (supernode, first column)
+  double* rhs;               // [nf][3]
+  double* ybuf;              // [nf][3]
+  double* xbuf;              // [nf][3]
+  double* upd;               // [rows][3]
+
+  // reductions
+  double* part_e;            // [nb][2]
+  double* part_g;            // [nb][2]
+  int32_t* part_cnt;         // [nb][2]
+  double* part_gram;         // [nbg][kGramEntries]
+  double* gram;              // [kGramEntries]
+  double* zbuf;              // [48]
+  double* part_ls;           // [nb][2*kLsTerms]
+  Ctl* ctl;
+};
+
+}  // namespace emu

@@ -1,0 +1,35 @@
+// Launch helpers of the HIP kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "../../include/emu.h"
+#include "device.hpp"
+
+#define EMU_E_NONFINITE_CODE 5
+#define EMU_E_NOT_CONVERGED_CODE 3
+#define EMU_E_LINESEARCH_CODE 4
+
+namespace emu {
+
+// Level schedule of the triangular sweeps: work items of forward level L are
+// fwd_items[fwd_ptr[L] .. fwd_ptr[L+1]) (leaves first); backward level L
+// (root first) uses bwd_ptr likewise.
+struct SolvePlan {
+  int nlevels = 0;
+  std::vector<int> fwd_ptr, bwd_ptr;
+};
+
+void launch_init_rest(const DevMesh& d, hipStream_t st);
+void launch_set_F(const DevMesh& d, const double* F, const int32_t* eold, hipStream_t st);
+void launch_get_F(const DevMesh& d, double* F, const int32_t* eold, hipStream_t st);
+void launch_get_dir(const DevMesh& d, double* out, const int32_t* eold, hipStream_t st);
+void launch_scatter_F(const DevMesh& d, hipStream_t st);
+void launch_solve(const DevMesh& d, const SolvePlan& pl, int add_pin, double* x, int check_done, hipStream_t st);
+void launch_set_pins(const DevMesh& d, hipStream_t st);
+void launch_iteration(const DevMesh& d, const SolvePlan& pl, hipStream_t st);
+void launch_evaluate(const DevMesh& d, hipStream_t st);
+
+}  // namespace emu

@@ -1,0 +1,218 @@
+"""Python front end of the EMU library: meshes, solves, evaluation.
+
+PyTorch is used only for device memory and the current HIP stream; all
+computation runs in libemu.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+
+from . import _lib
+from ._lib import check, dptr, iptr
+
+PRECISION = {"fp64": 0, "mixed": 1}
+
+
+def _desc_arrays(problem, alpha_hat=None, n_modes=None, precision="fp64", weight_mode=0,
+                 leaf_size=0, mu_ref=0.0, fiber_k=0.0):
+    """Contiguous host arrays + the emu_mesh_desc struct that points at them."""
+    keep = dict(
+        rest=np.ascontiguousarray(problem.rest_xyz, np.float64),
+        tets=np.ascontiguousarray(problem.tets, np.int32),
+        youngs=np.ascontiguousarray(problem.youngs, np.float64),
+        poisson=np.ascontiguousarray(problem.poisson, np.float64),
+        fiber=np.ascontiguousarray(problem.fiber, np.float64),
+        group=np.ascontiguousarray(problem.group, np.int32),
+        pins=np.ascontiguousarray(problem.pins, np.int32),
+        pin_xyz=np.ascontiguousarray(problem.pin_xyz, np.float64),
+    )
+    d = _lib.MeshDesc()
+    d.n_vertices = keep["rest"].shape[0]
+    d.n_tets = keep["tets"].shape[0]
+    d.n_groups = int(len(problem.activation))
+    d.n_pins = keep["pins"].shape[0]
+    d.rest_xyz = dptr(keep["rest"])
+    d.tets = iptr(keep["tets"])
+    d.youngs = dptr(keep["youngs"])
+    d.poisson = dptr(keep["poisson"])
+    d.fiber = dptr(keep["fiber"])
+    d.group = iptr(keep["group"])
+    d.pins = iptr(keep["pins"])
+    d.pin_xyz = dptr(keep["pin_xyz"])
+    d.alpha_hat = float(problem.alpha_hat if alpha_hat is None else alpha_hat)
+    d.mu_ref = float(mu_ref)
+    d.fiber_k = float(fiber_k)
+    d.weight_mode = int(weight_mode)
+    d.n_modes = int(problem.n_modes if n_modes is None else n_modes)
+    d.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    d.leaf_size = int(leaf_size)
+    return d, keep
+
+
+class HostSetup:
+    """Host-only mesh setup (no GPU): factor and modes of the ACAP operator."""
+
+    def __init__(self, problem, **kw):
+        self._lib = _lib.load()
+        desc, self._keep = _desc_arrays(problem, **kw)
+        h = C.c_void_p()
+        check(self._lib.emu_host_setup_create(C.byref(desc), C.byref(h)), "emu_host_setup_create")
+        self._h = h
+        self.n = problem.n_vertices
+        self.m = problem.n_tets
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.emu_host_setup_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def info(self):
+        inf = _lib.MeshInfo()
+        check(self._lib.emu_host_setup_info(self._h, C.byref(inf)))
+        return inf.as_dict()
+
+    def solve(self, b):
+        b = np.ascontiguousarray(b, np.float64)
+        x = np.zeros((self.n, 3))
+        check(self._lib.emu_host_setup_solve(self._h, dptr(b), dptr(x)))
+        return x
+
+    def apply(self, x):
+        x = np.ascontiguousarray(x, np.float64)
+        y = np.zeros((self.n, 3))
+        check(self._lib.emu_host_setup_apply(self._h, dptr(x), dptr(y)))
+        return y
+
+    def modes(self):
+        k1 = self.info()["n_modes"] // 3
+        nu = np.zeros(k1)
+        phi = np.zeros((k1, self.n))
+        check(self._lib.emu_host_setup_modes(self._h, dptr(nu), dptr(phi)))
+        return nu, phi
+
+    def geometry(self):
+        t = np.zeros((self.m, 4), np.int32)
+        vol = np.zeros(self.m)
+        w = np.zeros(self.m)
+        check(self._lib.emu_host_setup_geometry(self._h, iptr(t), dptr(vol), dptr(w)))
+        return t, vol, w
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("EMU device meshes need a HIP GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _stream(torch):
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def default_opts(**kw):
+    o = _lib.load().emu_solve_opts_default()
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Mesh:
+    """A mesh resident on the current HIP device (factor, modes and state)."""
+
+    def __init__(self, problem, **kw):
+        self.torch = _torch()
+        self._lib = _lib.load()
+        desc, keep = _desc_arrays(problem, **kw)
+        h = C.c_void_p()
+        check(self._lib.emu_create_mesh(C.byref(desc), C.byref(h)), "emu_create_mesh")
+        self._h = h
+        self.n = problem.n_vertices
+        self.m = problem.n_tets
+        self.n_groups = problem.n_groups
+        self.set_activation(problem.activation)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.emu_destroy_mesh(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        inf = _lib.MeshInfo()
+        check(self._lib.emu_mesh_get_info(self._h, C.byref(inf)))
+        return inf.as_dict()
+
+    def set_activation(self, a):
+        a = np.ascontiguousarray(np.atleast_1d(a), np.float64)
+        check(self._lib.emu_set_activation(self._h, dptr(a)), "emu_set_activation")
+
+    def set_pin_targets(self, pin_xyz):
+        p = np.ascontiguousarray(pin_xyz, np.float64)
+        check(self._lib.emu_set_pin_targets(self._h, dptr(p)), "emu_set_pin_targets")
+
+    def set_modes(self, nu, phi):
+        nu = np.ascontiguousarray(nu, np.float64)
+        phi = np.ascontiguousarray(phi, np.float64)
+        check(self._lib.emu_set_modes(self._h, int(nu.shape[0]), dptr(nu), dptr(phi)), "emu_set_modes")
+
+    def get_modes(self):
+        k1 = self.info()["n_modes"] // 3
+        nu = np.zeros(k1)
+        phi = np.zeros((k1, self.n))
+        check(self._lib.emu_get_modes(self._h, dptr(nu), dptr(phi)))
+        return nu, phi
+
+    def solve(self, opts=None, raise_on_error=True, **kw):
+        """Run the solver; returns (q [n,3] float64 device tensor, stats dict)."""
+        t = self.torch
+        o = opts if opts is not None else default_opts(**kw)
+        q = t.empty((self.n, 3), dtype=t.float64, device="cuda")
+        st = _lib.SolveStats()
+        code = self._lib.emu_solve(self._h, C.byref(o), C.c_void_p(q.data_ptr()), C.byref(st), _stream(t))
+        stats = st.as_dict()
+        stats["status_name"] = _lib.STATUS_NAMES.get(code, str(code))
+        if raise_on_error and code not in (0, 3):
+            check(code, "emu_solve")
+        return q, stats
+
+    def get_state(self):
+        t = self.torch
+        F = t.empty((self.m, 3, 3), dtype=t.float64, device="cuda")
+        q = t.empty((self.n, 3), dtype=t.float64, device="cuda")
+        check(self._lib.emu_get_state(self._h, C.c_void_p(F.data_ptr()), C.c_void_p(q.data_ptr()), _stream(t)))
+        return F, q
+
+    def set_state(self, F):
+        t = self.torch
+        F = t.as_tensor(F, dtype=t.float64, device="cuda").contiguous()
+        check(self._lib.emu_set_state(self._h, C.c_void_p(F.data_ptr()), _stream(t)), "emu_set_state")
+
+    def evaluate(self, F, direction=True):
+        """q*(F), E(F), |dE/dF| and the quasi-Newton direction at F (state unchanged)."""
+        t = self.torch
+        F = t.as_tensor(F, dtype=t.float64, device="cuda").contiguous()
+        q = t.empty((self.n, 3), dtype=t.float64, device="cuda")
+        dvec = t.empty((self.m, 3, 3), dtype=t.float64, device="cuda") if direction else None
+        e = C.c_double()
+        g = C.c_double()
+        check(self._lib.emu_evaluate(self._h, C.c_void_p(F.data_ptr()), C.c_void_p(q.data_ptr()),
+                                     C.byref(e), C.byref(g),
+                                     C.c_void_p(dvec.data_ptr()) if dvec is not None else None,
+                                     _stream(t)), "emu_evaluate")
+        return dict(q=q, energy=e.value, grad_norm=g.value, direction=dvec)
