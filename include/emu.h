@@ -80,8 +80,9 @@ typedef struct {
                                 0 -> mu_ref                                      */
   int32_t weight_mode;       /* EMU_WEIGHT_STIFFNESS: w_i = vol_i mu_i / mu_ref;
                                 EMU_WEIGHT_VOLUME: w_i = vol_i                   */
-  int32_t n_modes;           /* k = 3 * (scalar modes), 0 <= k <= 48, k % 3 == 0;
-                                -1 -> 48 (eq. low-rank)                          */
+  int32_t n_modes;           /* k = 3 * (scalar modes), 0 <= k <= 48, k % 3 == 0,
+                                k/3 < free vertices; -1 -> min(48, 3 (free - 1))
+                                (eq. low-rank)                                    */
   int32_t precision;         /* EMU_PRECISION_FP64 or EMU_PRECISION_MIXED          */
   int32_t leaf_size;         /* nested-dissection leaf size; 0 -> 64              */
 } emu_mesh_desc;
@@ -175,6 +176,30 @@ emu_status emu_set_state(emu_mesh* mesh, const double* F, void* stream);
    d = Htilde^{-1} dE/dF (device [m][9] in F coordinates, or NULL). */
 emu_status emu_evaluate(emu_mesh* mesh, const double* F, double* q, double* energy,
                         double* grad_norm, double* direction, void* stream);
+
+/* Diagnostics: kernel classes of one quasi-Newton iteration. */
+enum {
+  EMU_K_ELEMENT = 0,      /* accept step, polar split, energy, gradient, blocks */
+  EMU_K_GRAM = 1,         /* Woodbury Gram and y partial sums                   */
+  EMU_K_GRAM_REDUCE = 2,
+  EMU_K_CONTROL_A = 3,    /* convergence test, k x k Cholesky, z                */
+  EMU_K_UZ = 4,           /* mode field Phi^T z                                 */
+  EMU_K_DIRECTION = 5,    /* Woodbury direction                                 */
+  EMU_K_RHS = 6,          /* ACAP right-hand side                               */
+  EMU_K_FWD = 7,          /* forward triangular sweep (all levels)              */
+  EMU_K_BWD = 8,          /* backward triangular sweep (all levels)             */
+  EMU_K_LSCOEF = 9,       /* line-search polynomial                             */
+  EMU_K_CONTROL_B = 10,   /* Armijo test                                        */
+  EMU_K_ADD_Q = 11,       /* q += sigma dq                                      */
+  EMU_NUM_KERNELS = 12
+};
+
+/* Average device time (ms) of each kernel class at the current state, each
+   launched `reps` times back to back with HIP events on the mesh's stream;
+   ms_out host [EMU_NUM_KERNELS].  The mesh state is left unchanged. */
+emu_status emu_profile_kernels(emu_mesh* mesh, int32_t reps, double* ms_out, void* stream);
+/* Name of kernel class k (static string), or NULL. */
+const char* emu_kernel_name(int32_t k);
 
 #ifdef __cplusplus
 }

@@ -121,6 +121,8 @@ def build(problem, alpha_hat=None, n_modes=None, weight_mode=0, modes=True):
              group=group, w=w, beta=beta, alpha=alpha, mu_ref=mu_ref, kf=kf,
              pins=pins, pin_xyz=np.asarray(problem.pin_xyz, np.float64),
              free=free, fpos=fpos, L=L, Lff=Lff, Lfp=Lfp, lu=lu)
+    if n_modes < 0:                       # default: 48 modes, capped by the mesh
+        n_modes = min(48, 3 * (free.size - 1))
     if modes and n_modes > 0:
         compute_modes(M, n_modes // 3)
     return M

@@ -74,6 +74,8 @@ SIGNATURES = {
     "emu_get_state": (C.c_int, [P, P, P, P]),
     "emu_set_state": (C.c_int, [P, P, P]),
     "emu_evaluate": (C.c_int, [P, P, P, DP, DP, P, P]),
+    "emu_profile_kernels": (C.c_int, [P, C.c_int32, DP, P]),
+    "emu_kernel_name": (C.c_char_p, [C.c_int32]),
     "emu_host_setup_create": (C.c_int, [C.POINTER(MeshDesc), C.POINTER(P)]),
     "emu_host_setup_destroy": (C.c_int, [P]),
     "emu_host_setup_info": (C.c_int, [P, C.POINTER(MeshInfo)]),

@@ -651,6 +651,51 @@ emu_status emu_evaluate(emu_mesh* M, const double* F, double* q, double* energy,
   }
 }
 
+const char* emu_kernel_name(int32_t k) {
+  static const char* names[EMU_NUM_KERNELS] = {"element", "gram", "gram_reduce", "control_a", "uz", "direction",
+                                               "rhs", "fwd_sweep", "bwd_sweep", "lscoef", "control_b", "add_q"};
+  return (k >= 0 && k < EMU_NUM_KERNELS) ? names[k] : nullptr;
+}
+
+emu_status emu_profile_kernels(emu_mesh* M, int32_t reps, double* ms_out, void* stream) {
+  if (!M || !ms_out || reps <= 0) {
+    emu::set_error("invalid argument");
+    return EMU_E_INVALID;
+  }
+  try {
+    join_user_stream(M, stream);
+    backup_state(M);
+    emu_solve_opts o = emu_solve_opts_default();
+    o.max_iters = 1 << 30;
+    std::vector<hipEvent_t> ev(2 * reps);
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    for (int k = 0; k < EMU_NUM_KERNELS; ++k) {
+      for (int r = 0; r < reps; ++r) {
+        init_ctl(M, o, 1);
+        HIPCHK(hipEventRecord(ev[2 * r], M->st));
+        emu::launch_class(k, M->d, M->plan, M->st);
+        HIPCHK(hipEventRecord(ev[2 * r + 1], M->st));
+      }
+      HIPCHK(hipStreamSynchronize(M->st));
+      double tot = 0;
+      for (int r = 0; r < reps; ++r) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]));
+        tot += ms;
+      }
+      ms_out[k] = tot / reps;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    restore_state(M);
+    HIPCHK(hipStreamSynchronize(M->st));
+    HIPCHK(hipGetLastError());
+    release_user_stream(M, stream);
+    return EMU_OK;
+  } catch (const emu::Error& e) {
+    return fail_with(e);
+  }
+}
+
 emu_status emu_solve_grad(emu_mesh* M, const double* dL_dq, double* dL_da, emu_solve_stats* stats,
                           void* stream) {
   (void)dL_dq;

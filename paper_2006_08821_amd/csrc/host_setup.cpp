@@ -202,6 +202,7 @@ static void geometry(const emu_mesh_desc& d, HostMesh& hm) {
   hm.precision = d.precision;
   hm.leaf_size = d.leaf_size > 0 ? d.leaf_size : 64;
   hm.k1 = (d.n_modes < 0 ? 48 : d.n_modes) / 3;
+  hm.k1_default = d.n_modes < 0;
 }
 
 // hat gradients b_v (rows of D_m^{-1}, b_3 = -(b_0 + b_1 + b_2))
@@ -481,6 +482,37 @@ static void order_and_factor(HostMesh& hm) {
     }
   const int32_t nf = (int32_t)fl.size();
   if (nf == 0) fail(EMU_E_INVALID, "every vertex is pinned");
+  // every connected part of the mesh needs a pinned vertex, or L_ff is singular
+  {
+    std::vector<int32_t> comp(n, -1), stack;
+    int32_t nc = 0;
+    for (int32_t s0 = 0; s0 < n; ++s0) {
+      if (comp[s0] >= 0 || hm.lap_ptr[s0] == hm.lap_ptr[s0 + 1]) continue;
+      bool has_pin = false;
+      comp[s0] = nc;
+      stack.assign(1, s0);
+      while (!stack.empty()) {
+        int32_t u = stack.back();
+        stack.pop_back();
+        has_pin = has_pin || pinned[u];
+        for (int32_t k = hm.lap_ptr[u]; k < hm.lap_ptr[u + 1]; ++k) {
+          int32_t v = hm.lap_idx[k];
+          if (comp[v] < 0) {
+            comp[v] = nc;
+            stack.push_back(v);
+          }
+        }
+      }
+      if (!has_pin)
+        fail(EMU_E_SINGULAR, "a connected part of the mesh has no pinned vertex (vertex " +
+                                 std::to_string(s0) + ")");
+      ++nc;
+    }
+    for (int32_t v = 0; v < n; ++v)
+      if (comp[v] < 0 && !pinned[v])
+        fail(EMU_E_SINGULAR, "vertex " + std::to_string(v) + " belongs to no tet and is not pinned");
+  }
+  if (hm.k1_default) hm.k1 = std::min(hm.k1, std::max(0, nf - 1));
   if (hm.k1 > 0 && hm.k1 >= nf) fail(EMU_E_INVALID, "n_modes/3 must be < number of free vertices");
   hm.nf = nf;
   std::vector<int32_t> adj_ptr(nf + 1, 0), adj;
@@ -823,21 +855,110 @@ void jacobi_eigh(int n, double* A, double* ev, double* V) {
   std::copy(V2.begin(), V2.end(), V);
 }
 
-// orthonormalize the p columns of X (nf x p, row-major) by Gram-Schmidt, twice
-static void orthonormalize(int64_t nf, int p, double* X) {
-  for (int pass = 0; pass < 2; ++pass)
-    for (int j = 0; j < p; ++j) {
-      for (int k = 0; k < j; ++k) {
-        double d = 0;
-        for (int64_t i = 0; i < nf; ++i) d += X[i * p + j] * X[i * p + k];
-        for (int64_t i = 0; i < nf; ++i) X[i * p + j] -= d * X[i * p + k];
+// Deterministic dense helpers over tall row-major blocks (nf rows): partial
+// sums over fixed 4096-row chunks, added in chunk order.
+static constexpr int64_t kChunk = 4096;
+
+// G = A^T B  (A: nf x pa, B: nf x pb, row-major; G: pa x pb)
+static void gram_tn(int64_t nf, int pa, const double* A, int lda, int pb, const double* B, int ldb,
+                    std::vector<double>& G) {
+  const int64_t nch = (nf + kChunk - 1) / kChunk;
+  std::vector<double> part((size_t)nch * pa * pb, 0.0);
+  parallel_for(nch, [&](int64_t ch) {
+    double* P = part.data() + (size_t)ch * pa * pb;
+    const int64_t r0 = ch * kChunk, r1 = std::min(nf, r0 + kChunk);
+    for (int64_t i = r0; i < r1; ++i) {
+      const double* a = A + i * lda;
+      const double* b = B + i * ldb;
+      for (int x = 0; x < pa; ++x) {
+        const double av = a[x];
+        double* Px = P + (size_t)x * pb;
+        for (int y = 0; y < pb; ++y) Px[y] += av * b[y];
       }
-      double nn = 0;
-      for (int64_t i = 0; i < nf; ++i) nn += X[i * p + j] * X[i * p + j];
-      nn = std::sqrt(nn);
-      if (nn == 0) nn = 1;
-      for (int64_t i = 0; i < nf; ++i) X[i * p + j] /= nn;
     }
+  });
+  G.assign((size_t)pa * pb, 0.0);
+  for (int64_t ch = 0; ch < nch; ++ch)
+    for (size_t k = 0; k < G.size(); ++k) G[k] += part[(size_t)ch * pa * pb + k];
+}
+
+// C = A W  (A: nf x pa, W: pa x pc) -> C row-major nf x pc
+static void mul_nn(int64_t nf, int pa, const double* A, int lda, int pc, const double* W, double* C, int ldc) {
+  parallel_for(nf, [&](int64_t i) {
+    const double* a = A + i * lda;
+    double* c = C + i * ldc;
+    for (int y = 0; y < pc; ++y) c[y] = 0;
+    for (int x = 0; x < pa; ++x) {
+      const double av = a[x];
+      const double* w = W + (size_t)x * pc;
+      for (int y = 0; y < pc; ++y) c[y] += av * w[y];
+    }
+  }, 2048);
+}
+
+// Orthonormalize the columns [c0, c1) of Q (nf x ld) against columns [0, c0)
+// (two passes of block Gram-Schmidt) and among themselves (Cholesky QR, twice).
+// Returns the number of columns kept (rank-deficient columns are dropped).
+static int orth_block(int64_t nf, double* Q, int ld, int c0, int c1) {
+  int nb = c1 - c0;
+  std::vector<double> G;
+  std::vector<double> Wt;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (c0 > 0) {
+      gram_tn(nf, c0, Q, ld, nb, Q + c0, ld, G);  // c0 x nb
+      parallel_for(nf, [&](int64_t i) {
+        double* q = Q + i * ld;
+        for (int x = 0; x < c0; ++x) {
+          const double qx = q[x];
+          for (int y = 0; y < nb; ++y) q[c0 + y] -= qx * G[(size_t)x * nb + y];
+        }
+      }, 2048);
+    }
+    // Cholesky QR of the new block with column dropping
+    gram_tn(nf, nb, Q + c0, ld, nb, Q + c0, ld, G);
+    std::vector<double> L((size_t)nb * nb, 0.0);
+    std::vector<int> keep;
+    double maxd = 0;
+    for (int j = 0; j < nb; ++j) maxd = std::max(maxd, G[(size_t)j * nb + j]);
+    std::vector<double> Linv((size_t)nb * nb, 0.0);
+    // pivot-free Cholesky; columns whose remaining norm is tiny are dropped
+    std::vector<double> A = G;
+    std::vector<char> ok(nb, 0);
+    for (int j = 0; j < nb; ++j) {
+      double d = A[(size_t)j * nb + j];
+      for (int k = 0; k < j; ++k)
+        if (ok[k]) d -= L[(size_t)j * nb + k] * L[(size_t)j * nb + k];
+      if (d > 1e-20 * maxd && d > 0) {
+        ok[j] = 1;
+        L[(size_t)j * nb + j] = std::sqrt(d);
+        for (int i = j + 1; i < nb; ++i) {
+          double t = A[(size_t)i * nb + j];
+          for (int k = 0; k < j; ++k)
+            if (ok[k]) t -= L[(size_t)i * nb + k] * L[(size_t)j * nb + k];
+          L[(size_t)i * nb + j] = t / L[(size_t)j * nb + j];
+        }
+      }
+    }
+    for (int j = 0; j < nb; ++j)
+      if (ok[j]) keep.push_back(j);
+    const int nk = (int)keep.size();
+    // Q_new = Q_block L^{-T} restricted to kept columns: solve per row
+    parallel_for(nf, [&](int64_t i) {
+      double* q = Q + i * ld + c0;
+      double tmp[512];
+      for (int a = 0; a < nk; ++a) {
+        const int j = keep[a];
+        double t = q[j];
+        for (int b = 0; b < a; ++b) t -= tmp[b] * L[(size_t)j * nb + keep[b]];
+        tmp[a] = t / L[(size_t)j * nb + j];
+      }
+      for (int a = 0; a < nk; ++a) q[a] = tmp[a];
+      for (int a = nk; a < nb; ++a) q[a] = 0;
+    }, 2048);
+    nb = nk;
+    if (nb == 0) break;
+  }
+  return c0 + nb;
 }
 
 void host_modes(HostMesh& hm, int k1) {
@@ -845,48 +966,65 @@ void host_modes(HostMesh& hm, int k1) {
   hm.nu.clear();
   hm.phi.clear();
   if (k1 <= 0) return;
-  const int p = (int)std::min<int64_t>(nf, std::max(2 * k1 + 8, k1 + 4));
-  std::vector<double> X((size_t)nf * p), Y((size_t)nf * p), LY((size_t)nf * p);
+  // block Krylov space of L_ff^{-1} (shift-invert about 0), Rayleigh-Ritz with
+  // L_ff, thick restart from the lowest Ritz vectors
+  const int b = (int)std::min<int64_t>(nf, k1 + 8);
+  const int steps = 6;
+  const int cap = (int)std::min<int64_t>(nf, (int64_t)b * (steps + 1));
+  std::vector<double> Q((size_t)nf * cap, 0.0), LQ((size_t)nf * cap), X((size_t)nf * b);
   std::mt19937_64 rng(20200615ULL);
   std::normal_distribution<double> nd(0.0, 1.0);
   for (auto& v : X) v = nd(rng);
-  orthonormalize(nf, p, X.data());
-  std::vector<double> T((size_t)p * p), ev(p), W((size_t)p * p);
-  for (int it = 0; it < 500; ++it) {
-    host_factor_solve(hm.fac, p, X.data(), Y.data());
-    orthonormalize(nf, p, Y.data());
-    host_lff_apply(hm, p, Y.data(), LY.data());
-    for (int a = 0; a < p; ++a)
-      for (int b = 0; b < p; ++b) {
-        double t = 0;
-        for (int64_t i = 0; i < nf; ++i) t += Y[i * p + a] * LY[i * p + b];
-        T[(size_t)a * p + b] = t;
-      }
-    for (int a = 0; a < p; ++a)
-      for (int b = 0; b < a; ++b) T[(size_t)a * p + b] = T[(size_t)b * p + a] = 0.5 * (T[(size_t)a * p + b] + T[(size_t)b * p + a]);
-    jacobi_eigh(p, T.data(), ev.data(), W.data());
-    // X = Y W, residual of the first k1 Ritz pairs
-    parallel_for(nf, [&](int64_t i) {
-      for (int j = 0; j < p; ++j) {
-        double t = 0;
-        for (int a = 0; a < p; ++a) t += Y[i * p + a] * W[(size_t)a * p + j];
-        X[i * p + j] = t;
-      }
-    }, 4096);
-    double worst = 0;
+  std::vector<double> T, ev, W, blk, sol;
+  for (int cycle = 0; cycle < 40; ++cycle) {
+    for (int64_t i = 0; i < nf; ++i)
+      for (int j = 0; j < b; ++j) Q[(size_t)i * cap + j] = X[(size_t)i * b + j];
+    int nc = orth_block(nf, Q.data(), cap, 0, b);
+    int last0 = 0, last1 = nc;
+    for (int st = 0; st < steps && nc < cap; ++st) {
+      const int nb = std::min(last1 - last0, cap - nc);
+      if (nb <= 0) break;
+      blk.assign((size_t)nf * nb, 0.0);
+      sol.assign((size_t)nf * nb, 0.0);
+      for (int64_t i = 0; i < nf; ++i)
+        for (int j = 0; j < nb; ++j) blk[(size_t)i * nb + j] = Q[(size_t)i * cap + last0 + j];
+      host_factor_solve(hm.fac, nb, blk.data(), sol.data());
+      for (int64_t i = 0; i < nf; ++i)
+        for (int j = 0; j < nb; ++j) Q[(size_t)i * cap + nc + j] = sol[(size_t)i * nb + j];
+      int n2 = orth_block(nf, Q.data(), cap, nc, nc + nb);
+      last0 = nc;
+      last1 = n2;
+      nc = n2;
+    }
+    // Rayleigh-Ritz: T = Q^T L Q (nc x nc)
     {
-      std::vector<double> LX((size_t)nf * p);
-      host_lff_apply(hm, p, X.data(), LX.data());
+      std::vector<double> Qc((size_t)nf * nc), LQc((size_t)nf * nc);
+      for (int64_t i = 0; i < nf; ++i)
+        for (int j = 0; j < nc; ++j) Qc[(size_t)i * nc + j] = Q[(size_t)i * cap + j];
+      host_lff_apply(hm, nc, Qc.data(), LQc.data());
+      gram_tn(nf, nc, Qc.data(), nc, nc, LQc.data(), nc, T);
+      for (int a = 0; a < nc; ++a)
+        for (int c = 0; c < a; ++c) T[(size_t)a * nc + c] = T[(size_t)c * nc + a] = 0.5 * (T[(size_t)a * nc + c] + T[(size_t)c * nc + a]);
+      ev.assign(nc, 0.0);
+      W.assign((size_t)nc * nc, 0.0);
+      jacobi_eigh(nc, T.data(), ev.data(), W.data());
+      std::vector<double> Wb((size_t)nc * b);
+      for (int a = 0; a < nc; ++a)
+        for (int j = 0; j < b; ++j) Wb[(size_t)a * b + j] = W[(size_t)a * nc + j];
+      mul_nn(nf, nc, Qc.data(), nc, b, Wb.data(), X.data(), b);
+      std::vector<double> LX((size_t)nf * b);
+      mul_nn(nf, nc, LQc.data(), nc, b, Wb.data(), LX.data(), b);
+      double worst = 0;
       for (int j = 0; j < k1; ++j) {
         double r = 0;
         for (int64_t i = 0; i < nf; ++i) {
-          double d = LX[i * p + j] - ev[j] * X[i * p + j];
+          double d = LX[(size_t)i * b + j] - ev[j] * X[(size_t)i * b + j];
           r += d * d;
         }
         worst = std::max(worst, std::sqrt(r) / std::fabs(ev[j]));
       }
+      if (worst < 1e-8) break;
     }
-    if (worst < 1e-9) break;
   }
   hm.nu.assign(ev.begin(), ev.begin() + k1);
   hm.phi.assign((size_t)k1 * nf, 0.0);
@@ -894,9 +1032,12 @@ void host_modes(HostMesh& hm, int k1) {
     // sign convention: largest-magnitude entry positive
     int64_t im = 0;
     for (int64_t i = 0; i < nf; ++i)
-      if (std::fabs(X[i * p + j]) > std::fabs(X[im * p + j])) im = i;
-    double sg = X[im * p + j] < 0 ? -1.0 : 1.0;
-    for (int64_t i = 0; i < nf; ++i) hm.phi[(size_t)j * nf + i] = sg * X[i * p + j];
+      if (std::fabs(X[(size_t)i * b + j]) > std::fabs(X[(size_t)im * b + j])) im = i;
+    double sg = X[(size_t)im * b + j] < 0 ? -1.0 : 1.0;
+    double nn = 0;
+    for (int64_t i = 0; i < nf; ++i) nn += X[(size_t)i * b + j] * X[(size_t)i * b + j];
+    nn = std::sqrt(nn);
+    for (int64_t i = 0; i < nf; ++i) hm.phi[(size_t)j * nf + i] = sg * X[(size_t)i * b + j] / nn;
   }
   // captured fraction of trace(L_ff^{-1}) (Hutchinson estimate, 8 probes)
   {
@@ -908,9 +1049,9 @@ void host_modes(HostMesh& hm, int k1) {
     double tr = 0;
     for (size_t i = 0; i < Z.size(); ++i) tr += Z[i] * ZI[i];
     tr /= np;
-    double cap = 0;
-    for (int j = 0; j < k1; ++j) cap += 1.0 / hm.nu[j];
-    hm.mode_captured = tr > 0 ? cap / tr : 0;
+    double capd = 0;
+    for (int j = 0; j < k1; ++j) capd += 1.0 / hm.nu[j];
+    hm.mode_captured = tr > 0 ? capd / tr : 0;
   }
 }
 

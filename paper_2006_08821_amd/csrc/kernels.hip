@@ -1325,6 +1325,43 @@ void launch_iteration(const DevMesh& d, const SolvePlan& pl, hipStream_t st) {
   hipLaunchKernelGGL(k_add_q, dim3(blocks(3 * (int64_t)d.nf)), dim3(kBlock), 0, st, d);
 }
 
+void launch_class(int k, const DevMesh& d, const SolvePlan& pl, hipStream_t st) {
+  switch (k) {
+    case 0:
+      if (d.mixed) hipLaunchKernelGGL(k_element<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
+      else hipLaunchKernelGGL(k_element<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
+      break;
+    case 1:
+      if (d.mixed) hipLaunchKernelGGL(k_gram<float>, dim3(d.nbg), dim3(kBlock), 0, st, d);
+      else hipLaunchKernelGGL(k_gram<double>, dim3(d.nbg), dim3(kBlock), 0, st, d);
+      break;
+    case 2: hipLaunchKernelGGL(k_gram_reduce, dim3(blocks(kGramEntries)), dim3(kBlock), 0, st, d); break;
+    case 3: hipLaunchKernelGGL(k_control_a, dim3(1), dim3(kBlock), 0, st, d); break;
+    case 4: hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d); break;
+    case 5:
+      if (d.mixed) hipLaunchKernelGGL(k_direction<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
+      else hipLaunchKernelGGL(k_direction<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
+      break;
+    case 6: hipLaunchKernelGGL(k_rhs, dim3(blocks(d.nf)), dim3(kBlock), 0, st, d, 0, 1); break;
+    case 7:
+      for (int L = 0; L < pl.nlevels; ++L) {
+        int n0 = pl.fwd_ptr[L], n1 = pl.fwd_ptr[L + 1];
+        if (n1 > n0) hipLaunchKernelGGL(k_fwd, dim3(n1 - n0), dim3(kBlock), 0, st, d, n0, 1);
+      }
+      break;
+    case 8:
+      for (int L = 0; L < pl.nlevels; ++L) {
+        int n0 = pl.bwd_ptr[L], n1 = pl.bwd_ptr[L + 1];
+        if (n1 > n0) hipLaunchKernelGGL(k_bwd, dim3(n1 - n0), dim3(kBlock), 0, st, d, n0, d.dq, 1);
+      }
+      break;
+    case 9: hipLaunchKernelGGL(k_lscoef, dim3(d.nb), dim3(kBlock), 0, st, d); break;
+    case 10: hipLaunchKernelGGL(k_control_b, dim3(1), dim3(kBlock), 0, st, d); break;
+    case 11: hipLaunchKernelGGL(k_add_q, dim3(blocks(3 * (int64_t)d.nf)), dim3(kBlock), 0, st, d); break;
+    default: break;
+  }
+}
+
 // evaluation at the current state: element pass, Woodbury system, direction
 void launch_evaluate(const DevMesh& d, hipStream_t st) {
   if (d.mixed) {

@@ -31,5 +31,6 @@ void launch_solve(const DevMesh& d, const SolvePlan& pl, int add_pin, double* x,
 void launch_set_pins(const DevMesh& d, hipStream_t st);
 void launch_iteration(const DevMesh& d, const SolvePlan& pl, hipStream_t st);
 void launch_evaluate(const DevMesh& d, hipStream_t st);
+void launch_class(int k, const DevMesh& d, const SolvePlan& pl, hipStream_t st);
 
 }  // namespace emu

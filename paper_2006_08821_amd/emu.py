@@ -203,6 +203,13 @@ class Mesh:
         F = t.as_tensor(F, dtype=t.float64, device="cuda").contiguous()
         check(self._lib.emu_set_state(self._h, C.c_void_p(F.data_ptr()), _stream(t)), "emu_set_state")
 
+    def profile_kernels(self, reps=20):
+        """Average device ms per kernel class (HIP events), {name: ms}."""
+        t = self.torch
+        out = np.zeros(12)
+        check(self._lib.emu_profile_kernels(self._h, int(reps), dptr(out), _stream(t)), "emu_profile_kernels")
+        return {self._lib.emu_kernel_name(k).decode(): float(out[k]) for k in range(12)}
+
     def evaluate(self, F, direction=True):
         """q*(F), E(F), |dE/dF| and the quasi-Newton direction at F (state unchanged)."""
         t = self.torch

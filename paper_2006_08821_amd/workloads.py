@@ -50,7 +50,7 @@ class Problem:
     activation: np.ndarray        # [n_groups] float64
     dims: tuple = ()
     alpha_hat: float = 10.0
-    n_modes: int = 48
+    n_modes: int = -1               # -1: library default (48, capped by the mesh)
     extra: dict = dataclasses.field(default_factory=dict)
 
     @property
