@@ -98,6 +98,7 @@ typedef struct {
   int32_t iters_per_sync;    /* iterations per host check of the stop flag       */
   double stall_rel;          /* mixed precision only: also stop if no Armijo step
                                 exists and |g| <= stall_rel * |g_0|; 0 disables  */
+  double grad_rtol;          /* also stop when |dE/dF|_2 <= grad_rtol |g_0|; 0 = off */
 } emu_solve_opts;
 
 typedef struct {

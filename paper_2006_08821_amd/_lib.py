@@ -34,7 +34,7 @@ class MeshDesc(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("grad_tol", C.c_double), ("max_iters", C.c_int32), ("sigma0", C.c_double),
                 ("armijo_c", C.c_double), ("rho", C.c_double), ("warm_start", C.c_int32),
-                ("iters_per_sync", C.c_int32), ("stall_rel", C.c_double)]
+                ("iters_per_sync", C.c_int32), ("stall_rel", C.c_double), ("grad_rtol", C.c_double)]
 
 
 class SolveStats(C.Structure):

@@ -65,6 +65,9 @@ struct emu_mesh {
   bool converged = false;
   // backup of the state for emu_evaluate
   double *R_bak = nullptr, *S_bak = nullptr, *q_bak = nullptr;
+  // adjoint work arrays (allocated on first use)
+  double *a_lam = nullptr, *a_r = nullptr, *a_z = nullptr, *a_p = nullptr, *a_hp = nullptr;
+  double *a_ypart = nullptr, *a_part = nullptr, *a_vin = nullptr, *a_vx = nullptr, *a_el = nullptr;
 
   template <typename T>
   T* dalloc(size_t count) {
@@ -143,7 +146,7 @@ void build_device(emu_mesh* M) {
   d.npins = hm.npins;
   d.ngroups = hm.ngroups;
   d.nb = std::max(1, std::min((m + emu::kBlock - 1) / emu::kBlock, 1024));
-  d.nbg = std::max(1, std::min((m + 63) / 64, 256));
+  d.nbg = std::max(1, std::min((m + 63) / 64, 1024));
   d.mixed = hm.precision == EMU_PRECISION_MIXED;
   d.alpha = hm.alpha;
   d.kf = hm.kf;
@@ -257,6 +260,23 @@ void build_device(emu_mesh* M) {
     d.sn_front = M->upload(front);
     d.rows = M->upload(fac.rows);
     d.vals = M->upload(fac.vals);
+    {
+      // transposed blocks for the backward sweep: row c holds column c of
+      // [Linv; M] from row c down (entries r = c .. h-1)
+      std::vector<double> tv(fac.vals.size());
+      for (int s = 0; s < fac.ns; ++s) {
+        const int64_t w = fac.w[s], h = fac.h[s];
+        const double* A = fac.vals.data() + fac.valoff[s];
+        double* T = tv.data() + fac.valoff[s];
+        const int64_t tri = w * (w + 1) / 2;
+        for (int64_t c = 0; c < w; ++c) {
+          double* row = T + c * h - c * (c - 1) / 2;
+          for (int64_t r = c; r < h; ++r)
+            row[r - c] = r < w ? A[r * (r + 1) / 2 + c] : A[tri + (r - w) * w + c];
+        }
+      }
+      d.tvals = M->upload(tv);
+    }
     d.gptr = M->upload(gptr);
     d.gsrc = M->upload(gsrc);
     d.fwd_items = M->upload(fwd);
@@ -276,6 +296,8 @@ void build_device(emu_mesh* M) {
     d.zbuf = M->upload(z);
   }
   d.part_ls = M->dalloc<double>(2 * (size_t)emu::kLsTerms * d.nb);
+  d.cfac = M->dalloc<double>(48 * 48);
+  d.cfac_ok = M->dalloc<int32_t>(1);
   d.ctl = M->dalloc<emu::Ctl>(1);
   M->d_eold = M->upload(hm.eold);
   M->d_vold = M->upload(hm.vold);
@@ -295,6 +317,7 @@ void init_ctl(emu_mesh* M, const emu_solve_opts& o, int eval_only) {
   c.max_iters = o.max_iters;
   c.eval_only = eval_only;
   c.tol2 = o.grad_tol * o.grad_tol;
+  c.rtol2 = o.grad_rtol * o.grad_rtol;
   c.gnorm0_2 = -1.0;
   c.sigma0 = o.sigma0;
   c.armijo_c = o.armijo_c;
@@ -380,6 +403,7 @@ emu_solve_opts emu_solve_opts_default(void) {
   o.warm_start = 1;
   o.iters_per_sync = 16;
   o.stall_rel = 1e-6;
+  o.grad_rtol = 0.0;
   return o;
 }
 
@@ -696,18 +720,130 @@ emu_status emu_profile_kernels(emu_mesh* M, int32_t reps, double* ms_out, void* 
   }
 }
 
+// Sum of the nb double-double block partials (fixed order) on the host.
+static double host_dd_sum(emu_mesh* M, const double* dpart, int nb) {
+  std::vector<double> h(2 * (size_t)nb);
+  HIPCHK(hipMemcpyAsync(h.data(), dpart, h.size() * 8, hipMemcpyDeviceToHost, M->st));
+  HIPCHK(hipStreamSynchronize(M->st));
+  double hi = 0, lo = 0;
+  for (int b = 0; b < nb; ++b) {
+    // two-sum of (hi, lo) + (h[2b], h[2b+1])
+    double s = hi + h[2 * b];
+    double bb = s - hi;
+    double e = (hi - (s - bb)) + (h[2 * b] - bb);
+    e += lo + h[2 * b + 1];
+    hi = s + e;
+    lo = e - (hi - s);
+  }
+  return hi + lo;
+}
+
 emu_status emu_solve_grad(emu_mesh* M, const double* dL_dq, double* dL_da, emu_solve_stats* stats,
                           void* stream) {
-  (void)dL_dq;
-  (void)dL_da;
-  (void)stats;
-  (void)stream;
-  if (!M) {
+  if (!M || !dL_dq || (!dL_da && M->hm.ngroups > 0)) {
     emu::set_error("NULL argument");
     return EMU_E_INVALID;
   }
-  emu::set_error("emu_solve_grad: not available in this build");
-  return EMU_E_STATE;
+  if (!M->converged) {
+    emu::set_error("emu_solve_grad needs a converged emu_solve at the current activations");
+    return EMU_E_STATE;
+  }
+  try {
+    auto& d = M->d;
+    const size_t m = M->hm.m, n = M->hm.n, nf = M->hm.nf;
+    if (!M->a_lam) {
+      M->a_lam = M->dalloc<double>(9 * m);
+      M->a_r = M->dalloc<double>(9 * m);
+      M->a_z = M->dalloc<double>(9 * m);
+      M->a_p = M->dalloc<double>(9 * m);
+      M->a_hp = M->dalloc<double>(9 * m);
+      M->a_ypart = M->dalloc<double>(48 * (size_t)d.nb);
+      M->a_part = M->dalloc<double>(2 * (size_t)d.nb);
+      std::vector<double> z3(3 * n, 0.0);
+      M->a_vin = M->upload(z3);
+      M->a_vx = M->upload(z3);
+      M->a_el = M->dalloc<double>(m);
+    }
+    join_user_stream(M, stream);
+    HIPCHK(hipEventRecord(M->ev_t0, M->st));
+    // element blocks and the Woodbury factor at the converged state
+    emu_solve_opts o = emu_solve_opts_default();
+    init_ctl(M, o, 1);
+    emu::launch_evaluate(d, M->st);
+    // right-hand side b = W G L^{-1} (dL/dq)_f  (one ACAP solve)
+    hipLaunchKernelGGL(k_from_user_q, dim3((n + 255) / 256), dim3(256), 0, M->st, dL_dq, M->d_vold, (int)n,
+                       M->a_vin);
+    HIPCHK(hipMemcpyAsync(d.rhs, M->a_vin, 3 * nf * 8, hipMemcpyDeviceToDevice, M->st));
+    emu::launch_sweeps(d, M->plan, M->a_vx, M->st);
+    emu::launch_weighted_grad(d, M->a_vx, M->a_r, M->st);
+    HIPCHK(hipMemsetAsync(M->a_lam, 0, 9 * m * 8, M->st));
+    HIPCHK(hipMemsetAsync(M->a_hp, 0, 9 * m * 8, M->st));
+    // preconditioned conjugate gradients on d2E/dF2 lam = b
+    emu::launch_precond(d, M->a_r, M->a_z, M->a_ypart, M->a_part, M->st);
+    double rz = host_dd_sum(M, M->a_part, d.nb);
+    HIPCHK(hipMemcpyAsync(M->a_p, M->a_z, 9 * m * 8, hipMemcpyDeviceToDevice, M->st));
+    // |b| for the relative stopping test
+    emu::launch_cg_update(d, 0.0, M->a_p, M->a_hp, M->a_lam, M->a_r, M->a_part, M->st);
+    const double bnorm = std::sqrt(std::max(0.0, host_dd_sum(M, M->a_part, d.nb)));
+    const double tol = 1e-10 * bnorm;
+    int it = 0;
+    double rnorm = bnorm;
+    const int max_it = 20000;
+    int status = EMU_OK;
+    while (rnorm > tol && it < max_it) {
+      emu::launch_field_solve(d, M->plan, M->a_p, M->a_vx, M->st);
+      emu::launch_hvp(d, M->a_p, M->a_vx, M->a_hp, M->a_part, M->st);
+      const double php = host_dd_sum(M, M->a_part, d.nb);
+      if (!(php > 0) || !std::isfinite(php)) {
+        status = EMU_E_NONFINITE;
+        break;
+      }
+      const double alpha = rz / php;
+      emu::launch_cg_update(d, alpha, M->a_p, M->a_hp, M->a_lam, M->a_r, M->a_part, M->st);
+      rnorm = std::sqrt(std::max(0.0, host_dd_sum(M, M->a_part, d.nb)));
+      ++it;
+      if (rnorm <= tol) break;
+      emu::launch_precond(d, M->a_r, M->a_z, M->a_ypart, M->a_part, M->st);
+      const double rz2 = host_dd_sum(M, M->a_part, d.nb);
+      const double beta = rz2 / rz;
+      rz = rz2;
+      emu::launch_cg_dir(d, beta, M->a_z, M->a_p, M->st);
+    }
+    if (status == EMU_OK && rnorm > tol) status = EMU_E_NOT_CONVERGED;
+    // dL/da_g = -2 kf sum_{i in g} vol (lam_i u).(F_i u)
+    emu::launch_adj_da(d, M->a_lam, M->a_el, M->st);
+    std::vector<double> per(m);
+    HIPCHK(hipMemcpyAsync(per.data(), M->a_el, m * 8, hipMemcpyDeviceToHost, M->st));
+    HIPCHK(hipEventRecord(M->ev_t1, M->st));
+    HIPCHK(hipEventSynchronize(M->ev_t1));
+    HIPCHK(hipGetLastError());
+    std::vector<double> hi(M->hm.ngroups, 0.0), lo(M->hm.ngroups, 0.0);
+    for (size_t e = 0; e < m; ++e) {
+      const int g = M->hm.group[M->hm.eold[e]];
+      if (g < 0) continue;
+      double s2 = hi[g] + per[e], bb = s2 - hi[g];
+      double er = (hi[g] - (s2 - bb)) + (per[e] - bb);
+      lo[g] += er;
+      hi[g] = s2;
+    }
+    for (int g = 0; g < M->hm.ngroups; ++g) dL_da[g] = -2.0 * M->hm.kf * (hi[g] + lo[g]);
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, M->ev_t0, M->ev_t1));
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->status = status;
+      stats->iters = it;
+      stats->acap_solves = it + 1;
+      stats->grad_norm = rnorm;
+      stats->grad_norm0 = bnorm;
+      stats->ms_total = ms;
+    }
+    release_user_stream(M, stream);
+    if (status != EMU_OK) emu::set_error("adjoint conjugate gradients did not converge");
+    return (emu_status)status;
+  } catch (const emu::Error& e) {
+    return fail_with(e);
+  }
 }
 
 }  // extern "C"

@@ -11,7 +11,7 @@ constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kMaxK1 = 16;         // scalar low-rank modes (k = 3 * k1 <= 48)
 constexpr int kGramEntries = 6 * 256 + 48;   // 6 coordinate-pair 16x16 blocks + y
 constexpr int kLsTerms = 7;        // 6 polynomial coefficients + g.p
-constexpr int kTriRows = 64;       // rows (forward) / columns (backward) per work item
+constexpr int kTriRows = 32;       // rows (forward) / columns (backward) per work item
 constexpr int kMaxFrontW = 2048;   // largest supernode width held in LDS
 
 // Iteration control block (device memory, one per mesh).
@@ -35,6 +35,7 @@ struct Ctl {
   double gtp;          // g . p of the last direction
   double sigma0, armijo_c, rho;
   double stall_rel;
+  double rtol2;        // relative stop: |g|^2 <= rtol2 |g_0|^2
 };
 
 // Plain pointers to every device array of a mesh (passed by value).
@@ -81,7 +82,8 @@ struct DevMesh {
   const int64_t* sn_valoff;
   const int32_t* sn_front;   // offset of the supernode's positions in gptr
   const int32_t* rows;
-  const double* vals;
+  const double* vals;         // forward blocks [Linv; M], packed rows
+  const double* tvals;        // the same blocks transposed (columns of L as rows)
   const int32_t* gptr;       // [sum h + 1] children's update rows per front position
   const int32_t* gsrc;
   const int2* fwd_items;     // (supernode, first row)
@@ -98,6 +100,8 @@ struct DevMesh {
   double* part_gram;         // [nbg][kGramEntries]
   double* gram;              // [kGramEntries]
   double* zbuf;              // [48]
+  double* cfac;              // [48][48] Cholesky factor of the last Woodbury system
+  int32_t* cfac_ok;          // [1] 1 if that factorization succeeded
   double* part_ls;           // [nb][2*kLsTerms]
   Ctl* ctl;
 };

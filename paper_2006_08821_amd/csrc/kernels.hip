@@ -53,18 +53,18 @@ DEV DD dd_add_d(DD x, double y) {
 
 // Block-wide reduction of NV double-double values (kBlock threads); result valid
 // in thread 0.  Fixed tree order.
-template <int NV>
+template <int NV, int NT = kBlock>
 DEV void block_reduce_dd(DD (&v)[NV], DD* sh) {
   const int t = threadIdx.x;
-  for (int k = 0; k < NV; ++k) sh[k * kBlock + t] = v[k];
+  for (int k = 0; k < NV; ++k) sh[k * NT + t] = v[k];
   __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
+  for (int s = NT / 2; s > 0; s >>= 1) {
     if (t < s)
-      for (int k = 0; k < NV; ++k) sh[k * kBlock + t] = dd_add(sh[k * kBlock + t], sh[k * kBlock + t + s]);
+      for (int k = 0; k < NV; ++k) sh[k * NT + t] = dd_add(sh[k * NT + t], sh[k * NT + t + s]);
     __syncthreads();
   }
   if (t == 0)
-    for (int k = 0; k < NV; ++k) v[k] = sh[k * kBlock];
+    for (int k = 0; k < NV; ++k) v[k] = sh[k * NT];
 }
 
 // ------------------------------------------------------------------ 3x3 helpers
@@ -257,6 +257,14 @@ __device__ constexpr int kYn[9] = {1, 1, 1, 2, 2, 2, 2, 2, 2};
 __device__ constexpr int kYi[9][2] = {{0, 0}, {4, 4}, {8, 8}, {1, 3}, {2, 6}, {5, 7}, {1, 3}, {2, 6}, {5, 7}};
 __device__ constexpr double kYv[9][2] = {{1, 0}, {1, 0}, {1, 0}, {kRs2, kRs2}, {kRs2, kRs2}, {kRs2, kRs2},
                                          {kRs2, -kRs2}, {kRs2, -kRs2}, {kRs2, -kRs2}};
+
+
+// For each matrix entry A = 3a+i: the (up to two) basis elements with a nonzero
+// there and the value: diagonal -> symmetric basis only; off-diagonal ->
+// symmetric (1/sqrt2) and skew (+1/sqrt2 above, -1/sqrt2 below the diagonal).
+__device__ constexpr int kYof[9][2] = {{0, -1}, {3, 6}, {4, 7}, {3, 6}, {1, -1}, {5, 8}, {4, 7}, {5, 8}, {2, -1}};
+__device__ constexpr double kYvf[9][2] = {{1, 0}, {kRs2, kRs2}, {kRs2, kRs2}, {kRs2, -kRs2}, {1, 0},
+                                          {kRs2, kRs2}, {kRs2, -kRs2}, {kRs2, -kRs2}, {1, 0}};
 
 template <typename T>
 DEV T hproj(int y, int z, const T* S, T mu, T kappa, T phi, const T* u) {
@@ -507,94 +515,147 @@ __global__ void __launch_bounds__(kBlock) k_rhs(DevMesh d, int add_pin, int chec
   for (int c = 0; c < 3; ++c) d.rhs[3 * f + c] = acc[c];
 }
 
+// Packed-row products of the triangular sweeps.  A workgroup (4 waves) owns
+// kTriRows output rows; each wave splits into 8 groups of 8 lanes and a group
+// computes one row at a time: lanes stride the packed row (8 consecutive
+// doubles per step, 4 steps in flight), then reduce within the group.  The
+// vector the rows multiply lives in LDS, loaded in chunks of kVecChunk.
+constexpr int kVecChunk = 2048;
+
+template <bool kFwd>
+DEV void row_products(const double* __restrict__ V, int64_t base, int w, int h, int r0, int nrows,
+                      const double* vec, int vbase, int vlen, double (&acc)[kTriRows / 32][3]) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int g = lane >> 3, l = lane & 7;
+#pragma unroll
+  for (int k = 0; k < kTriRows / 32; ++k) {
+    const int rr = (k * 4 + wave) * 8 + g;  // row handled by this group in round k
+    const int r = r0 + rr;
+    double a0 = 0, a1 = 0, a2 = 0;
+    if (rr < nrows) {
+      // forward: row r has length (r < w ? r+1 : w), starts at column 0
+      // backward: row r (a column of L) covers vector entries [r, h)
+      int64_t roff;
+      int lo, hi;
+      if (kFwd) {
+        roff = r < w ? (int64_t)r * (r + 1) / 2 : (int64_t)w * (w + 1) / 2 + (int64_t)(r - w) * w;
+        lo = 0;
+        hi = r < w ? r + 1 : w;
+      } else {
+        roff = (int64_t)r * h - (int64_t)r * (r - 1) / 2;
+        lo = r;
+        hi = h;
+      }
+      // intersect with the vector chunk [vbase, vbase + vlen)
+      const int c0 = max(lo, vbase), c1 = min(hi, vbase + vlen);
+      const double* row = V + base + roff - lo;
+      int c = c0 + l;
+      for (; c + 24 < c1; c += 32) {
+        const double x0 = row[c], x1 = row[c + 8], x2 = row[c + 16], x3 = row[c + 24];
+        const double* v0 = vec + 3 * (c - vbase);
+        a0 += x0 * v0[0] + x1 * v0[24] + x2 * v0[48] + x3 * v0[72];
+        a1 += x0 * v0[1] + x1 * v0[25] + x2 * v0[49] + x3 * v0[73];
+        a2 += x0 * v0[2] + x1 * v0[26] + x2 * v0[50] + x3 * v0[74];
+      }
+      for (; c < c1; c += 8) {
+        const double x0 = row[c];
+        const double* v0 = vec + 3 * (c - vbase);
+        a0 += x0 * v0[0];
+        a1 += x0 * v0[1];
+        a2 += x0 * v0[2];
+      }
+    }
+#pragma unroll
+    for (int off = 4; off > 0; off >>= 1) {
+      a0 += __shfl_xor(a0, off);
+      a1 += __shfl_xor(a1, off);
+      a2 += __shfl_xor(a2, off);
+    }
+    acc[k][0] += a0;
+    acc[k][1] += a1;
+    acc[k][2] += a2;
+  }
+}
+
 // Forward sweep of one level.  Work item (s, r0): rows [r0, r0 + kTriRows) of
 // supernode s.  Frontal vector f = [rhs at the columns; 0] + children's update
 // vectors; rows r < w give y = Linv f_top, rows r >= w give u = f_r - M_r f_top.
 __global__ void __launch_bounds__(kBlock) k_fwd(DevMesh d, int it0, int check_done) {
   if (check_done && d.ctl->done) return;
-  __shared__ double ft[kMaxFrontW * 3];
+  __shared__ double ft[kVecChunk * 3];
   const int2 item = d.fwd_items[it0 + blockIdx.x];
   const int s = item.x, r0 = item.y;
   const int w = d.sn_w[s], h = d.sn_h[s], col0 = d.sn_col0[s];
   const int fo = d.sn_front[s];
   const int t = threadIdx.x;
-  for (int c = t; c < w; c += kBlock) {
-    double a0 = d.rhs[3 * (col0 + c)], a1 = d.rhs[3 * (col0 + c) + 1], a2 = d.rhs[3 * (col0 + c) + 2];
-    for (int k = d.gptr[fo + c]; k < d.gptr[fo + c + 1]; ++k) {
-      const double* u = d.upd + 3 * (int64_t)d.gsrc[k];
-      a0 += u[0];
-      a1 += u[1];
-      a2 += u[2];
+  const int nrows = min(kTriRows, h - r0);
+  // the rows of this item need f_top entries [0, min(w, r0 + nrows))
+  const int need = min(w, r0 + nrows);
+  double acc[kTriRows / 32][3] = {};
+  for (int vb = 0; vb < need; vb += kVecChunk) {
+    const int vl = min(kVecChunk, need - vb);
+    __syncthreads();
+    for (int k = t; k < vl; k += kBlock) {
+      const int c = vb + k;
+      double a0 = d.rhs[3 * (col0 + c)], a1 = d.rhs[3 * (col0 + c) + 1], a2 = d.rhs[3 * (col0 + c) + 2];
+      for (int q = d.gptr[fo + c]; q < d.gptr[fo + c + 1]; ++q) {
+        const double* u = d.upd + 3 * (int64_t)d.gsrc[q];
+        a0 += u[0];
+        a1 += u[1];
+        a2 += u[2];
+      }
+      ft[3 * k] = a0;
+      ft[3 * k + 1] = a1;
+      ft[3 * k + 2] = a2;
     }
-    ft[3 * c] = a0;
-    ft[3 * c + 1] = a1;
-    ft[3 * c + 2] = a2;
+    __syncthreads();
+    row_products<true>(d.vals, d.sn_valoff[s], w, h, r0, nrows, ft, vb, vl, acc);
   }
-  __syncthreads();
-  const int lane = t & 63, wave = t >> 6;
-  const double* V = d.vals + d.sn_valoff[s];
-  const int64_t tri = (int64_t)w * (w + 1) / 2;
-  for (int rr = wave; rr < kTriRows; rr += kBlock / 64) {
-    const int r = r0 + rr;
-    if (r >= h) break;
-    const double* row = r < w ? V + (int64_t)r * (r + 1) / 2 : V + tri + (int64_t)(r - w) * w;
-    const int len = r < w ? r + 1 : w;
-    double a0 = 0, a1 = 0, a2 = 0;
-    for (int c = lane; c < len; c += 64) {
-      double v = row[c];
-      a0 += v * ft[3 * c];
-      a1 += v * ft[3 * c + 1];
-      a2 += v * ft[3 * c + 2];
-    }
+  const int lane = t & 63, wave = t >> 6, g = lane >> 3, l = lane & 7;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      a0 += __shfl_xor(a0, off);
-      a1 += __shfl_xor(a1, off);
-      a2 += __shfl_xor(a2, off);
-    }
-    if (lane == 0) {
+  for (int k = 0; k < kTriRows / 32; ++k) {
+    const int rr = (k * 4 + wave) * 8 + g;
+    const int r = r0 + rr;
+    if (l == 0 && rr < nrows) {
       if (r < w) {
-        d.ybuf[3 * (col0 + r)] = a0;
-        d.ybuf[3 * (col0 + r) + 1] = a1;
-        d.ybuf[3 * (col0 + r) + 2] = a2;
+        d.ybuf[3 * (col0 + r)] = acc[k][0];
+        d.ybuf[3 * (col0 + r) + 1] = acc[k][1];
+        d.ybuf[3 * (col0 + r) + 2] = acc[k][2];
       } else {
         double b0 = 0, b1 = 0, b2 = 0;
-        for (int k = d.gptr[fo + r]; k < d.gptr[fo + r + 1]; ++k) {
-          const double* u = d.upd + 3 * (int64_t)d.gsrc[k];
+        for (int q = d.gptr[fo + r]; q < d.gptr[fo + r + 1]; ++q) {
+          const double* u = d.upd + 3 * (int64_t)d.gsrc[q];
           b0 += u[0];
           b1 += u[1];
           b2 += u[2];
         }
         double* o = d.upd + 3 * (int64_t)(d.sn_rowoff[s] + r - w);
-        o[0] = b0 - a0;
-        o[1] = b1 - a1;
-        o[2] = b2 - a2;
+        o[0] = b0 - acc[k][0];
+        o[1] = b1 - acc[k][1];
+        o[2] = b2 - acc[k][2];
       }
     }
   }
 }
 
-// Backward sweep of one level.  Work item (s, c0): columns [c0, c0 + kTriRows)
-// of supernode s:  x_c = sum_{r >= c, r < w} Linv[r][c] y_r - sum_r' M[r'][c] x[rows_r'].
+// Backward sweep of one level with the transposed blocks.  Work item (s, c0):
+// columns [c0, c0 + kTriRows) of supernode s.  With z = [y_s; -x[rows]],
+//   x_c = sum_{r >= c} L^{-T}-block[c][r - c] z[r].
 __global__ void __launch_bounds__(kBlock) k_bwd(DevMesh d, int it0, double* x, int check_done) {
   if (check_done && d.ctl->done) return;
-  constexpr int CH = 1024;
-  __shared__ double z[CH * 3];
-  __shared__ double part[kBlock / 64][64][3];
+  __shared__ double z[kVecChunk * 3];
   const int2 item = d.bwd_items[it0 + blockIdx.x];
   const int s = item.x, c0 = item.y;
   const int w = d.sn_w[s], h = d.sn_h[s], col0 = d.sn_col0[s];
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int c = c0 + lane;
-  const double* V = d.vals + d.sn_valoff[s];
-  const int64_t tri = (int64_t)w * (w + 1) / 2;
+  const int t = threadIdx.x;
+  const int ncols = min(kTriRows, w - c0);
   const int32_t* rows = d.rows + d.sn_rowoff[s];
-  double a0 = 0, a1 = 0, a2 = 0;
-  for (int base = c0; base < h; base += CH) {
-    const int nr = min(CH, h - base);
+  double acc[kTriRows / 32][3] = {};
+  for (int vb = c0; vb < h; vb += kVecChunk) {
+    const int vl = min(kVecChunk, h - vb);
     __syncthreads();
-    for (int k = t; k < nr; k += kBlock) {
-      const int r = base + k;
+    for (int k = t; k < vl; k += kBlock) {
+      const int r = vb + k;
       if (r < w) {
         z[3 * k] = d.ybuf[3 * (col0 + r)];
         z[3 * k + 1] = d.ybuf[3 * (col0 + r) + 1];
@@ -607,31 +668,17 @@ __global__ void __launch_bounds__(kBlock) k_bwd(DevMesh d, int it0, double* x, i
       }
     }
     __syncthreads();
-    if (c < w) {
-      for (int k = wave; k < nr; k += kBlock / 64) {
-        const int r = base + k;
-        double v;
-        if (r < w)
-          v = (c <= r) ? V[(int64_t)r * (r + 1) / 2 + c] : 0.0;
-        else
-          v = V[tri + (int64_t)(r - w) * w + c];
-        a0 += v * z[3 * k];
-        a1 += v * z[3 * k + 1];
-        a2 += v * z[3 * k + 2];
-      }
-    }
+    row_products<false>(d.tvals, d.sn_valoff[s], w, h, c0, ncols, z, vb, vl, acc);
   }
-  part[wave][lane][0] = a0;
-  part[wave][lane][1] = a1;
-  part[wave][lane][2] = a2;
-  __syncthreads();
-  if (wave == 0 && c < w) {
+  const int lane = t & 63, wave = t >> 6, g = lane >> 3, l = lane & 7;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      double sum = part[0][lane][k];
-#pragma unroll
-      for (int ww = 1; ww < kBlock / 64; ++ww) sum += part[ww][lane][k];
-      x[3 * (col0 + c) + k] = sum;
+  for (int k = 0; k < kTriRows / 32; ++k) {
+    const int cc = (k * 4 + wave) * 8 + g;
+    if (l == 0 && cc < ncols) {
+      const int c = c0 + cc;
+      x[3 * (col0 + c)] = acc[k][0];
+      x[3 * (col0 + c) + 1] = acc[k][1];
+      x[3 * (col0 + c) + 2] = acc[k][2];
     }
   }
 }
@@ -795,91 +842,161 @@ __global__ void __launch_bounds__(kBlock) k_element(DevMesh d) {
 // mode gradients gphi_j = sum_v phi_j(v) b_v.  Accumulates, per workgroup,
 //   Gram[(c,j),(c',j')] += w^2 gphi_j^T Z_{cc'} gphi_j'   (6 pairs c <= c')
 //   y[(c,j)]            += w (R D(gbar) gphi_j)[c]
+// A tile of 32 elements is staged in LDS (one thread per element builds Z).
+// Two groups of 128 threads then take alternate elements; in a group, thread
+// (pair, jb, qb) owns a 4x4 register tile of one 16x16 pair block and forms
+// h = Z_{cc'} gphi_j' for its 4 columns once per element; 12 more threads own
+// 4 entries of y each.  The two groups are added in a fixed order at the end.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_gram(DevMesh d) {
   if (d.ctl->done) return;
-  constexpr int TE = 64;
+  constexpr int TE = 32;
   __shared__ T zs[TE][45];
   __shared__ T gp[TE][kMaxK1][3];
   __shared__ T fg[TE][9];
   __shared__ T ws[TE];
+  __shared__ double comb[108][16];
   const int t = threadIdx.x;
   const int m = d.m;
   const int per = (m + d.nbg - 1) / d.nbg;
   const int e0 = blockIdx.x * per, e1 = min(m, e0 + per);
-  const int jj = t >> 4, jp = t & 15;
   const int k1 = d.k1;
-  T acc[6] = {0, 0, 0, 0, 0, 0};
-  T accy = 0;
-  const int yc = t >> 4, yj = t & 15;  // for t < 48
+  const int grp = t >> 7, tl = t & 127;
+  const bool gth = tl < 96, yth = tl >= 96 && tl < 108;
+  const int pair = tl >> 4, jb = (tl & 15) >> 2, qb = tl & 3;
+  const int pc = pair < 3 ? 0 : (pair < 5 ? 1 : 2);
+  const int pcp = pair < 3 ? pair : (pair < 5 ? pair - 2 : 2);
+  const int yc = (tl - 96) >> 2, yb = (tl - 96) & 3;
+  int zoff[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const int A = 3 * pc + a, B = 3 * pcp + b;
+      const int lo = A < B ? A : B, hi = A < B ? B : A;
+      zoff[a][b] = lo * 9 - lo * (lo - 1) / 2 + (hi - lo);
+    }
+  T acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0;
   for (int base = e0; base < e1; base += TE) {
     const int ne = min(TE, e1 - base);
     __syncthreads();
     if (t < ne) {
       const int i = base + t;
-      double R[9];
-      load_R(d, i, R);
+      T R[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) R[k] = (T)d.R[k * m + i];
       const T* Lf = (const T*)d.Lf;
       const T* gbar = (const T*)d.gbar;
-      T Ls[21], Lk[6];
+      // explicit block inverses H^{-1} = L^{-T} L^{-1} (6x6 and 3x3, packed lower)
+      T Hs[21], Hk[6];
+      {
+        T Ls[21], Li[21];
 #pragma unroll
-      for (int k = 0; k < 21; ++k) Ls[k] = Lf[k * m + i];
+        for (int k = 0; k < 21; ++k) Ls[k] = Lf[k * m + i];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) Lk[k] = Lf[(21 + k) * m + i];
-      // columns of T: vec(R Y_y), y = 0..8
-      T Tm[9][9];
+        for (int c = 0; c < 6; ++c) {
+          Li[c * (c + 1) / 2 + c] = T(1) / Ls[c * (c + 1) / 2 + c];
 #pragma unroll
-      for (int y = 0; y < 9; ++y) {
-        double Yy[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-        Yy[kYi[y][0]] += kYv[y][0];
-        if (kYn[y] > 1) Yy[kYi[y][1]] += kYv[y][1];
-        double RY[9];
-        matmul3(R, Yy, RY);
+          for (int r = c + 1; r < 6; ++r) {
+            T v = 0;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) Tm[k][y] = (T)RY[k];
+            for (int k = c; k < r; ++k) v += Ls[r * (r + 1) / 2 + k] * Li[k * (k + 1) / 2 + c];
+            Li[r * (r + 1) / 2 + c] = -v / Ls[r * (r + 1) / 2 + r];
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+          for (int c = 0; c <= r; ++c) {
+            T v = 0;
+#pragma unroll
+            for (int k = r; k < 6; ++k) v += Li[k * (k + 1) / 2 + r] * Li[k * (k + 1) / 2 + c];
+            Hs[r * (r + 1) / 2 + c] = v;
+          }
+        T Lk[6], Lki[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Lk[k] = Lf[(21 + k) * m + i];
+        Lki[0] = T(1) / Lk[0];
+        Lki[2] = T(1) / Lk[2];
+        Lki[5] = T(1) / Lk[5];
+        Lki[1] = -Lk[1] * Lki[0] * Lki[2];
+        Lki[4] = -Lk[4] * Lki[2] * Lki[5];
+        Lki[3] = -(Lk[3] * Lki[0] + Lk[4] * Lki[1]) * Lki[5];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int c = 0; c <= r; ++c) {
+            T v = 0;
+#pragma unroll
+            for (int k = r; k < 3; ++k) v += Lki[k * (k + 1) / 2 + r] * Lki[k * (k + 1) / 2 + c];
+            Hk[r * (r + 1) / 2 + c] = v;
+          }
       }
-      // N = T L^{-T} per block: rows n solve n L^T = t  (forward substitution)
-      T N[9][9];
+      // Z_X[(e,dd),(e',dd')] = sum Y H^{-1} Y^T (rotated frame), then per
+      // (dd <= dd') block Z[(c,dd),(c',dd')] = (R M R^T)[c][c'] with
+      // M[e][e'] = Z_X[(e,dd),(e',dd')]
 #pragma unroll
-      for (int r = 0; r < 9; ++r) {
+      for (int dd = 0; dd < 3; ++dd)
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
-          T v = Tm[r][j];
+        for (int dp = dd; dp < 3; ++dp) {
+          T Mx[3][3];
 #pragma unroll
-          for (int k = 0; k < j; ++k) v -= N[r][k] * Ls[j * (j + 1) / 2 + k];
-          N[r][j] = v / Ls[j * (j + 1) / 2 + j];
+          for (int e = 0; e < 3; ++e)
+#pragma unroll
+            for (int ep = 0; ep < 3; ++ep) {
+              const int A = 3 * e + dd, B = 3 * ep + dp;
+              T v = 0;
+#pragma unroll
+              for (int pa = 0; pa < 2; ++pa)
+#pragma unroll
+                for (int pb = 0; pb < 2; ++pb) {
+                  const int ya = kYof[A][pa], yb = kYof[B][pb];
+                  if (ya >= 0 && yb >= 0 && (ya < 6) == (yb < 6)) {
+                    const T cv = T(kYvf[A][pa] * kYvf[B][pb]);
+                    if (ya < 6) {
+                      const int lo = ya < yb ? ya : yb, hi = ya < yb ? yb : ya;
+                      v += cv * Hs[hi * (hi + 1) / 2 + lo];
+                    } else {
+                      const int lo = (ya < yb ? ya : yb) - 6, hi = (ya < yb ? yb : ya) - 6;
+                      v += cv * Hk[hi * (hi + 1) / 2 + lo];
+                    }
+                  }
+                }
+              Mx[e][ep] = v;
+            }
+          T RM[3][3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int ep = 0; ep < 3; ++ep)
+              RM[c][ep] = R[3 * c] * Mx[0][ep] + R[3 * c + 1] * Mx[1][ep] + R[3 * c + 2] * Mx[2][ep];
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int cp = 0; cp < 3; ++cp) {
+              if (dd == dp && cp < c) continue;
+              const T v = RM[c][0] * R[3 * cp] + RM[c][1] * R[3 * cp + 1] + RM[c][2] * R[3 * cp + 2];
+              const int A = 3 * c + dd, B = 3 * cp + dp;
+              const int lo = A < B ? A : B, hi = A < B ? B : A;
+              zs[t][lo * 9 - lo * (lo - 1) / 2 + (hi - lo)] = v;
+            }
         }
+      double gbd[9], D[9], RD[9], Rd[9];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          T v = Tm[r][6 + j];
-#pragma unroll
-          for (int k = 0; k < j; ++k) v -= N[r][6 + k] * Lk[j * (j + 1) / 2 + k];
-          N[r][6 + j] = v / Lk[j * (j + 1) / 2 + j];
-        }
+      for (int k = 0; k < 9; ++k) {
+        gbd[k] = (double)gbar[k * m + i];
+        Rd[k] = (double)R[k];
       }
-      int o = 0;
-#pragma unroll
-      for (int a = 0; a < 9; ++a)
-#pragma unroll
-        for (int b = a; b < 9; ++b) {
-          T s = 0;
-#pragma unroll
-          for (int k = 0; k < 9; ++k) s += N[a][k] * N[b][k];
-          zs[t][o++] = s;
-        }
-      T gb[9];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) gb[k] = gbar[k * m + i];
-      double gbd[9], D[9], RD[9];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) gbd[k] = (double)gb[k];
       from_y<double>(gbd, D);
-      matmul3(R, D, RD);
+      matmul3(Rd, D, RD);
 #pragma unroll
       for (int k = 0; k < 9; ++k) fg[t][k] = (T)RD[k];
       ws[t] = (T)d.w[i];
     }
-    // mode gradients, all threads
     for (int idx = t; idx < ne * kMaxK1; idx += kBlock) {
       const int el = idx / kMaxK1, j = idx % kMaxK1;
       const int i = base + el;
@@ -895,7 +1012,7 @@ __global__ void __launch_bounds__(kBlock) k_gram(DevMesh d) {
         double a0 = 0, a1 = 0, a2 = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          double ph = d.phi[(int64_t)kMaxK1 * d.vid[k * m + i] + j];
+          const double ph = d.phi[(int64_t)kMaxK1 * d.vid[k * m + i] + j];
           a0 += ph * b[k][0];
           a1 += ph * b[k][1];
           a2 += ph * b[k][2];
@@ -909,85 +1026,148 @@ __global__ void __launch_bounds__(kBlock) k_gram(DevMesh d) {
       gp[el][j][2] = g2;
     }
     __syncthreads();
-    // accumulate
-    for (int el = 0; el < ne; ++el) {
-      const T w2 = ws[el] * ws[el];
-      const T gj[3] = {gp[el][jj][0], gp[el][jj][1], gp[el][jj][2]};
-      const T gq[3] = {gp[el][jp][0], gp[el][jp][1], gp[el][jp][2]};
-      int pair = 0;
+    for (int el = grp; el < ne; el += 2) {
+      const T wv = ws[el];
+      if (gth) {
+        // Z_{c c'} block (3x3) from the packed upper triangle
+        T zb[3][3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int cp = c; cp < 3; ++cp) {
-          T s = 0;
+          for (int b = 0; b < 3; ++b) zb[a][b] = zs[el][zoff[a][b]];
+        T hh[3][4];
 #pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            T hz = 0;
+        for (int q = 0; q < 4; ++q) {
+          const T g0 = gp[el][4 * qb + q][0], g1 = gp[el][4 * qb + q][1], g2 = gp[el][4 * qb + q][2];
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-              const int A = 3 * c + a, B = 3 * cp + b;
-              const int lo = A < B ? A : B, hi = A < B ? B : A;
-              const int zi = lo * 9 - lo * (lo - 1) / 2 + (hi - lo);
-              hz += zs[el][zi] * gq[b];
-            }
-            s += gj[a] * hz;
-          }
-          acc[pair++] += w2 * s;
+          for (int a = 0; a < 3; ++a) hh[a][q] = zb[a][0] * g0 + zb[a][1] * g1 + zb[a][2] * g2;
         }
-      if (t < 48) {
-        accy += ws[el] * (fg[el][3 * yc] * gp[el][yj][0] + fg[el][3 * yc + 1] * gp[el][yj][1] +
-                          fg[el][3 * yc + 2] * gp[el][yj][2]);
+        const T w2 = wv * wv;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const T g0 = w2 * gp[el][4 * jb + a][0], g1 = w2 * gp[el][4 * jb + a][1], g2 = w2 * gp[el][4 * jb + a][2];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[a][q] += g0 * hh[0][q] + g1 * hh[1][q] + g2 * hh[2][q];
+        }
+      } else if (yth) {
+        const T f0 = wv * fg[el][3 * yc], f1 = wv * fg[el][3 * yc + 1], f2 = wv * fg[el][3 * yc + 2];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+          acc[0][a] += f0 * gp[el][4 * yb + a][0] + f1 * gp[el][4 * yb + a][1] + f2 * gp[el][4 * yb + a][2];
       }
     }
   }
-  double* out = d.part_gram + (int64_t)kGramEntries * blockIdx.x;
+  // combine the two groups in a fixed order, then write the partial sums
+  __syncthreads();
+  if (grp == 1 && tl < 108)
 #pragma unroll
-  for (int pr = 0; pr < 6; ++pr) out[pr * 256 + t] = (double)acc[pr];
-  if (t < 48) out[1536 + t] = (double)accy;
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) comb[tl][4 * a + q] = (double)acc[a][q];
+  __syncthreads();
+  double* out = d.part_gram + (int64_t)kGramEntries * blockIdx.x;
+  if (grp == 0 && gth) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        out[pair * 256 + (4 * jb + a) * 16 + 4 * qb + q] = (double)acc[a][q] + comb[tl][4 * a + q];
+  } else if (grp == 0 && yth) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) out[1536 + yc * 16 + 4 * yb + a] = (double)acc[0][a] + comb[tl][a];
+  }
 }
 
+// Partial Gram sums: 16 threads per entry sum interleaved workgroup partials,
+// then add their results in a fixed order.
 __global__ void __launch_bounds__(kBlock) k_gram_reduce(DevMesh d) {
   if (d.ctl->done) return;
-  int e = blockIdx.x * kBlock + threadIdx.x;
-  if (e >= kGramEntries) return;
-  double s = 0;
-  for (int b = 0; b < d.nbg; ++b) s += d.part_gram[(int64_t)b * kGramEntries + e];
-  d.gram[e] = s;
+  __shared__ double sh[16][17];
+  const int t = threadIdx.x, part = t >> 4, el = t & 15;
+  const int e = blockIdx.x * 16 + el;
+  double s0 = 0, s1 = 0;
+  if (e < kGramEntries) {
+    int b = part;
+    for (; b + 16 < d.nbg; b += 32) {
+      s0 += d.part_gram[(int64_t)b * kGramEntries + e];
+      s1 += d.part_gram[(int64_t)(b + 16) * kGramEntries + e];
+    }
+    if (b < d.nbg) s0 += d.part_gram[(int64_t)b * kGramEntries + e];
+  }
+  sh[part][el] = s0 + s1;
+  __syncthreads();
+  if (part == 0 && e < kGramEntries) {
+    double s = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += sh[k][el];
+    d.gram[e] = s;
+  }
 }
 
-// Single workgroup: reduce energy / gradient-norm partials, test convergence,
-// then build C = Lambda - alpha Gram (3k1 x 3k1), Cholesky, z = C^{-1} y.
-__global__ void __launch_bounds__(kBlock) k_control_a(DevMesh d) {
+// One workgroup: reduce energy / gradient-norm partials, test convergence,
+// build C = Lambda - alpha Gram (3k1 x 3k1) with all threads; then the first
+// wave factors it (Cholesky, lane r owns row r in registers, pivot columns
+// broadcast by lane shuffles) and solves z = C^{-1} y.
+constexpr int kCtlThreads = kBlock;
+__global__ void __launch_bounds__(kCtlThreads) k_control_a(DevMesh d) {
   Ctl* ctl = d.ctl;
   if (ctl->done) return;
-  __shared__ DD sh[2 * kBlock];
+  __shared__ DD sh[2 * kCtlThreads];
+  __shared__ int cnt[2][kCtlThreads];
   __shared__ double Cm[48][49];
   __shared__ double yv[48];
   __shared__ int flag;
   const int t = threadIdx.x;
   DD acc[2] = {DD{0, 0}, DD{0, 0}};
   int cl = 0, inv = 0;
-  for (int b = t; b < d.nb; b += kBlock) {
+  for (int b = t; b < d.nb; b += kCtlThreads) {
     acc[0] = dd_add(acc[0], DD{d.part_e[2 * b], d.part_e[2 * b + 1]});
     acc[1] = dd_add(acc[1], DD{d.part_g[2 * b], d.part_g[2 * b + 1]});
+    cl += d.part_cnt[2 * b];
+    inv += d.part_cnt[2 * b + 1];
   }
-  block_reduce_dd<2>(acc, sh);
-  if (t == 0) {
-    for (int b = 0; b < d.nb; ++b) {
-      cl += d.part_cnt[2 * b];
-      inv += d.part_cnt[2 * b + 1];
+  // C and y do not depend on the convergence decision: load them now.  The
+  // system is padded to 48 x 48 with the identity (unused modes).
+  const int k1 = d.k1, K = 3 * k1;
+  for (int idx = t; idx < 48 * 48; idx += kCtlThreads) {
+    const int r = idx / 48, q = idx % 48;
+    if (q > r) continue;
+    double v = (r == q) ? 1.0 : 0.0;
+    if (r < K && q < K) {
+      const int c = r / k1, j = r % k1, cp = q / k1, jp = q % k1;
+      // lower triangle: c >= cp; the stored pair is (cp, c)
+      const int pair = cp == 0 ? c : (cp == 1 ? 2 + c : 5);
+      const double g1 = d.gram[pair * 256 + jp * 16 + j];
+      double g = g1;
+      if (c == cp) g = 0.5 * (g1 + d.gram[pair * 256 + j * 16 + jp]);
+      v = (r == q ? d.nu[j] : 0.0) - d.alpha * g;
     }
+    Cm[r][q] = v;
+  }
+  for (int r = t; r < 48; r += kCtlThreads) yv[r] = r < K ? d.gram[1536 + (r / k1) * 16 + (r % k1)] : 0.0;
+  block_reduce_dd<2, kCtlThreads>(acc, sh);
+  cnt[0][t] = cl;
+  cnt[1][t] = inv;
+  __syncthreads();
+  for (int s2 = kCtlThreads / 2; s2 > 0; s2 >>= 1) {
+    if (t < s2) {
+      cnt[0][t] += cnt[0][t + s2];
+      cnt[1][t] += cnt[1][t + s2];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
     const double g2 = acc[1].hi + acc[1].lo;
     ctl->energy = acc[0].hi + acc[0].lo;
     ctl->gnorm2 = g2;
-    ctl->clamped = cl;
-    ctl->inverted = inv;
+    ctl->clamped = cnt[0][0];
+    ctl->inverted = cnt[1][0];
     if (ctl->iter == 0 && ctl->gnorm0_2 < 0) ctl->gnorm0_2 = g2;
     int stop = 0;
     if (!(g2 == g2) || !(ctl->energy == ctl->energy) || g2 > 1e300) {
       ctl->status = EMU_E_NONFINITE_CODE;
       stop = 1;
-    } else if (!ctl->eval_only && g2 <= ctl->tol2) {
+    } else if (!ctl->eval_only && (g2 <= ctl->tol2 || (ctl->rtol2 > 0 && g2 <= ctl->rtol2 * ctl->gnorm0_2))) {
       ctl->status = 0;
       stop = 1;
     } else if (!ctl->eval_only && ctl->iter >= ctl->max_iters) {
@@ -995,76 +1175,66 @@ __global__ void __launch_bounds__(kBlock) k_control_a(DevMesh d) {
       stop = 1;
     }
     flag = stop;
+    if (stop) ctl->done = 1;
   }
   __syncthreads();
-  if (flag) {
-    if (t == 0) ctl->done = 1;
-    return;
-  }
-  const int k1 = d.k1, K = 3 * k1;
-  if (K == 0) {
-    return;
-  }
-  // C[(c,j),(c',j')] in compact indices (c*k1 + j)
-  for (int idx = t; idx < K * K; idx += kBlock) {
-    const int r = idx / K, q = idx % K;
-    const int c = r / k1, j = r % k1, cp = q / k1, jp = q % k1;
-    double g;
-    if (c <= cp) {
-      const int pair = c == 0 ? cp : (c == 1 ? 2 + cp : 5);
-      g = d.gram[pair * 256 + j * 16 + jp];
-    } else {
-      const int pair = cp == 0 ? c : (cp == 1 ? 2 + c : 5);
-      g = d.gram[pair * 256 + jp * 16 + j];
+  if (flag || K == 0 || t >= 64) return;
+  // ---- the first wave alone from here (LDS accesses of one wave execute in
+  // program order, so no barrier is needed).  The padded 48 x 48 matrix is
+  // copied column-major (CmT[k][t] = C[t][k]) so that lane t's row is read
+  // without bank conflicts; pivot columns are broadcast through colbuf.
+  __shared__ double CmT[48][64];
+  __shared__ double colbuf[64];
+  for (int k = 0; k < 48; ++k) CmT[k][t] = (t < 48 && k <= t) ? Cm[t][k] : 0.0;
+  __builtin_amdgcn_wave_barrier();
+  int bad = 0;
+  for (int j = 0; j < 48; ++j) {
+    const double dj = CmT[j][j];
+    bad |= !(dj > 0);
+    const double piv = dj > 0 ? sqrt(dj) : 1.0;
+    const double own = CmT[j][t];
+    const double lij = (t > j) ? own / piv : (t == j ? piv : 0.0);
+    if (t >= j) CmT[j][t] = lij;
+    colbuf[t] = lij;
+    __builtin_amdgcn_wave_barrier();
+    // branch-free trailing update (rows k > t are multiplied by 0)
+#pragma unroll 8
+    for (int k = j + 1; k < 48; ++k) {
+      const double mk = (k <= t) ? lij : 0.0;
+      CmT[k][t] -= mk * colbuf[k];
     }
-    Cm[r][q] = (r == q ? d.nu[j] : 0.0) - d.alpha * g;
+    __builtin_amdgcn_wave_barrier();
   }
-  for (int r = t; r < K; r += kBlock) yv[r] = d.gram[1536 + (r / k1) * 16 + (r % k1)];
-  __syncthreads();
-  // symmetrize, then right-looking Cholesky in place (lower)
-  for (int idx = t; idx < K * K; idx += kBlock) {
-    const int r = idx / K, q = idx % K;
-    if (r > q) {
-      double v = 0.5 * (Cm[r][q] + Cm[q][r]);
-      Cm[r][q] = v;
-    }
+  // forward substitution L u = y (lane t holds y_t; L[t][i] = CmT[i][t])
+  double yt = t < 48 ? yv[t] : 0.0;
+  for (int i = 0; i < 48; ++i) {
+    const double lti = CmT[i][t];
+    double ui = (t == i) ? yt / lti : 0.0;
+    ui = __shfl(ui, i);
+    if (t == i) yt = ui;
+    else if (t > i) yt -= lti * ui;
   }
-  if (t == 0) flag = 0;
-  __syncthreads();
-  for (int j = 0; j < K; ++j) {
-    if (t == 0) {
-      double v = Cm[j][j];
-      if (!(v > 0)) flag = 1;
-      Cm[j][j] = v > 0 ? sqrt(v) : 1.0;
-    }
-    __syncthreads();
-    for (int i = j + 1 + t; i < K; i += kBlock) Cm[i][j] /= Cm[j][j];
-    __syncthreads();
-    for (int idx = t; idx < (K - j - 1) * (K - j - 1); idx += kBlock) {
-      const int i = j + 1 + idx / (K - j - 1), k = j + 1 + idx % (K - j - 1);
-      if (k <= i) Cm[i][k] -= Cm[i][j] * Cm[k][j];
-    }
-    __syncthreads();
+  // row-major copy for the backward substitution (L[i][t] = Cm[i][t])
+  for (int k = 0; k < 48; ++k)
+    if (t < 48) Cm[t][k] = CmT[k][t];
+  __builtin_amdgcn_wave_barrier();
+  for (int i = 47; i >= 0; --i) {
+    const double lit = (t < 48) ? Cm[i][t] : 0.0;
+    const double lii = CmT[i][i];
+    double zi = (t == i) ? yt / lii : 0.0;
+    zi = __shfl(zi, i);
+    if (t == i) yt = zi;
+    else if (t < i) yt -= lit * zi;
   }
-  if (t == 0) {
-    double zz[48];
-    if (flag) {
-      for (int r = 0; r < K; ++r) zz[r] = 0.0;
-      ctl->chol_fail += 1;
-    } else {
-      for (int i = 0; i < K; ++i) {
-        double s = yv[i];
-        for (int k = 0; k < i; ++k) s -= Cm[i][k] * zz[k];
-        zz[i] = s / Cm[i][i];
-      }
-      for (int i = K - 1; i >= 0; --i) {
-        double s = zz[i];
-        for (int k = i + 1; k < K; ++k) s -= Cm[k][i] * zz[k];
-        zz[i] = s / Cm[i][i];
-      }
-    }
-    for (int c = 0; c < 3; ++c)
-      for (int j = 0; j < kMaxK1; ++j) d.zbuf[c * kMaxK1 + j] = j < k1 ? zz[c * k1 + j] : 0.0;
+  if (t < 48) yv[t] = yt;
+  __builtin_amdgcn_wave_barrier();
+  if (t == 0 && bad) ctl->chol_fail += 1;
+  if (t == 0) d.cfac_ok[0] = !bad;
+  for (int r = t; r < 48; r += 64)
+    for (int k = 0; k < 48; ++k) d.cfac[r * 48 + k] = k <= r ? Cm[r][k] : 0.0;
+  if (t < 48) {
+    const int c = t / kMaxK1, j = t % kMaxK1;
+    d.zbuf[t] = (!bad && j < k1) ? yv[c * k1 + j] : 0.0;
   }
 }
 
@@ -1271,6 +1441,317 @@ __global__ void __launch_bounds__(kBlock) k_control_b(DevMesh d) {
   }
 }
 
+// ------------------------------------------------------------------ adjoint
+// Exact Hessian-vector products and the quasi-Newton preconditioner used by
+// the adjoint conjugate-gradient solve.  Vectors over elements are F-coordinate
+// fields in world frame, structure of arrays [9][m].
+
+// per-thread sum of 2 values into a block partial (double-double)
+template <int NV>
+DEV void write_partial(DD (&acc)[NV], DD* sh, double* out) {
+  block_reduce_dd<NV>(acc, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      out[2 * k] = acc[k].hi;
+      out[2 * k + 1] = acc[k].lo;
+    }
+}
+
+// ACAP right-hand-side contributions of a field V ([9][m])
+__global__ void __launch_bounds__(kBlock) k_contrib_field(DevMesh d, const double* V) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.m) return;
+  Elem e;
+  load_elem(d, i, e);
+  double F[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) F[k] = V[k * d.m + i];
+  write_contrib(d, i, e, F);
+}
+
+// b_i = w_i A_i(x)  (x: vertex field [n][3], zero at pins)
+__global__ void __launch_bounds__(kBlock) k_weighted_grad(DevMesh d, const double* x, double* out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.m) return;
+  Elem e;
+  load_elem(d, i, e);
+  double A[9];
+  gather_grad(x, e, A);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) out[k * d.m + i] = e.w * A[k];
+}
+
+// out = H v with H = d2E/dF2 = blockdiag(vol d2Psi(F_i)) + alpha W - alpha W G L^{-1} G^T W:
+//   out_i = vol d2Psi(F_i)[v_i] + beta_i (v_i - A_i(x)),  x = L^{-1} G^T W v.
+// d2Psi[V] in the rotated frame at the symmetric S (X = R^T V):
+//   mu X + lhat <cof S, X> cof S + kappa dcof(S)[X] + 2 a kf (X u) u^T,
+// with dcof(S)[X] = cof(S + X) - cof(S) - cof(X).  Block partial of v . out.
+__global__ void __launch_bounds__(kBlock) k_hvp(DevMesh d, const double* V, const double* x, double* out,
+                                                double* part) {
+  __shared__ DD sh[kBlock];
+  DD acc[1] = {DD{0, 0}};
+  const int m = d.m;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
+    Elem e;
+    load_elem(d, i, e);
+    double R[9], S[9], v[9], X[9], A[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v[k] = V[k * m + i];
+    load_R(d, i, R);
+    load_S(d, i, S);
+    matTmul3(R, v, X);
+    const double J = det3(S);
+    double CS[9], SX[9], CSX[9], CX[9];
+    cof3<double>(S, CS);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) SX[k] = S[k] + X[k];
+    cof3<double>(SX, CSX);
+    cof3<double>(X, CX);
+    double cx = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) cx += CS[k] * X[k];
+    const double kap = e.lhat * (J - 1.0) - e.mu, afk2 = 2.0 * e.a * d.kf;
+    double Xu[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Xu[c] = X[3 * c] * e.u[0] + X[3 * c + 1] * e.u[1] + X[3 * c + 2] * e.u[2];
+    double HX[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const int k = 3 * a + b;
+        HX[k] = e.vol * (e.mu * X[k] + e.lhat * cx * CS[k] + kap * (CSX[k] - CS[k] - CX[k]) + afk2 * Xu[a] * e.u[b]);
+      }
+    double Hv[9];
+    matmul3(R, HX, Hv);
+    gather_grad(x, e, A);
+    const double beta = d.alpha * e.w;
+    double vh = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double o = Hv[k] + beta * (v[k] - A[k]);
+      out[k * m + i] = o;
+      vh += v[k] * o;
+    }
+    acc[0] = dd_add_d(acc[0], vh);
+  }
+  write_partial<1>(acc, sh, part + 2 * blockIdx.x);
+}
+
+// lam += alpha p, r -= alpha Hp; block partial of |r|^2
+__global__ void __launch_bounds__(kBlock) k_cg_update(DevMesh d, double alpha, const double* P, const double* HP,
+                                                      double* lam, double* r, double* part) {
+  __shared__ DD sh[kBlock];
+  DD acc[1] = {DD{0, 0}};
+  const int64_t n9 = 9 * (int64_t)d.m;
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n9; k += (int64_t)d.nb * kBlock) {
+    lam[k] += alpha * P[k];
+    const double rv = r[k] - alpha * HP[k];
+    r[k] = rv;
+    acc[0] = dd_add_d(acc[0], rv * rv);
+  }
+  write_partial<1>(acc, sh, part + 2 * blockIdx.x);
+}
+
+// p = z + beta p
+__global__ void __launch_bounds__(kBlock) k_cg_dir(DevMesh d, double beta, const double* Z, double* P) {
+  const int64_t n9 = 9 * (int64_t)d.m;
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n9; k += (int64_t)d.nb * kBlock)
+    P[k] = Z[k] + beta * P[k];
+}
+
+// Preconditioner, part 1: rbar = H^{-1} Y^T vec(R^T r) (blocks), stored in d.p,
+// and block partials of y[(c,j)] = sum_i w_i (R D(rbar) gphi_j)[c].
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_pc1(DevMesh d, const double* r, double* ypart) {
+  __shared__ double red[kBlock / 64][48];
+  const int m = d.m;
+  const T* Lf = (const T*)d.Lf;
+  double y[48];
+#pragma unroll
+  for (int k = 0; k < 48; ++k) y[k] = 0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
+    Elem e;
+    load_elem(d, i, e);
+    double R[9], rv[9], X[9];
+    load_R(d, i, R);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) rv[k] = r[k * m + i];
+    matTmul3(R, rv, X);
+    T ry[9];
+    to_y<T, double>(X, ry);
+    T Ls[21], Lk[6];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) Ls[k] = Lf[k * m + i];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Lk[k] = Lf[(21 + k) * m + i];
+    chol_solve<T, 6>(Ls, ry);
+    chol_solve<T, 3>(Lk, ry + 6);
+    double rb[9], D[9], RD[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      rb[k] = (double)ry[k];
+      d.p[k * m + i] = rb[k];
+    }
+    from_y<double>(rb, D);
+    matmul3(R, D, RD);
+    for (int j = 0; j < d.k1; ++j) {
+      double g0 = 0, g1 = 0, g2 = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double ph = d.phi[(int64_t)kMaxK1 * e.v[k] + j];
+        g0 += ph * e.b[k][0];
+        g1 += ph * e.b[k][1];
+        g2 += ph * e.b[k][2];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double contrib = e.w * (RD[3 * c] * g0 + RD[3 * c + 1] * g1 + RD[3 * c + 2] * g2);
+#pragma unroll
+        for (int jj = 0; jj < kMaxK1; ++jj)
+          if (jj == j) y[c * kMaxK1 + jj] += contrib;
+      }
+    }
+  }
+  // wave butterfly, then the 4 waves in order
+#pragma unroll
+  for (int k = 0; k < 48; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) y[k] += __shfl_xor(y[k], off);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 48; ++k) red[wave][k] = y[k];
+  __syncthreads();
+  if (threadIdx.x < 48) {
+    double s0 = 0;
+#pragma unroll
+    for (int w2 = 0; w2 < kBlock / 64; ++w2) s0 += red[w2][threadIdx.x];
+    ypart[48 * blockIdx.x + threadIdx.x] = s0;
+  }
+}
+
+// Preconditioner, part 2 (one workgroup): y = sum of partials, z = C^{-1} y with
+// the Cholesky factor of C kept by the last element/Gram pass.
+__global__ void __launch_bounds__(64) k_pc_solve(DevMesh d, const double* ypart) {
+  __shared__ double yv[48];
+  const int t = threadIdx.x;
+  const int k1 = d.k1, K = 3 * k1;
+  if (t < 48) {
+    double s0 = 0;
+    for (int b = 0; b < d.nb; ++b) s0 += ypart[48 * b + t];
+    yv[t] = s0;
+  }
+  __syncthreads();
+  if (K == 0) {
+    if (t < 48) d.zbuf[t] = 0.0;
+    return;
+  }
+  // compact index c*k1+j
+  double yt = 0.0;
+  if (t < K) yt = yv[(t / k1) * kMaxK1 + (t % k1)];
+  const double* L = d.cfac;
+  for (int i = 0; i < K; ++i) {
+    const double lti = (t < K) ? L[t * 48 + i] : 1.0;
+    double ui = (t == i) ? yt / lti : 0.0;
+    ui = __shfl(ui, i);
+    if (t == i) yt = ui;
+    else if (t > i && t < K) yt -= lti * ui;
+  }
+  for (int i = K - 1; i >= 0; --i) {
+    const double lit = (t < K) ? L[i * 48 + t] : 0.0;
+    const double lii = L[i * 48 + i];
+    double zi = (t == i) ? yt / lii : 0.0;
+    zi = __shfl(zi, i);
+    if (t == i) yt = zi;
+    else if (t < i) yt -= lit * zi;
+  }
+  if (t < K) yv[t] = yt;
+  __syncthreads();
+  if (t < 48) {
+    const int c = t / kMaxK1, j = t % kMaxK1;
+    d.zbuf[t] = (j < k1 && d.cfac_ok[0]) ? yv[c * k1 + j] : 0.0;
+  }
+}
+
+// Preconditioner, part 3: z_i = R D(rbar_i + alpha H^{-1} w Y^T vec(R^T A_i(uz)))
+// (F coordinates); block partials of r . z.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_pc2(DevMesh d, const double* r, double* zout, double* part) {
+  __shared__ DD sh[kBlock];
+  DD acc[1] = {DD{0, 0}};
+  const int m = d.m;
+  const T* Lf = (const T*)d.Lf;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
+    Elem e;
+    load_elem(d, i, e);
+    double R[9], Az[9], RA[9];
+    load_R(d, i, R);
+    gather_grad(d.uz, e, Az);
+    matTmul3(R, Az, RA);
+    T ty[9];
+    to_y<T, double>(RA, ty);
+    T Ls[21], Lk[6];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) Ls[k] = Lf[k * m + i];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Lk[k] = Lf[(21 + k) * m + i];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) ty[k] *= (T)e.w;
+    chol_solve<T, 6>(Ls, ty);
+    chol_solve<T, 3>(Lk, ty + 6);
+    double zy[9], D[9], Z[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) zy[k] = d.p[k * m + i] + d.alpha * (double)ty[k];
+    from_y<double>(zy, D);
+    matmul3(R, D, Z);
+    double rz = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      zout[k * m + i] = Z[k];
+      rz += r[k * m + i] * Z[k];
+    }
+    acc[0] = dd_add_d(acc[0], rz);
+  }
+  write_partial<1>(acc, sh, part + 2 * blockIdx.x);
+}
+
+// dL/da partials: per group g, sum over its tets of vol (lam_i u).(F_i u)
+__global__ void __launch_bounds__(kBlock) k_adj_da(DevMesh d, const double* lam, double* part) {
+  const int m = d.m;
+  const int ng = d.ngroups;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
+    const int g = d.grp[i];
+    double val = 0.0;
+    if (g >= 0) {
+      Elem e;
+      load_elem(d, i, e);
+      double R[9], S[9], F[9], L[9];
+      load_R(d, i, R);
+      load_S(d, i, S);
+      matmul3(R, S, F);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) L[k] = lam[k * m + i];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double lu = L[3 * c] * e.u[0] + L[3 * c + 1] * e.u[1] + L[3 * c + 2] * e.u[2];
+        const double fu = F[3 * c] * e.u[0] + F[3 * c + 1] * e.u[1] + F[3 * c + 2] * e.u[2];
+        val += lu * fu;
+      }
+      val *= e.vol;
+    }
+    part[i] = val;  // per element; summed per group on the host in element order
+    (void)ng;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_scale_free(DevMesh d, const double* in, double* out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * d.nf) return;
+  out[i] = in[i];
+}
+
 // ------------------------------------------------------------------ launch helpers
 static inline int blocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
@@ -1300,6 +1781,46 @@ void launch_solve(const DevMesh& d, const SolvePlan& pl, int add_pin, double* x,
     if (n1 > n0) hipLaunchKernelGGL(k_bwd, dim3(n1 - n0), dim3(kBlock), 0, st, d, n0, x, check_done);
   }
 }
+void launch_sweeps(const DevMesh& d, const SolvePlan& pl, double* x, hipStream_t st) {
+  for (int L = 0; L < pl.nlevels; ++L) {
+    int n0 = pl.fwd_ptr[L], n1 = pl.fwd_ptr[L + 1];
+    if (n1 > n0) hipLaunchKernelGGL(k_fwd, dim3(n1 - n0), dim3(kBlock), 0, st, d, n0, 0);
+  }
+  for (int L = 0; L < pl.nlevels; ++L) {
+    int n0 = pl.bwd_ptr[L], n1 = pl.bwd_ptr[L + 1];
+    if (n1 > n0) hipLaunchKernelGGL(k_bwd, dim3(n1 - n0), dim3(kBlock), 0, st, d, n0, x, 0);
+  }
+}
+void launch_field_solve(const DevMesh& d, const SolvePlan& pl, const double* V, double* x, hipStream_t st) {
+  hipLaunchKernelGGL(k_contrib_field, dim3(blocks(d.m)), dim3(kBlock), 0, st, d, V);
+  hipLaunchKernelGGL(k_rhs, dim3(blocks(d.nf)), dim3(kBlock), 0, st, d, 0, 0);
+  launch_sweeps(d, pl, x, st);
+}
+void launch_weighted_grad(const DevMesh& d, const double* x, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_weighted_grad, dim3(blocks(d.m)), dim3(kBlock), 0, st, d, x, out);
+}
+void launch_hvp(const DevMesh& d, const double* V, const double* x, double* out, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_hvp, dim3(d.nb), dim3(kBlock), 0, st, d, V, x, out, part);
+}
+void launch_cg_update(const DevMesh& d, double alpha, const double* P, const double* HP, double* lam, double* r,
+                      double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_update, dim3(d.nb), dim3(kBlock), 0, st, d, alpha, P, HP, lam, r, part);
+}
+void launch_cg_dir(const DevMesh& d, double beta, const double* Z, double* P, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_dir, dim3(d.nb), dim3(kBlock), 0, st, d, beta, Z, P);
+}
+void launch_precond(const DevMesh& d, const double* r, double* z, double* ypart, double* part, hipStream_t st) {
+  if (d.mixed) hipLaunchKernelGGL(k_pc1<float>, dim3(d.nb), dim3(kBlock), 0, st, d, r, ypart);
+  else hipLaunchKernelGGL(k_pc1<double>, dim3(d.nb), dim3(kBlock), 0, st, d, r, ypart);
+  hipLaunchKernelGGL(k_pc_solve, dim3(1), dim3(64), 0, st, d, ypart);
+  hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d);
+  if (d.mixed) hipLaunchKernelGGL(k_pc2<float>, dim3(d.nb), dim3(kBlock), 0, st, d, r, z, part);
+  else hipLaunchKernelGGL(k_pc2<double>, dim3(d.nb), dim3(kBlock), 0, st, d, r, z, part);
+}
+void launch_adj_da(const DevMesh& d, const double* lam, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_da, dim3(d.nb), dim3(kBlock), 0, st, d, lam, part);
+}
+
 void launch_set_pins(const DevMesh& d, hipStream_t st) {
   hipLaunchKernelGGL(k_set_pins, dim3(blocks(d.npins)), dim3(kBlock), 0, st, d);
 }
@@ -1312,8 +1833,8 @@ void launch_iteration(const DevMesh& d, const SolvePlan& pl, hipStream_t st) {
     hipLaunchKernelGGL(k_element<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
     hipLaunchKernelGGL(k_gram<double>, dim3(d.nbg), dim3(kBlock), 0, st, d);
   }
-  hipLaunchKernelGGL(k_gram_reduce, dim3(blocks(kGramEntries)), dim3(kBlock), 0, st, d);
-  hipLaunchKernelGGL(k_control_a, dim3(1), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((kGramEntries + 15) / 16), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_control_a, dim3(1), dim3(kCtlThreads), 0, st, d);
   hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d);
   if (d.mixed)
     hipLaunchKernelGGL(k_direction<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
@@ -1335,8 +1856,8 @@ void launch_class(int k, const DevMesh& d, const SolvePlan& pl, hipStream_t st) 
       if (d.mixed) hipLaunchKernelGGL(k_gram<float>, dim3(d.nbg), dim3(kBlock), 0, st, d);
       else hipLaunchKernelGGL(k_gram<double>, dim3(d.nbg), dim3(kBlock), 0, st, d);
       break;
-    case 2: hipLaunchKernelGGL(k_gram_reduce, dim3(blocks(kGramEntries)), dim3(kBlock), 0, st, d); break;
-    case 3: hipLaunchKernelGGL(k_control_a, dim3(1), dim3(kBlock), 0, st, d); break;
+    case 2: hipLaunchKernelGGL(k_gram_reduce, dim3((kGramEntries + 15) / 16), dim3(kBlock), 0, st, d); break;
+    case 3: hipLaunchKernelGGL(k_control_a, dim3(1), dim3(kCtlThreads), 0, st, d); break;
     case 4: hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d); break;
     case 5:
       if (d.mixed) hipLaunchKernelGGL(k_direction<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
@@ -1371,8 +1892,8 @@ void launch_evaluate(const DevMesh& d, hipStream_t st) {
     hipLaunchKernelGGL(k_element<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
     hipLaunchKernelGGL(k_gram<double>, dim3(d.nbg), dim3(kBlock), 0, st, d);
   }
-  hipLaunchKernelGGL(k_gram_reduce, dim3(blocks(kGramEntries)), dim3(kBlock), 0, st, d);
-  hipLaunchKernelGGL(k_control_a, dim3(1), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((kGramEntries + 15) / 16), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_control_a, dim3(1), dim3(kCtlThreads), 0, st, d);
   hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d);
   if (d.mixed)
     hipLaunchKernelGGL(k_direction<float>, dim3(d.nb), dim3(kBlock), 0, st, d);

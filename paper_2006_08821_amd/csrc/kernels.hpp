@@ -32,5 +32,15 @@ void launch_set_pins(const DevMesh& d, hipStream_t st);
 void launch_iteration(const DevMesh& d, const SolvePlan& pl, hipStream_t st);
 void launch_evaluate(const DevMesh& d, hipStream_t st);
 void launch_class(int k, const DevMesh& d, const SolvePlan& pl, hipStream_t st);
+// adjoint building blocks
+void launch_sweeps(const DevMesh& d, const SolvePlan& pl, double* x, hipStream_t st);
+void launch_field_solve(const DevMesh& d, const SolvePlan& pl, const double* V, double* x, hipStream_t st);
+void launch_weighted_grad(const DevMesh& d, const double* x, double* out, hipStream_t st);
+void launch_hvp(const DevMesh& d, const double* V, const double* x, double* out, double* part, hipStream_t st);
+void launch_cg_update(const DevMesh& d, double alpha, const double* P, const double* HP, double* lam, double* r,
+                      double* part, hipStream_t st);
+void launch_cg_dir(const DevMesh& d, double beta, const double* Z, double* P, hipStream_t st);
+void launch_precond(const DevMesh& d, const double* r, double* z, double* ypart, double* part, hipStream_t st);
+void launch_adj_da(const DevMesh& d, const double* lam, double* part, hipStream_t st);
 
 }  // namespace emu

@@ -203,6 +203,16 @@ class Mesh:
         F = t.as_tensor(F, dtype=t.float64, device="cuda").contiguous()
         check(self._lib.emu_set_state(self._h, C.c_void_p(F.data_ptr()), _stream(t)), "emu_set_state")
 
+    def solve_grad(self, dL_dq, stats=False):
+        """dL/da (numpy [n_groups]) at the converged state for dL/dq ([n,3] GPU tensor)."""
+        t = self.torch
+        g = t.as_tensor(dL_dq, dtype=t.float64, device="cuda").contiguous()
+        out = np.zeros(max(1, self.n_groups))
+        st = _lib.SolveStats()
+        check(self._lib.emu_solve_grad(self._h, C.c_void_p(g.data_ptr()), dptr(out), C.byref(st), _stream(t)),
+              "emu_solve_grad")
+        return (out[:self.n_groups], st.as_dict()) if stats else out[:self.n_groups]
+
     def profile_kernels(self, reps=20):
         """Average device ms per kernel class (HIP events), {name: ms}."""
         t = self.torch
@@ -223,3 +233,42 @@ class Mesh:
                                      C.c_void_p(dvec.data_ptr()) if dvec is not None else None,
                                      _stream(t)), "emu_evaluate")
         return dict(q=q, energy=e.value, grad_norm=g.value, direction=dvec)
+
+
+class _SolveFn:
+    """torch.autograd.Function: activations -> equilibrium positions.
+
+    forward: emu_set_activation + emu_solve (to the given tolerance);
+    backward: emu_solve_grad (adjoint of the equilibrium w.r.t. activations)."""
+
+    _cls = None
+
+    @classmethod
+    def get(cls):
+        if cls._cls is None:
+            import torch
+
+            class SolveFunction(torch.autograd.Function):
+                @staticmethod
+                def forward(ctx, a, mesh, grad_tol, max_iters):
+                    mesh.set_activation(a.detach().cpu().numpy())
+                    q, st = mesh.solve(grad_tol=grad_tol, max_iters=max_iters)
+                    if st["status"] != 0:
+                        raise _lib.EmuError(st["status"], "forward solve did not converge")
+                    ctx.mesh = mesh
+                    return q
+
+                @staticmethod
+                def backward(ctx, grad_q):
+                    g = ctx.mesh.solve_grad(grad_q.contiguous())
+                    return torch.as_tensor(g, dtype=torch.float64), None, None, None
+
+            cls._cls = SolveFunction
+        return cls._cls
+
+
+def solve(mesh: "Mesh", a, grad_tol: float = 1e-8, max_iters: int = 10000):
+    """Differentiable equilibrium q(a) (float64 [n,3] on the GPU)."""
+    import torch
+    a = torch.as_tensor(a, dtype=torch.float64)
+    return _SolveFn.get().apply(a, mesh, grad_tol, max_iters)
