@@ -145,9 +145,84 @@ def run(args):
                          "solves_per_s": args.frames / t_all,
                          "latency_ms_p50": float(np.percentile(lat, 50)),
                          "latency_ms_p99": float(np.percentile(lat, 99))}
+    if args.serve > 0:
+        out["serving"] = serving(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args)
     return out
+
+
+def serving(args):
+    """The serving stream: the first ``args.serve`` requests of the seeded
+    Poisson trace (200 req/s, 2k-300k tets log-uniform, 4 groups, random pin
+    pattern) submitted in real time to the continuous-batching server, then the
+    same requests solved one mesh at a time (create, solve, destroy) in arrival
+    order.  Both at the same accuracy (|g| <= serve_rtol |g_0|, at most
+    serve_max_iters iterations, cold start)."""
+    import threading
+    import torch
+    from paper_2006_08821_amd import workloads as wl
+    from paper_2006_08821_amd.emu import Mesh, Server
+
+    trace = wl.serving_trace(n_requests=args.serve)
+    probs = [wl.serving_problem(r["dims"], r["activation"], r["pin_mode"]) for r in trace]
+    opts = dict(grad_tol=0.0, grad_rtol=args.serve_rtol, max_iters=args.serve_max_iters, warm_start=0)
+
+    srv = Server(max_slots=args.serve_slots)
+    tickets = [None] * len(probs)
+    t_start = time.perf_counter()
+
+    def feeder():
+        for k, (r, p) in enumerate(zip(trace, probs)):
+            dt = r["arrival"] - (time.perf_counter() - t_start)
+            if dt > 0:
+                time.sleep(dt)
+            tickets[k] = srv.submit(p, **opts)
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    th.join()
+    res = [srv.wait(t) for t in tickets]
+    rep = srv.report()
+    srv.close()
+    lat = np.array([tm["t_finish"] - tm["t_submit"] for _, _, tm in res]) * 1e3
+    setup = np.array([tm["t_setup_done"] - tm["t_submit"] for _, _, tm in res]) * 1e3
+    queue = np.array([tm["t_admit"] - tm["t_setup_done"] for _, _, tm in res]) * 1e3
+    span = max(tm["t_finish"] for _, _, tm in res) - min(tm["t_submit"] for _, _, tm in res)
+    el_it = sum(p.n_tets * st["iters"] for p, (_, st, _) in zip(probs, res))
+    served = {"requests": len(res), "converged": int(sum(st["status"] == 0 for _, st, _ in res)),
+              "requests_per_s": len(res) / span, "element_iterations_per_s": el_it / span,
+              "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+              "setup_ms_p50": float(np.percentile(setup, 50)), "setup_ms_p99": float(np.percentile(setup, 99)),
+              "queue_ms_p50": float(np.percentile(queue, 50)),
+              "peak_active": rep["peak_active"], "peak_resident_mb": rep["peak_resident_bytes"] / 1e6,
+              "rounds": rep["rounds"]}
+    print(f"[bench] served {len(res)} requests in {span:.2f} s", file=sys.stderr, flush=True)
+
+    # plain: one mesh at a time, in arrival order, same options
+    lat1 = []
+    el_it1 = 0
+    conv1 = 0
+    t_start = time.perf_counter()
+    for r, p in zip(trace, probs):
+        now = time.perf_counter() - t_start
+        if now < r["arrival"]:
+            time.sleep(r["arrival"] - now)
+        mesh = Mesh(p)
+        _, st = mesh.solve(raise_on_error=False, **opts)
+        torch.cuda.synchronize()
+        mesh.close()
+        lat1.append((time.perf_counter() - t_start - r["arrival"]) * 1e3)
+        el_it1 += p.n_tets * st["iters"]
+        conv1 += st["status"] == 0
+    span1 = time.perf_counter() - t_start - trace[0]["arrival"]
+    plain = {"requests": len(trace), "converged": int(conv1), "requests_per_s": len(trace) / span1,
+             "element_iterations_per_s": el_it1 / span1,
+             "latency_ms_p50": float(np.percentile(lat1, 50)), "latency_ms_p99": float(np.percentile(lat1, 99))}
+    print(f"[bench] plain {len(trace)} requests in {span1:.2f} s", file=sys.stderr, flush=True)
+    return {"workload": f"serving trace, first {len(trace)} requests (Poisson 200/s, 2k-300k tets)",
+            "grad_rtol": args.serve_rtol, "max_iters": args.serve_max_iters,
+            "served": served, "plain_one_at_a_time": plain}
 
 
 def cpu_baseline(p, args):
@@ -167,6 +242,20 @@ def cpu_baseline(p, args):
                       f"(fresh ACAP solve per Armijo trial), mesh setup excluded; {dt:.1f} s"}
 
 
+def calibrate_copy(mib):
+    """A plain elementwise copy (y = 1.0 * x, FP64) of known size: under a
+    counter run its FETCH_SIZE / WRITE_SIZE give the factor between the
+    counters and bytes actually moved."""
+    import torch
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(f"[bench] copy calibration: 3 x ({n * 8} B read + {n * 8} B written)", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,12 +268,20 @@ def main():
     ap.add_argument("--profile-reps", type=int, default=20)
     ap.add_argument("--cpu-iters", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", type=int, default=48, help="requests of the serving trace (0: skip)")
+    ap.add_argument("--serve-rtol", type=float, default=1e-4)
+    ap.add_argument("--serve-max-iters", type=int, default=300)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; multi-GPU runs are not supported "
               "(the sharded design is described in the design notes).", file=sys.stderr)
         sys.exit(2)
     out = run(args)
+    if args.calibrate_copy_mib > 0:
+        calibrate_copy(args.calibrate_copy_mib)
     print(json.dumps(out), flush=True)
 
 

@@ -202,6 +202,69 @@ emu_status emu_profile_kernels(emu_mesh* mesh, int32_t reps, double* ms_out, voi
 /* Name of kernel class k (static string), or NULL. */
 const char* emu_kernel_name(int32_t k);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of independent solve requests on one GPU.
+ *
+ * Each request is one quasi-static solve (Sec. 3.2, Algorithm 1) of its own
+ * mesh at its own activations, with the options of emu_solve.  Requests are
+ * set up on host worker threads (ordering, factor, modes; cached by the full
+ * content of the description, pin targets included), admitted in submission
+ * order when a slot is free and the mesh's device block fits the HBM budget
+ * next to every resident mesh, and iterated together: each scheduler round
+ * replays K iterations of all active meshes with one launch per kernel class,
+ * and new requests join between rounds.  A finished request's mesh stays
+ * resident (idle, with its final state) and is reused by a later request with
+ * the same description (warm-started from that state when opts.warm_start is
+ * 1, from rest otherwise); idle meshes are evicted least-recently-used when
+ * the budget needs their memory.  Every mesh runs exactly the kernels and
+ * block partition of emu_solve with fixed-order reductions, so a cold-started
+ * request gives the same bits alone or in any mix.
+ *
+ * Threads: submit / wait / report may be called from any thread.  Times are
+ * seconds since emu_server_create (steady clock).
+ * ---------------------------------------------------------------------- */
+typedef struct emu_server emu_server;
+
+typedef struct {
+  int64_t hbm_budget_bytes;  /* device bytes resident meshes may hold (0 -> 80% of free) */
+  int32_t max_slots;         /* requests iterated concurrently (0 -> 64)          */
+  int32_t setup_threads;     /* host setup workers (0 -> 4)                       */
+  int32_t iters_per_round;   /* iterations per scheduler round (0 -> 16, <= 256)  */
+} emu_server_opts;
+
+typedef struct {
+  double t_submit, t_setup_done, t_admit, t_finish;  /* seconds                  */
+  int64_t device_bytes;      /* device block the request's mesh held             */
+  int32_t setup_cached;      /* 1 if the host setup came from the cache          */
+} emu_request_times;
+
+typedef struct {
+  int64_t peak_resident_bytes;
+  int32_t peak_active;
+  int32_t submitted, completed, failed;
+  int32_t rounds;            /* scheduler rounds that launched work              */
+} emu_server_report;
+
+/* Create a server on the current HIP device.  opts may be NULL (defaults).
+   EMU_E_INVALID for negative options, EMU_E_HIP without a device. */
+emu_status emu_server_create(const emu_server_opts* opts, emu_server** out);
+/* Queue one request; the description's arrays and activation (host,
+   [n_groups]) are copied; opts may be NULL (emu_solve_opts_default).  Writes a
+   ticket.  EMU_E_INVALID for NULL arrays, negative sizes, bad activations or
+   options; mesh validation errors (as emu_create_mesh) and EMU_E_OOM for a
+   mesh whose device block alone exceeds the budget come from emu_server_wait. */
+emu_status emu_server_submit(emu_server* s, const emu_mesh_desc* desc, const double* activation,
+                             const emu_solve_opts* opts, uint64_t* ticket);
+/* Block until the request has finished, then release its ticket.  q_host
+   [n_vertices][3] (user vertex order), stats and times may be NULL.  Returns
+   the request's status (as emu_solve); EMU_E_INVALID for an unknown ticket. */
+emu_status emu_server_wait(emu_server* s, uint64_t ticket, double* q_host, emu_solve_stats* stats,
+                           emu_request_times* times);
+emu_status emu_server_report_get(emu_server* s, emu_server_report* rep);
+/* Finish every queued request, then release the server and all its device
+   memory.  Results not collected by emu_server_wait are discarded. */
+emu_status emu_server_destroy(emu_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -58,6 +58,28 @@ class MeshInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_slots", C.c_int32),
+                ("setup_threads", C.c_int32), ("iters_per_round", C.c_int32)]
+
+
+class RequestTimes(C.Structure):
+    _fields_ = [("t_submit", C.c_double), ("t_setup_done", C.c_double), ("t_admit", C.c_double),
+                ("t_finish", C.c_double), ("device_bytes", C.c_int64), ("setup_cached", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerReport(C.Structure):
+    _fields_ = [("peak_resident_bytes", C.c_int64), ("peak_active", C.c_int32),
+                ("submitted", C.c_int32), ("completed", C.c_int32), ("failed", C.c_int32),
+                ("rounds", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # name -> (restype, argtypes); mirrors the declarations of the two headers
 SIGNATURES = {
     "emu_solve_opts_default": (SolveOpts, []),
@@ -76,6 +98,12 @@ SIGNATURES = {
     "emu_evaluate": (C.c_int, [P, P, P, DP, DP, P, P]),
     "emu_profile_kernels": (C.c_int, [P, C.c_int32, DP, P]),
     "emu_kernel_name": (C.c_char_p, [C.c_int32]),
+    "emu_server_create": (C.c_int, [C.POINTER(ServerOpts), C.POINTER(P)]),
+    "emu_server_submit": (C.c_int, [P, C.POINTER(MeshDesc), DP, C.POINTER(SolveOpts),
+                                    C.POINTER(C.c_uint64)]),
+    "emu_server_wait": (C.c_int, [P, C.c_uint64, DP, C.POINTER(SolveStats), C.POINTER(RequestTimes)]),
+    "emu_server_report_get": (C.c_int, [P, C.POINTER(ServerReport)]),
+    "emu_server_destroy": (C.c_int, [P]),
     "emu_host_setup_create": (C.c_int, [C.POINTER(MeshDesc), C.POINTER(P)]),
     "emu_host_setup_destroy": (C.c_int, [P]),
     "emu_host_setup_info": (C.c_int, [P, C.POINTER(MeshInfo)]),

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libemu.so")
 
 HOST_SRC = ["host_setup.cpp", "api_host.cpp"]
-HIP_SRC = ["kernels.hip", "api.hip"]
+HIP_SRC = ["kernels.hip", "api.hip", "serve.hip"]
 ARCH = os.environ.get("EMU_OFFLOAD_ARCH", "gfx950")
 
 

@@ -9,21 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/emu.h"
-#include "device.hpp"
-#include "host_setup.hpp"
-#include "kernels.hpp"
-
-namespace emu {
-const std::string& last_error_str();
-}
-
-#define HIPCHK(x)                                                                   \
-  do {                                                                              \
-    hipError_t e_ = (x);                                                            \
-    if (e_ != hipSuccess)                                                           \
-      throw emu::Error{EMU_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
-  } while (0)
+#include "mesh_impl.hpp"
 
 namespace {
 
@@ -46,58 +32,6 @@ __global__ void k_from_user_q(const double* in, const int32_t* vold, int n, doub
 
 }  // namespace
 
-struct emu_mesh {
-  emu::HostMesh hm;
-  emu::DevMesh d{};
-  emu::SolvePlan plan;
-  int device = 0;
-  hipStream_t st = nullptr;
-  hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
-  std::vector<void*> allocs;
-  int64_t bytes = 0;
-  int32_t* d_eold = nullptr;
-  int32_t* d_vold = nullptr;
-  emu::Ctl* h_ctl = nullptr;  // pinned host copy
-  hipGraphExec_t gexec = nullptr;
-  hipGraph_t graph = nullptr;
-  int graph_iters = 0;
-  std::vector<double> act;
-  bool converged = false;
-  // backup of the state for emu_evaluate
-  double *R_bak = nullptr, *S_bak = nullptr, *q_bak = nullptr;
-  // adjoint work arrays (allocated on first use)
-  double *a_lam = nullptr, *a_r = nullptr, *a_z = nullptr, *a_p = nullptr, *a_hp = nullptr;
-  double *a_ypart = nullptr, *a_part = nullptr, *a_vin = nullptr, *a_vx = nullptr, *a_el = nullptr;
-
-  template <typename T>
-  T* dalloc(size_t count) {
-    void* p = nullptr;
-    size_t nb = std::max<size_t>(1, count * sizeof(T));
-    hipError_t e = hipMalloc(&p, nb);
-    if (e != hipSuccess) throw emu::Error{EMU_E_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
-    allocs.push_back(p);
-    bytes += (int64_t)nb;
-    return (T*)p;
-  }
-  template <typename T>
-  T* upload(const std::vector<T>& v) {
-    T* p = dalloc<T>(v.size());
-    if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-    return p;
-  }
-  ~emu_mesh() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
-    for (void* p : allocs) (void)hipFree(p);
-    if (h_ctl) (void)hipHostFree(h_ctl);
-    if (ev_a) (void)hipEventDestroy(ev_a);
-    if (ev_b) (void)hipEventDestroy(ev_b);
-    if (ev_t0) (void)hipEventDestroy(ev_t0);
-    if (ev_t1) (void)hipEventDestroy(ev_t1);
-    if (st) (void)hipStreamDestroy(st);
-  }
-};
-
 namespace {
 
 emu_status fail_with(const emu::Error& e) {
@@ -105,13 +39,18 @@ emu_status fail_with(const emu::Error& e) {
   return e.code;
 }
 
-void upload_modes(emu_mesh* M) {
-  const auto& hm = M->hm;
-  std::vector<double> phi((size_t)emu::kMaxK1 * hm.n, 0.0), nu(emu::kMaxK1, 1.0);
+void modes_layout(const emu::HostMesh& hm, std::vector<double>& phi, std::vector<double>& nu) {
+  phi.assign((size_t)emu::kMaxK1 * hm.n, 0.0);
+  nu.assign(emu::kMaxK1, 1.0);
   for (int j = 0; j < hm.k1; ++j) {
     nu[j] = hm.nu[j];
     for (int32_t f = 0; f < hm.nf; ++f) phi[(size_t)emu::kMaxK1 * f + j] = hm.phi[(size_t)j * hm.nf + f];
   }
+}
+
+void upload_modes(emu_mesh* M) {
+  std::vector<double> phi, nu;
+  modes_layout(M->hm, phi, nu);
   HIPCHK(hipMemcpy((void*)M->d.phi, phi.data(), phi.size() * 8, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy((void*)M->d.nu, nu.data(), nu.size() * 8, hipMemcpyHostToDevice));
 }
@@ -122,23 +61,38 @@ void upload_pins(emu_mesh* M) {
   HIPCHK(hipMemcpy((void*)M->d.pin_xyz, hm.pin_xyz.data(), hm.pin_xyz.size() * 8, hipMemcpyHostToDevice));
 }
 
-void build_device(emu_mesh* M) {
-  auto& hm = M->hm;
-  auto& d = M->d;
+// Collects the pieces of a DevImage (256-byte aligned offsets).
+struct ImageBuilder {
+  emu::DevImage& im;
+  template <typename T>
+  void put(size_t slot, const std::vector<T>& v) {
+    add(slot, v.size() * sizeof(T), v.data());
+  }
+  void reserve(size_t slot, size_t bytes) { add(slot, bytes, nullptr); }
+  void add(size_t slot, size_t bytes, const void* src) {
+    emu::DevImage::Piece p;
+    p.slot = slot;
+    p.offset = im.total;
+    p.bytes = std::max<size_t>(1, bytes);
+    if (src && bytes) p.data.assign((const char*)src, (const char*)src + bytes);
+    im.total += (p.bytes + 255) & ~(size_t)255;
+    im.pieces.push_back(std::move(p));
+  }
+};
+#define SLOT(f) offsetof(emu::DevMesh, f)
+
+}  // namespace
+
+std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm) {
+  auto imp = std::make_shared<emu::DevImage>();
+  emu::DevImage& im = *imp;
+  ImageBuilder B{im};
+  auto& d = im.d;
   const int32_t n = hm.n, m = hm.m, nf = hm.nf;
   const auto& fac = hm.fac;
   for (int s = 0; s < fac.ns; ++s)
     if (fac.w[s] > emu::kMaxFrontW)
       throw emu::Error{EMU_E_INVALID, "separator wider than " + std::to_string(emu::kMaxFrontW) + " vertices"};
-  HIPCHK(hipGetDevice(&M->device));
-  HIPCHK(hipStreamCreateWithFlags(&M->st, hipStreamNonBlocking));
-  HIPCHK(hipEventCreateWithFlags(&M->ev_a, hipEventDisableTiming));
-  HIPCHK(hipEventCreateWithFlags(&M->ev_b, hipEventDisableTiming));
-  HIPCHK(hipEventCreate(&M->ev_t0));
-  HIPCHK(hipEventCreate(&M->ev_t1));
-  HIPCHK(hipHostMalloc((void**)&M->h_ctl, sizeof(emu::Ctl), hipHostMallocDefault));
-  std::memset(M->h_ctl, 0, sizeof(emu::Ctl));
-
   d.n = n;
   d.nf = nf;
   d.m = m;
@@ -153,44 +107,50 @@ void build_device(emu_mesh* M) {
 
   // element arrays in internal order (structure of arrays)
   std::vector<int32_t> vid(4 * (size_t)m);
-  std::vector<double> dminv(9 * (size_t)m), vol(m), mu(m), lhat(m), w(m), fib(3 * (size_t)m);
-  std::vector<int32_t> grp(m);
-  for (int32_t e = 0; e < m; ++e) {
-    const int32_t o = hm.eold[e];
-    for (int k = 0; k < 4; ++k) vid[(size_t)k * m + e] = hm.vnew[hm.tets[4 * (size_t)o + k]];
-    for (int k = 0; k < 9; ++k) dminv[(size_t)k * m + e] = hm.dminv[9 * (size_t)o + k];
-    vol[e] = hm.vol[o];
-    mu[e] = hm.mu[o];
-    lhat[e] = hm.lhat[o];
-    w[e] = hm.w[o];
-    for (int c = 0; c < 3; ++c) fib[(size_t)c * m + e] = hm.fiber[3 * (size_t)o + c];
-    grp[e] = hm.group[o];
+  {
+    std::vector<double> dminv(9 * (size_t)m), vol(m), mu(m), lhat(m), w(m), fib(3 * (size_t)m);
+    std::vector<int32_t> grp(m);
+    for (int32_t e = 0; e < m; ++e) {
+      const int32_t o = hm.eold[e];
+      for (int k = 0; k < 4; ++k) vid[(size_t)k * m + e] = hm.vnew[hm.tets[4 * (size_t)o + k]];
+      for (int k = 0; k < 9; ++k) dminv[(size_t)k * m + e] = hm.dminv[9 * (size_t)o + k];
+      vol[e] = hm.vol[o];
+      mu[e] = hm.mu[o];
+      lhat[e] = hm.lhat[o];
+      w[e] = hm.w[o];
+      for (int c = 0; c < 3; ++c) fib[(size_t)c * m + e] = hm.fiber[3 * (size_t)o + c];
+      grp[e] = hm.group[o];
+    }
+    B.put(SLOT(vid), vid);
+    B.put(SLOT(dminv), dminv);
+    B.put(SLOT(vol), vol);
+    B.put(SLOT(mu), mu);
+    B.put(SLOT(lhat), lhat);
+    B.put(SLOT(w), w);
+    B.put(SLOT(fib), fib);
+    B.put(SLOT(grp), grp);
   }
-  d.vid = M->upload(vid);
-  d.dminv = M->upload(dminv);
-  d.vol = M->upload(vol);
-  d.mu = M->upload(mu);
-  d.lhat = M->upload(lhat);
-  d.w = M->upload(w);
-  d.fib = M->upload(fib);
-  d.grp = M->upload(grp);
-  d.R = M->dalloc<double>(9 * (size_t)m);
-  d.S = M->dalloc<double>(6 * (size_t)m);
   const size_t tsz = d.mixed ? 4 : 8;
-  d.gbar = M->dalloc<char>(9 * (size_t)m * tsz);
-  d.Lf = M->dalloc<char>(27 * (size_t)m * tsz);
-  d.p = M->dalloc<double>(9 * (size_t)m);
-  d.contrib = M->dalloc<double>(12 * (size_t)m);
-  std::vector<double> zeros3(3 * (size_t)n, 0.0);
-  d.q = M->upload(zeros3);
-  d.dq = M->upload(zeros3);
-  d.uz = M->upload(zeros3);
-  d.phi = M->dalloc<double>((size_t)emu::kMaxK1 * n);
-  d.nu = M->dalloc<double>(emu::kMaxK1);
-  M->act.assign(std::max(1, hm.ngroups), 0.0);
-  d.act = M->upload(M->act);
-  d.pin_rhs = M->dalloc<double>(3 * (size_t)nf);
-  d.pin_xyz = M->dalloc<double>(3 * (size_t)hm.npins);
+  B.reserve(SLOT(R), 72 * (size_t)m);
+  B.reserve(SLOT(S), 48 * (size_t)m);
+  B.reserve(SLOT(gbar), 9 * (size_t)m * tsz);
+  B.reserve(SLOT(Lf), 27 * (size_t)m * tsz);
+  B.reserve(SLOT(p), 72 * (size_t)m);
+  B.reserve(SLOT(contrib), 96 * (size_t)m);
+  {
+    std::vector<double> zeros3(3 * (size_t)n, 0.0);
+    B.put(SLOT(q), zeros3);
+    B.put(SLOT(dq), zeros3);
+    B.put(SLOT(uz), zeros3);
+    std::vector<double> phi, nu;
+    modes_layout(hm, phi, nu);
+    B.put(SLOT(phi), phi);
+    B.put(SLOT(nu), nu);
+    std::vector<double> act(std::max(1, hm.ngroups), 0.0);
+    B.put(SLOT(act), act);
+    B.put(SLOT(pin_rhs), hm.pin_rhs);
+    B.put(SLOT(pin_xyz), hm.pin_xyz);
+  }
   // incidence of free vertices (fixed element order)
   {
     std::vector<int32_t> cnt(nf + 1, 0);
@@ -207,8 +167,8 @@ void build_device(emu_mesh* M) {
         int32_t v = vid[(size_t)k * m + e];
         if (v < nf) inc[pos[v]++] = 4 * e + k;
       }
-    d.inc_ptr = M->upload(cnt);
-    d.inc = M->upload(inc);
+    B.put(SLOT(inc_ptr), cnt);
+    B.put(SLOT(inc), inc);
   }
   // factor and level schedule
   {
@@ -236,7 +196,7 @@ void build_device(emu_mesh* M) {
       gptr[i + 1] = (int32_t)gsrc.size();
     }
     std::vector<int2> fwd, bwd;
-    auto& pl = M->plan;
+    auto& pl = im.plan;
     pl.nlevels = fac.nlevels;
     pl.fwd_ptr.assign(fac.nlevels + 1, 0);
     pl.bwd_ptr.assign(fac.nlevels + 1, 0);
@@ -252,14 +212,14 @@ void build_device(emu_mesh* M) {
           for (int c = 0; c < fac.w[s]; c += emu::kTriRows) bwd.push_back(make_int2(s, c));
       pl.bwd_ptr[k + 1] = (int)bwd.size();
     }
-    d.sn_col0 = M->upload(fac.col0);
-    d.sn_w = M->upload(fac.w);
-    d.sn_h = M->upload(fac.h);
-    d.sn_rowoff = M->upload(fac.rowoff);
-    d.sn_valoff = M->upload(fac.valoff);
-    d.sn_front = M->upload(front);
-    d.rows = M->upload(fac.rows);
-    d.vals = M->upload(fac.vals);
+    B.put(SLOT(sn_col0), fac.col0);
+    B.put(SLOT(sn_w), fac.w);
+    B.put(SLOT(sn_h), fac.h);
+    B.put(SLOT(sn_rowoff), fac.rowoff);
+    B.put(SLOT(sn_valoff), fac.valoff);
+    B.put(SLOT(sn_front), front);
+    B.put(SLOT(rows), fac.rows);
+    B.put(SLOT(vals), fac.vals);
     {
       // transposed blocks for the backward sweep: row c holds column c of
       // [Linv; M] from row c down (entries r = c .. h-1)
@@ -275,43 +235,68 @@ void build_device(emu_mesh* M) {
             row[r - c] = r < w ? A[r * (r + 1) / 2 + c] : A[tri + (r - w) * w + c];
         }
       }
-      d.tvals = M->upload(tv);
+      B.put(SLOT(tvals), tv);
     }
-    d.gptr = M->upload(gptr);
-    d.gsrc = M->upload(gsrc);
-    d.fwd_items = M->upload(fwd);
-    d.bwd_items = M->upload(bwd);
-    d.rhs = M->dalloc<double>(3 * (size_t)nf);
-    d.ybuf = M->dalloc<double>(3 * (size_t)nf);
-    d.xbuf = M->dalloc<double>(3 * (size_t)nf);
-    d.upd = M->dalloc<double>(3 * (size_t)std::max<int32_t>(1, fac.rowoff[fac.ns]));
+    B.put(SLOT(gptr), gptr);
+    B.put(SLOT(gsrc), gsrc);
+    B.put(SLOT(fwd_items), fwd);
+    B.put(SLOT(bwd_items), bwd);
+    B.reserve(SLOT(rhs), 24 * (size_t)nf);
+    B.reserve(SLOT(ybuf), 24 * (size_t)nf);
+    B.reserve(SLOT(xbuf), 24 * (size_t)nf);
+    B.reserve(SLOT(upd), 24 * (size_t)std::max<int32_t>(1, fac.rowoff[fac.ns]));
   }
-  d.part_e = M->dalloc<double>(2 * (size_t)d.nb);
-  d.part_g = M->dalloc<double>(2 * (size_t)d.nb);
-  d.part_cnt = M->dalloc<int32_t>(2 * (size_t)d.nb);
-  d.part_gram = M->dalloc<double>((size_t)emu::kGramEntries * d.nbg);
-  d.gram = M->dalloc<double>(emu::kGramEntries);
-  {
-    std::vector<double> z(48, 0.0);
-    d.zbuf = M->upload(z);
-  }
-  d.part_ls = M->dalloc<double>(2 * (size_t)emu::kLsTerms * d.nb);
-  d.cfac = M->dalloc<double>(48 * 48);
-  d.cfac_ok = M->dalloc<int32_t>(1);
-  d.ctl = M->dalloc<emu::Ctl>(1);
-  M->d_eold = M->upload(hm.eold);
-  M->d_vold = M->upload(hm.vold);
-  upload_modes(M);
-  upload_pins(M);
+  B.reserve(SLOT(part_e), 16 * (size_t)d.nb);
+  B.reserve(SLOT(part_g), 16 * (size_t)d.nb);
+  B.reserve(SLOT(part_cnt), 8 * (size_t)d.nb);
+  B.reserve(SLOT(part_gram), 8 * (size_t)emu::kGramEntries * d.nbg);
+  B.reserve(SLOT(gram), 8 * (size_t)emu::kGramEntries);
+  B.put(SLOT(zbuf), std::vector<double>(48, 0.0));
+  B.reserve(SLOT(part_ls), 16 * (size_t)emu::kLsTerms * d.nb);
+  B.reserve(SLOT(cfac), 8 * 48 * 48);
+  B.reserve(SLOT(cfac_ok), 4);
+  B.reserve(SLOT(ctl), sizeof(emu::Ctl));
+  B.put(emu::DevImage::kSlotEold, hm.eold);
+  B.put(emu::DevImage::kSlotVold, hm.vold);
+  return imp;
 }
 
-void fresh_solve(emu_mesh* M) {
+void emu::upload_image(emu_mesh* M, std::shared_ptr<const emu::DevImage> img, hipStream_t stream) {
+  HIPCHK(hipGetDevice(&M->device));
+  if (stream) {
+    M->st = stream;
+    M->own_stream = false;
+  } else {
+    HIPCHK(hipStreamCreateWithFlags(&M->st, hipStreamNonBlocking));
+    M->own_stream = true;
+  }
+  HIPCHK(hipEventCreateWithFlags(&M->ev_a, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&M->ev_b, hipEventDisableTiming));
+  HIPCHK(hipEventCreate(&M->ev_t0));
+  HIPCHK(hipEventCreate(&M->ev_t1));
+  HIPCHK(hipHostMalloc((void**)&M->h_ctl, sizeof(emu::Ctl), hipHostMallocDefault));
+  std::memset(M->h_ctl, 0, sizeof(emu::Ctl));
+  char* base = M->dalloc<char>(img->total);
+  M->d = img->d;
+  M->plan = img->plan;
+  for (const auto& p : img->pieces) {
+    char* ptr = base + p.offset;
+    if (p.slot == emu::DevImage::kSlotEold) M->d_eold = (int32_t*)ptr;
+    else if (p.slot == emu::DevImage::kSlotVold) M->d_vold = (int32_t*)ptr;
+    else std::memcpy((char*)&M->d + p.slot, &ptr, sizeof(ptr));
+    if (!p.data.empty()) HIPCHK(hipMemcpyAsync(ptr, p.data.data(), p.data.size(), hipMemcpyHostToDevice, M->st));
+  }
+  M->act.assign(std::max(1, M->hm.ngroups), 0.0);
+  M->img = std::move(img);
+}
+
+void emu::fresh_solve(emu_mesh* M) {
   emu::launch_scatter_F(M->d, M->st);
   emu::launch_solve(M->d, M->plan, 1, M->d.q, 0, M->st);
   emu::launch_set_pins(M->d, M->st);
 }
 
-void init_ctl(emu_mesh* M, const emu_solve_opts& o, int eval_only) {
+void emu::init_ctl(emu_mesh* M, const emu_solve_opts& o, int eval_only) {
   emu::Ctl& c = *M->h_ctl;
   std::memset(&c, 0, sizeof(c));
   c.max_iters = o.max_iters;
@@ -326,6 +311,8 @@ void init_ctl(emu_mesh* M, const emu_solve_opts& o, int eval_only) {
   c.solves = 1;
   HIPCHK(hipMemcpyAsync(M->d.ctl, &c, sizeof(c), hipMemcpyHostToDevice, M->st));
 }
+
+namespace {
 
 void read_ctl(emu_mesh* M) {
   HIPCHK(hipMemcpyAsync(M->h_ctl, M->d.ctl, sizeof(emu::Ctl), hipMemcpyDeviceToHost, M->st));
@@ -354,9 +341,10 @@ void release_user_stream(emu_mesh* M, void* stream) {
   HIPCHK(hipStreamWaitEvent((hipStream_t)stream, M->ev_b, 0));
 }
 
-void fill_stats(emu_mesh* M, emu_solve_stats* s, float ms) {
+}  // namespace
+
+void emu::fill_stats(const emu::Ctl& c, emu_solve_stats* s, float ms) {
   if (!s) return;
-  const emu::Ctl& c = *M->h_ctl;
   s->status = c.status;
   s->iters = c.iter;
   s->ls_trials = c.trials;
@@ -368,6 +356,13 @@ void fill_stats(emu_mesh* M, emu_solve_stats* s, float ms) {
   s->grad_norm0 = std::sqrt(std::max(0.0, c.gnorm0_2));
   s->ms_total = ms;
 }
+
+void emu::launch_to_user_q(emu_mesh* M, double* out) {
+  hipLaunchKernelGGL(k_to_user_q, dim3((M->hm.n + 255) / 256), dim3(256), 0, M->st, M->d.q, M->d_vold, M->hm.n,
+                     out);
+}
+
+namespace {
 
 void backup_state(emu_mesh* M) {
   const size_t m = M->hm.m, n = M->hm.n;
@@ -388,6 +383,9 @@ void restore_state(emu_mesh* M) {
 }
 
 }  // namespace
+
+using emu::fresh_solve;
+using emu::init_ctl;
 
 extern "C" {
 
@@ -418,16 +416,17 @@ emu_status emu_create_mesh(const emu_mesh_desc* desc, emu_mesh** out) {
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
       throw emu::Error{EMU_E_HIP, "no HIP device available"};
-    M = new emu_mesh();
+    M = new emu_mesh(std::make_shared<emu::HostMesh>());
     auto t0 = std::chrono::steady_clock::now();
     emu::host_setup(*desc, M->hm, true);
-    build_device(M);
+    emu::upload_image(M, emu::prepare_image(M->hm), nullptr);
     emu::launch_init_rest(M->d, M->st);
     emu_solve_opts o = emu_solve_opts_default();
     init_ctl(M, o, 0);
     fresh_solve(M);
     HIPCHK(hipStreamSynchronize(M->st));
     HIPCHK(hipGetLastError());
+    M->img.reset();  // the uploaded host copy is no longer needed
     M->hm.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = M;
     return EMU_OK;
@@ -592,7 +591,7 @@ emu_status emu_solve(emu_mesh* M, const emu_solve_opts* opts, double* q_out, emu
     HIPCHK(hipGetLastError());
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, M->ev_t0, M->ev_t1));
-    fill_stats(M, stats, ms);
+    emu::fill_stats(*M->h_ctl, stats, ms);
     release_user_stream(M, stream);
     emu_status st = (emu_status)M->h_ctl->status;
     M->converged = st == EMU_OK;

@@ -18,12 +18,22 @@
 // diagonal blocks (each made positive semi-definite, then + beta I).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.hpp"
 #include "kernels.hpp"
 
 namespace emu {
 
 #define DEV __device__ __forceinline__
+
+// value of v in lane `lane` (uniform) for every lane of the wave
+DEV double bcast_lane(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 constexpr double kRs2 = 0.70710678118654752440;  // 1/sqrt(2)
 
@@ -497,9 +507,9 @@ __global__ void __launch_bounds__(kBlock) k_scatter_F(DevMesh d) {
 
 // right-hand side of the ACAP solve: fixed-order sum of element contributions
 // at each free vertex, plus (optionally) the constant pinned term -L_fp qbar_p
-__global__ void __launch_bounds__(kBlock) k_rhs(DevMesh d, int add_pin, int check_done) {
+DEV void b_rhs(const DevMesh& d, int bid, int add_pin, int check_done) {
   if (check_done && d.ctl->done) return;
-  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  int f = bid * blockDim.x + threadIdx.x;
   if (f >= d.nf) return;
   double acc[3] = {0, 0, 0};
   if (add_pin)
@@ -514,6 +524,7 @@ __global__ void __launch_bounds__(kBlock) k_rhs(DevMesh d, int add_pin, int chec
 #pragma unroll
   for (int c = 0; c < 3; ++c) d.rhs[3 * f + c] = acc[c];
 }
+__global__ void __launch_bounds__(kBlock) k_rhs(DevMesh d, int add_pin, int check_done) { b_rhs(d, blockIdx.x, add_pin, check_done); }
 
 // Packed-row products of the triangular sweeps.  A workgroup (4 waves) owns
 // kTriRows output rows; each wave splits into 8 groups of 8 lanes and a group
@@ -580,10 +591,10 @@ DEV void row_products(const double* __restrict__ V, int64_t base, int w, int h, 
 // Forward sweep of one level.  Work item (s, r0): rows [r0, r0 + kTriRows) of
 // supernode s.  Frontal vector f = [rhs at the columns; 0] + children's update
 // vectors; rows r < w give y = Linv f_top, rows r >= w give u = f_r - M_r f_top.
-__global__ void __launch_bounds__(kBlock) k_fwd(DevMesh d, int it0, int check_done) {
+DEV void b_fwd(const DevMesh& d, int bid, int check_done) {
   if (check_done && d.ctl->done) return;
   __shared__ double ft[kVecChunk * 3];
-  const int2 item = d.fwd_items[it0 + blockIdx.x];
+  const int2 item = d.fwd_items[bid];
   const int s = item.x, r0 = item.y;
   const int w = d.sn_w[s], h = d.sn_h[s], col0 = d.sn_col0[s];
   const int fo = d.sn_front[s];
@@ -637,14 +648,15 @@ __global__ void __launch_bounds__(kBlock) k_fwd(DevMesh d, int it0, int check_do
     }
   }
 }
+__global__ void __launch_bounds__(kBlock) k_fwd(DevMesh d, int it0, int check_done) { b_fwd(d, it0 + (int)blockIdx.x, check_done); }
 
 // Backward sweep of one level with the transposed blocks.  Work item (s, c0):
 // columns [c0, c0 + kTriRows) of supernode s.  With z = [y_s; -x[rows]],
 //   x_c = sum_{r >= c} L^{-T}-block[c][r - c] z[r].
-__global__ void __launch_bounds__(kBlock) k_bwd(DevMesh d, int it0, double* x, int check_done) {
+DEV void b_bwd(const DevMesh& d, int bid, double* x, int check_done) {
   if (check_done && d.ctl->done) return;
   __shared__ double z[kVecChunk * 3];
-  const int2 item = d.bwd_items[it0 + blockIdx.x];
+  const int2 item = d.bwd_items[bid];
   const int s = item.x, c0 = item.y;
   const int w = d.sn_w[s], h = d.sn_h[s], col0 = d.sn_col0[s];
   const int t = threadIdx.x;
@@ -682,6 +694,7 @@ __global__ void __launch_bounds__(kBlock) k_bwd(DevMesh d, int it0, double* x, i
     }
   }
 }
+__global__ void __launch_bounds__(kBlock) k_bwd(DevMesh d, int it0, double* x, int check_done) { b_bwd(d, it0 + (int)blockIdx.x, x, check_done); }
 
 // q = solution at free vertices, pin targets at pinned vertices
 __global__ void __launch_bounds__(kBlock) k_set_pins(DevMesh d) {
@@ -691,13 +704,14 @@ __global__ void __launch_bounds__(kBlock) k_set_pins(DevMesh d) {
   for (int c = 0; c < 3; ++c) d.q[3 * (d.nf + i) + c] = d.pin_xyz[3 * i + c];
 }
 
-__global__ void __launch_bounds__(kBlock) k_add_q(DevMesh d) {
+DEV void b_add_q(const DevMesh& d, int bid) {
   if (d.ctl->done) return;
   const double sg = d.ctl->sigma;
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = bid * blockDim.x + threadIdx.x;
   if (i >= 3 * d.nf) return;
   d.q[i] += sg * d.dq[i];
 }
+__global__ void __launch_bounds__(kBlock) k_add_q(DevMesh d) { b_add_q(d, blockIdx.x); }
 
 // --------------------------------------------------------------- element pass
 // Accept the previous step (if sigma > 0): X = S + sigma D(p), R <- R polar(X),
@@ -705,7 +719,7 @@ __global__ void __launch_bounds__(kBlock) k_add_q(DevMesh d) {
 // G = vol P(F) + beta (F - A) (eq. gradient), the two clamped Hessian blocks
 // + beta I, their Cholesky factors and gbar = H^{-1} g.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_element(DevMesh d) {
+DEV void b_element(const DevMesh& d, int bid) {
   Ctl* ctl = d.ctl;
   if (ctl->done) return;
   __shared__ DD sh[2 * kBlock];
@@ -714,7 +728,7 @@ __global__ void __launch_bounds__(kBlock) k_element(DevMesh d) {
   DD acc[2] = {DD{0, 0}, DD{0, 0}};
   int nclamp = 0, ninv = 0;
   const int m = d.m;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
+  for (int i = bid * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
     Elem e;
     load_elem(d, i, e);
     double R[9], S[9];
@@ -828,14 +842,16 @@ __global__ void __launch_bounds__(kBlock) k_element(DevMesh d) {
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    d.part_e[2 * blockIdx.x] = acc[0].hi;
-    d.part_e[2 * blockIdx.x + 1] = acc[0].lo;
-    d.part_g[2 * blockIdx.x] = acc[1].hi;
-    d.part_g[2 * blockIdx.x + 1] = acc[1].lo;
-    d.part_cnt[2 * blockIdx.x] = shc[0][0];
-    d.part_cnt[2 * blockIdx.x + 1] = shc[1][0];
+    d.part_e[2 * bid] = acc[0].hi;
+    d.part_e[2 * bid + 1] = acc[0].lo;
+    d.part_g[2 * bid] = acc[1].hi;
+    d.part_g[2 * bid + 1] = acc[1].lo;
+    d.part_cnt[2 * bid] = shc[0][0];
+    d.part_cnt[2 * bid + 1] = shc[1][0];
   }
 }
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_element(DevMesh d) { b_element<T>(d, blockIdx.x); }
 
 // --------------------------------------------------------------- Woodbury Gram
 // Per element: Z = T H^{-1} T^T (9x9, F coordinates; T = (R (x) I) Y) and the
@@ -848,7 +864,7 @@ __global__ void __launch_bounds__(kBlock) k_element(DevMesh d) {
 // h = Z_{cc'} gphi_j' for its 4 columns once per element; 12 more threads own
 // 4 entries of y each.  The two groups are added in a fixed order at the end.
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_gram(DevMesh d) {
+DEV void b_gram(const DevMesh& d, int bid) {
   if (d.ctl->done) return;
   constexpr int TE = 32;
   __shared__ T zs[TE][45];
@@ -859,7 +875,7 @@ __global__ void __launch_bounds__(kBlock) k_gram(DevMesh d) {
   const int t = threadIdx.x;
   const int m = d.m;
   const int per = (m + d.nbg - 1) / d.nbg;
-  const int e0 = blockIdx.x * per, e1 = min(m, e0 + per);
+  const int e0 = bid * per, e1 = min(m, e0 + per);
   const int k1 = d.k1;
   const int grp = t >> 7, tl = t & 127;
   const bool gth = tl < 96, yth = tl >= 96 && tl < 108;
@@ -1065,7 +1081,7 @@ __global__ void __launch_bounds__(kBlock) k_gram(DevMesh d) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) comb[tl][4 * a + q] = (double)acc[a][q];
   __syncthreads();
-  double* out = d.part_gram + (int64_t)kGramEntries * blockIdx.x;
+  double* out = d.part_gram + (int64_t)kGramEntries * bid;
   if (grp == 0 && gth) {
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -1077,14 +1093,16 @@ __global__ void __launch_bounds__(kBlock) k_gram(DevMesh d) {
     for (int a = 0; a < 4; ++a) out[1536 + yc * 16 + 4 * yb + a] = (double)acc[0][a] + comb[tl][a];
   }
 }
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gram(DevMesh d) { b_gram<T>(d, blockIdx.x); }
 
 // Partial Gram sums: 16 threads per entry sum interleaved workgroup partials,
 // then add their results in a fixed order.
-__global__ void __launch_bounds__(kBlock) k_gram_reduce(DevMesh d) {
+DEV void b_gram_reduce(const DevMesh& d, int bid) {
   if (d.ctl->done) return;
   __shared__ double sh[16][17];
   const int t = threadIdx.x, part = t >> 4, el = t & 15;
-  const int e = blockIdx.x * 16 + el;
+  const int e = bid * 16 + el;
   double s0 = 0, s1 = 0;
   if (e < kGramEntries) {
     int b = part;
@@ -1103,13 +1121,14 @@ __global__ void __launch_bounds__(kBlock) k_gram_reduce(DevMesh d) {
     d.gram[e] = s;
   }
 }
+__global__ void __launch_bounds__(kBlock) k_gram_reduce(DevMesh d) { b_gram_reduce(d, blockIdx.x); }
 
 // One workgroup: reduce energy / gradient-norm partials, test convergence,
 // build C = Lambda - alpha Gram (3k1 x 3k1) with all threads; then the first
 // wave factors it (Cholesky, lane r owns row r in registers, pivot columns
 // broadcast by lane shuffles) and solves z = C^{-1} y.
 constexpr int kCtlThreads = kBlock;
-__global__ void __launch_bounds__(kCtlThreads) k_control_a(DevMesh d) {
+DEV void b_control_a(const DevMesh& d, int bid) {
   Ctl* ctl = d.ctl;
   if (ctl->done) return;
   __shared__ DD sh[2 * kCtlThreads];
@@ -1237,11 +1256,12 @@ __global__ void __launch_bounds__(kCtlThreads) k_control_a(DevMesh d) {
     d.zbuf[t] = (!bad && j < k1) ? yv[c * k1 + j] : 0.0;
   }
 }
+__global__ void __launch_bounds__(kCtlThreads) k_control_a(DevMesh d) { b_control_a(d, blockIdx.x); }
 
 // uz[v][c] = sum_j z[(c,j)] phi_j(v)  (zero at pinned vertices)
-__global__ void __launch_bounds__(kBlock) k_uz(DevMesh d) {
+DEV void b_uz(const DevMesh& d, int bid) {
   if (d.ctl->done) return;
-  int v = blockIdx.x * kBlock + threadIdx.x;
+  int v = bid * kBlock + threadIdx.x;
   if (v >= d.n) return;
   double a[3] = {0, 0, 0};
   if (d.k1 > 0) {
@@ -1256,11 +1276,12 @@ __global__ void __launch_bounds__(kBlock) k_uz(DevMesh d) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) d.uz[3 * v + c] = a[c];
 }
+__global__ void __launch_bounds__(kBlock) k_uz(DevMesh d) { b_uz(d, blockIdx.x); }
 
 // Direction: d = gbar + alpha H^{-1} B^T z with B^T z = w Y^T vec(R^T G uz);
 // p = -d; g.p = (L^T gbar).(L^T p) per block; contributions of dF = R D(p).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_direction(DevMesh d) {
+DEV void b_direction(const DevMesh& d, int bid) {
   Ctl* ctl = d.ctl;
   if (ctl->done) return;
   __shared__ DD sh[kBlock];
@@ -1268,7 +1289,7 @@ __global__ void __launch_bounds__(kBlock) k_direction(DevMesh d) {
   const int m = d.m;
   const T* Lf = (const T*)d.Lf;
   const T* gbar = (const T*)d.gbar;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
+  for (int i = bid * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
     Elem e;
     load_elem(d, i, e);
     double R[9], Az[9], RA[9];
@@ -1314,14 +1335,16 @@ __global__ void __launch_bounds__(kBlock) k_direction(DevMesh d) {
   }
   block_reduce_dd<1>(acc, sh);
   if (threadIdx.x == 0) {
-    d.part_ls[2 * kLsTerms * blockIdx.x + 12] = acc[0].hi;
-    d.part_ls[2 * kLsTerms * blockIdx.x + 13] = acc[0].lo;
+    d.part_ls[2 * kLsTerms * bid + 12] = acc[0].hi;
+    d.part_ls[2 * kLsTerms * bid + 13] = acc[0].lo;
   }
 }
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_direction(DevMesh d) { b_direction<T>(d, blockIdx.x); }
 
 // Line-search polynomial: E(sigma) - E(0) = sum_k c_k sigma^k (k = 1..6), exact
 // per element along F(sigma) = R (S + sigma D), A(sigma) = A + sigma dA.
-__global__ void __launch_bounds__(kBlock) k_lscoef(DevMesh d) {
+DEV void b_lscoef(const DevMesh& d, int bid) {
   Ctl* ctl = d.ctl;
   if (ctl->done) return;
   __shared__ DD sh[6 * kBlock];
@@ -1329,7 +1352,7 @@ __global__ void __launch_bounds__(kBlock) k_lscoef(DevMesh d) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) acc[k] = DD{0, 0};
   const int m = d.m;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
+  for (int i = bid * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
     Elem e;
     load_elem(d, i, e);
     double R[9], S[9], py[9], D[9], A[9], dA[9], At[9], dAt[9];
@@ -1385,13 +1408,14 @@ __global__ void __launch_bounds__(kBlock) k_lscoef(DevMesh d) {
   if (threadIdx.x == 0)
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      d.part_ls[2 * kLsTerms * blockIdx.x + 2 * k] = acc[k].hi;
-      d.part_ls[2 * kLsTerms * blockIdx.x + 2 * k + 1] = acc[k].lo;
+      d.part_ls[2 * kLsTerms * bid + 2 * k] = acc[k].hi;
+      d.part_ls[2 * kLsTerms * bid + 2 * k + 1] = acc[k].lo;
     }
 }
+__global__ void __launch_bounds__(kBlock) k_lscoef(DevMesh d) { b_lscoef(d, blockIdx.x); }
 
 // Single workgroup: Armijo backtracking on the exact polynomial (Algorithm 1).
-__global__ void __launch_bounds__(kBlock) k_control_b(DevMesh d) {
+DEV void b_control_b(const DevMesh& d, int bid) {
   Ctl* ctl = d.ctl;
   if (ctl->done) return;
   __shared__ DD sh[kLsTerms * kBlock];
@@ -1440,6 +1464,7 @@ __global__ void __launch_bounds__(kBlock) k_control_b(DevMesh d) {
     ctl->done = 1;
   }
 }
+__global__ void __launch_bounds__(kBlock) k_control_b(DevMesh d) { b_control_b(d, blockIdx.x); }
 
 // ------------------------------------------------------------------ adjoint
 // Exact Hessian-vector products and the quasi-Newton preconditioner used by
@@ -1753,6 +1778,42 @@ __global__ void __launch_bounds__(kBlock) k_scale_free(DevMesh d, const double* 
 }
 
 // ------------------------------------------------------------------ launch helpers
+// ------------------------------------------------------- batched iteration
+// One launch per kernel class covers every mesh of a batch: block b runs block
+// map[b].y of mesh map[b].x, with exactly the code and the per-mesh block
+// partition of the single-mesh launch, so each mesh's arithmetic (and every
+// fixed-order reduction) is the same alone or batched.
+#define EMU_BATCHED(NAME, LB, CALL)                                                            \
+  __global__ void __launch_bounds__(LB) NAME(const DevMesh* __restrict__ ms,                   \
+                                             const int2* __restrict__ map) {                   \
+    const int2 e = map[blockIdx.x];                                                            \
+    const DevMesh d = ms[e.x];                                                                 \
+    CALL;                                                                                      \
+  }
+EMU_BATCHED(kb_element64, kBlock, b_element<double>(d, e.y))
+EMU_BATCHED(kb_element32, kBlock, b_element<float>(d, e.y))
+EMU_BATCHED(kb_gram64, kBlock, b_gram<double>(d, e.y))
+EMU_BATCHED(kb_gram32, kBlock, b_gram<float>(d, e.y))
+EMU_BATCHED(kb_gram_reduce, kBlock, b_gram_reduce(d, e.y))
+EMU_BATCHED(kb_control_a, kCtlThreads, b_control_a(d, e.y))
+EMU_BATCHED(kb_uz, kBlock, b_uz(d, e.y))
+EMU_BATCHED(kb_direction64, kBlock, b_direction<double>(d, e.y))
+EMU_BATCHED(kb_direction32, kBlock, b_direction<float>(d, e.y))
+EMU_BATCHED(kb_rhs, kBlock, b_rhs(d, e.y, 0, 1))
+EMU_BATCHED(kb_fwd, kBlock, b_fwd(d, e.y, 1))
+EMU_BATCHED(kb_bwd, kBlock, b_bwd(d, e.y, d.dq, 1))
+EMU_BATCHED(kb_lscoef, kBlock, b_lscoef(d, e.y))
+EMU_BATCHED(kb_control_b, kBlock, b_control_b(d, e.y))
+EMU_BATCHED(kb_add_q, kBlock, b_add_q(d, e.y))
+#undef EMU_BATCHED
+
+// control blocks of every mesh of a batch into one contiguous array
+__global__ void __launch_bounds__(64) kb_gather_ctl(const DevMesh* __restrict__ ms, int32_t* out) {
+  constexpr int W = (int)(sizeof(Ctl) / 4);
+  const int32_t* src = (const int32_t*)ms[blockIdx.x].ctl;
+  for (int t = threadIdx.x; t < W; t += 64) out[(int64_t)W * blockIdx.x + t] = src[t];
+}
+
 static inline int blocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
 void launch_init_rest(const DevMesh& d, hipStream_t st) {
@@ -1899,6 +1960,73 @@ void launch_evaluate(const DevMesh& d, hipStream_t st) {
     hipLaunchKernelGGL(k_direction<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
   else
     hipLaunchKernelGGL(k_direction<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
+}
+
+static inline void launch_map(void (*k)(const DevMesh*, const int2*), const BatchPlan& b, const BatchClass& c,
+                              int threads, hipStream_t st) {
+  if (c.count > 0) hipLaunchKernelGGL(k, dim3(c.count), dim3(threads), 0, st, b.meshes, b.map + c.offset);
+}
+
+void launch_batch_iteration(const BatchPlan& b, hipStream_t st) {
+  if (b.n_meshes == 0) return;
+  launch_map(b.mixed ? kb_element32 : kb_element64, b, b.element, kBlock, st);
+  launch_map(b.mixed ? kb_gram32 : kb_gram64, b, b.gram, kBlock, st);
+  launch_map(kb_gram_reduce, b, b.gram_reduce, kBlock, st);
+  launch_map(kb_control_a, b, b.one, kCtlThreads, st);
+  launch_map(kb_uz, b, b.uz, kBlock, st);
+  launch_map(b.mixed ? kb_direction32 : kb_direction64, b, b.element, kBlock, st);
+  launch_map(kb_rhs, b, b.rhs, kBlock, st);
+  for (const auto& c : b.fwd) launch_map(kb_fwd, b, c, kBlock, st);
+  for (const auto& c : b.bwd) launch_map(kb_bwd, b, c, kBlock, st);
+  launch_map(kb_lscoef, b, b.element, kBlock, st);
+  launch_map(kb_control_b, b, b.one, kBlock, st);
+  launch_map(kb_add_q, b, b.add_q, kBlock, st);
+}
+
+void launch_batch_gather_ctl(const BatchPlan& b, int32_t* out, hipStream_t st) {
+  if (b.n_meshes > 0) hipLaunchKernelGGL(kb_gather_ctl, dim3(b.n_meshes), dim3(64), 0, st, b.meshes, out);
+}
+
+void batch_layout(const std::vector<const DevMesh*>& ms, const std::vector<const SolvePlan*>& plans,
+                  BatchPlan& b, std::vector<int2>& map) {
+  map.clear();
+  const int nm = (int)ms.size();
+  b.n_meshes = nm;
+  auto add = [&](BatchClass& c, auto count_of) {
+    c.offset = (int64_t)map.size();
+    for (int j = 0; j < nm; ++j) {
+      const int cnt = count_of(j);
+      for (int k = 0; k < cnt; ++k) map.push_back(make_int2(j, k));
+    }
+    c.count = (int)((int64_t)map.size() - c.offset);
+  };
+  add(b.element, [&](int j) { return ms[j]->nb; });
+  add(b.gram, [&](int j) { return ms[j]->nbg; });
+  add(b.gram_reduce, [&](int) { return (kGramEntries + 15) / 16; });
+  add(b.one, [&](int) { return 1; });
+  add(b.uz, [&](int j) { return blocks(ms[j]->n); });
+  add(b.rhs, [&](int j) { return blocks(ms[j]->nf); });
+  add(b.add_q, [&](int j) { return blocks(3 * (int64_t)ms[j]->nf); });
+  int nl = 0;
+  for (int j = 0; j < nm; ++j) nl = std::max(nl, plans[j]->nlevels);
+  b.fwd.assign(nl, BatchClass{});
+  b.bwd.assign(nl, BatchClass{});
+  for (int L = 0; L < nl; ++L) {
+    BatchClass& c = b.fwd[L];
+    c.offset = (int64_t)map.size();
+    for (int j = 0; j < nm; ++j)
+      if (L < plans[j]->nlevels)
+        for (int it = plans[j]->fwd_ptr[L]; it < plans[j]->fwd_ptr[L + 1]; ++it) map.push_back(make_int2(j, it));
+    c.count = (int)((int64_t)map.size() - c.offset);
+  }
+  for (int L = 0; L < nl; ++L) {
+    BatchClass& c = b.bwd[L];
+    c.offset = (int64_t)map.size();
+    for (int j = 0; j < nm; ++j)
+      if (L < plans[j]->nlevels)
+        for (int it = plans[j]->bwd_ptr[L]; it < plans[j]->bwd_ptr[L + 1]; ++it) map.push_back(make_int2(j, it));
+    c.count = (int)((int64_t)map.size() - c.offset);
+  }
 }
 
 }  // namespace emu

@@ -22,6 +22,28 @@ struct SolvePlan {
   std::vector<int> fwd_ptr, bwd_ptr;
 };
 
+// Launch layout of one iteration over several meshes (same precision): for
+// each kernel class, `count` blocks whose (mesh, block) pairs start at
+// map[offset].  `meshes` and `map` are device arrays.
+struct BatchClass {
+  int64_t offset = 0;
+  int count = 0;
+};
+struct BatchPlan {
+  int n_meshes = 0;
+  int mixed = 0;
+  const DevMesh* meshes = nullptr;
+  const int2* map = nullptr;
+  BatchClass element, gram, gram_reduce, one, uz, rhs, add_q;
+  std::vector<BatchClass> fwd, bwd;   // per level (forward: leaves first; backward: root first)
+};
+// Host side of the layout (offsets and the map contents to upload).
+void batch_layout(const std::vector<const DevMesh*>& ms, const std::vector<const SolvePlan*>& plans,
+                  BatchPlan& b, std::vector<int2>& map);
+void launch_batch_iteration(const BatchPlan& b, hipStream_t st);
+// copies every mesh's Ctl (as int32 words) to out[j * sizeof(Ctl) / 4 ...]
+void launch_batch_gather_ctl(const BatchPlan& b, int32_t* out, hipStream_t st);
+
 void launch_init_rest(const DevMesh& d, hipStream_t st);
 void launch_set_F(const DevMesh& d, const double* F, const int32_t* eold, hipStream_t st);
 void launch_get_F(const DevMesh& d, double* F, const int32_t* eold, hipStream_t st);

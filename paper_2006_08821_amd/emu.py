@@ -1,4 +1,4 @@
-"""Python front end of the EMU library: meshes, solves, evaluation.
+"""Python front end of the EMU library: meshes, solves, evaluation, serving.
 
 PyTorch is used only for device memory and the current HIP stream; all
 computation runs in libemu.so.
@@ -272,3 +272,64 @@ def solve(mesh: "Mesh", a, grad_tol: float = 1e-8, max_iters: int = 10000):
     import torch
     a = torch.as_tensor(a, dtype=torch.float64)
     return _SolveFn.get().apply(a, mesh, grad_tol, max_iters)
+
+
+class Server:
+    """Continuous-batching solve server on the current HIP device.
+
+    ``submit`` queues one solve (a ``workloads.Problem`` with its activations)
+    and returns a ticket; ``wait`` blocks for its result.  Host setup, HBM
+    admission and the batched iteration all run inside the library."""
+
+    def __init__(self, hbm_budget_bytes=0, max_slots=0, setup_threads=0, iters_per_round=0):
+        _torch()
+        self._lib = _lib.load()
+        o = _lib.ServerOpts(int(hbm_budget_bytes), int(max_slots), int(setup_threads), int(iters_per_round))
+        h = C.c_void_p()
+        check(self._lib.emu_server_create(C.byref(o), C.byref(h)), "emu_server_create")
+        self._h = h
+        self._n = {}
+
+    def submit(self, problem, activation=None, precision="fp64", opts=None, **kw):
+        desc, keep = _desc_arrays(problem, precision=precision)
+        a = np.ascontiguousarray(problem.activation if activation is None else activation, np.float64)
+        if opts is None:
+            opts = default_opts(**kw)
+        t = C.c_uint64()
+        check(self._lib.emu_server_submit(self._h, C.byref(desc), dptr(a), C.byref(opts), C.byref(t)),
+              "emu_server_submit")
+        del keep  # the library copied every array
+        self._n[t.value] = problem.n_vertices
+        return t.value
+
+    def wait(self, ticket, raise_on_error=False):
+        """(q [n,3] numpy, stats dict, times dict); stats['status'] is the
+        request's emu_status (a failed request raises only with
+        ``raise_on_error``)."""
+        n = self._n.pop(ticket, 0)
+        q = np.zeros((n, 3))
+        st = _lib.SolveStats()
+        tm = _lib.RequestTimes()
+        code = self._lib.emu_server_wait(self._h, C.c_uint64(ticket), dptr(q), C.byref(st), C.byref(tm))
+        if code == 1 or (raise_on_error and code != 0):  # EMU_E_INVALID: unknown ticket
+            check(code, "emu_server_wait")
+        stats = st.as_dict()
+        stats["status"] = code
+        return q, stats, tm.as_dict()
+
+    def report(self):
+        r = _lib.ServerReport()
+        check(self._lib.emu_server_report_get(self._h, C.byref(r)))
+        return r.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            code = self._lib.emu_server_destroy(self._h)
+            self._h = None
+            check(code, "emu_server_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
