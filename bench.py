@@ -55,6 +55,24 @@ def algorithmic_bytes(kernel, m, n, nnz, mixed=False):
 GRAM_FLOPS_PER_ELEMENT = 9.6e3   # Z g (9x48x3 MAC) + 1176 x 3 MAC, x2 flops
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/*.md: FETCH_SIZE and WRITE_SIZE passes scaled by a plain copy
+    kernel), or None when the summary was taken on a different kernel source."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2006_08821_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        lines = open(f).read().splitlines()
+        if f"kernels.hip sha256: {sha}" not in lines:
+            continue
+        for ln in lines:
+            if ln.startswith(f"traffic: kernel={kernel} "):
+                return float(ln.split("bytes=")[1].split()[0])
+    return None
+
+
 def run(args):
     import torch
     from paper_2006_08821_amd import workloads as wl
@@ -92,12 +110,12 @@ def run(args):
         flops = GRAM_FLOPS_PER_ELEMENT * m
         ach = flops / (prof[dom] * 1e-3) / 1e12
         roof = dict(bound="alu", kernel=dom, achieved=ach, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=ach / FP64_PEAK_TFLOPS, traffic=None, ms=prof[dom])
+                    frac=ach / FP64_PEAK_TFLOPS, traffic=measured_traffic(dom), ms=prof[dom])
     else:
         b = algorithmic_bytes(dom, m, n, nnz)
         ach = b / (prof[dom] * 1e-3) / 1e9
         roof = dict(bound="hbm", kernel=dom, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=ach / HBM_PEAK_GBS, traffic=None, ms=prof[dom])
+                    frac=ach / HBM_PEAK_GBS, traffic=measured_traffic(dom), ms=prof[dom])
     value = m * main["iters"] / main["dt"]
     out = {
         "metric": "element-iterations/s",

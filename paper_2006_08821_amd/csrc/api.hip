@@ -135,7 +135,7 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
   B.reserve(SLOT(S), 48 * (size_t)m);
   B.reserve(SLOT(gbar), 9 * (size_t)m * tsz);
   B.reserve(SLOT(Lf), 27 * (size_t)m * tsz);
-  B.reserve(SLOT(p), 72 * (size_t)m);
+  B.put(SLOT(p), std::vector<double>(9 * (size_t)m, 0.0));
   B.reserve(SLOT(contrib), 96 * (size_t)m);
   {
     std::vector<double> zeros3(3 * (size_t)n, 0.0);
@@ -200,16 +200,32 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
     pl.nlevels = fac.nlevels;
     pl.fwd_ptr.assign(fac.nlevels + 1, 0);
     pl.bwd_ptr.assign(fac.nlevels + 1, 0);
-    for (int L = 0; L < fac.nlevels; ++L) {
+    // Levels with few work items at 32 rows per item split the supernodes
+    // with long rows into items of 8 rows (32 lanes per row) instead.
+    auto sparse_level = [&](int L, bool fwd_dir) {
+      int64_t items = 0;
       for (int s = 0; s < fac.ns; ++s)
-        if (fac.level[s] == L)
-          for (int r = 0; r < fac.h[s]; r += emu::kTriRows) fwd.push_back(make_int2(s, r));
+        if (fac.level[s] == L) items += ((fwd_dir ? fac.h[s] : fac.w[s]) + 31) / 32;
+      return items < emu::kWideLevelItems;
+    };
+    for (int L = 0; L < fac.nlevels; ++L) {
+      const bool sparse = sparse_level(L, true);
+      for (int s = 0; s < fac.ns; ++s)
+        if (fac.level[s] == L) {
+          const bool wide = sparse && fac.w[s] >= emu::kWideRowMin;
+          const int step = wide ? 8 : 32;
+          for (int r = 0; r < fac.h[s]; r += step) fwd.push_back(make_int2(s, r | (wide ? emu::kItemWideBit : 0)));
+        }
       pl.fwd_ptr[L + 1] = (int)fwd.size();
     }
     for (int L = fac.nlevels - 1, k = 0; L >= 0; --L, ++k) {
+      const bool sparse = sparse_level(L, false);
       for (int s = 0; s < fac.ns; ++s)
-        if (fac.level[s] == L)
-          for (int c = 0; c < fac.w[s]; c += emu::kTriRows) bwd.push_back(make_int2(s, c));
+        if (fac.level[s] == L) {
+          const bool wide = sparse && fac.h[s] >= emu::kWideRowMin;
+          const int step = wide ? 8 : 32;
+          for (int c = 0; c < fac.w[s]; c += step) bwd.push_back(make_int2(s, c | (wide ? emu::kItemWideBit : 0)));
+        }
       pl.bwd_ptr[k + 1] = (int)bwd.size();
     }
     B.put(SLOT(sn_col0), fac.col0);
@@ -695,6 +711,10 @@ emu_status emu_profile_kernels(emu_mesh* M, int32_t reps, double* ms_out, void* 
     for (int k = 0; k < EMU_NUM_KERNELS; ++k) {
       for (int r = 0; r < reps; ++r) {
         init_ctl(M, o, 1);
+        // a tiny accepted step, so that the element pass times its accept path
+        // (polar re-split) as it runs inside an iteration
+        M->h_ctl->sigma = 1e-12;
+        HIPCHK(hipMemcpyAsync(M->d.ctl, M->h_ctl, sizeof(emu::Ctl), hipMemcpyHostToDevice, M->st));
         HIPCHK(hipEventRecord(ev[2 * r], M->st));
         emu::launch_class(k, M->d, M->plan, M->st);
         HIPCHK(hipEventRecord(ev[2 * r + 1], M->st));

@@ -11,7 +11,13 @@ constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kMaxK1 = 16;         // scalar low-rank modes (k = 3 * k1 <= 48)
 constexpr int kGramEntries = 6 * 256 + 48;   // 6 coordinate-pair 16x16 blocks + y
 constexpr int kLsTerms = 7;        // 6 polynomial coefficients + g.p
-constexpr int kTriRows = 32;       // rows (forward) / columns (backward) per work item
+// Triangular-sweep work items: 32 rows (8 lanes per row) or, flagged by
+// kItemWideBit in the first row, 8 rows (32 lanes per row).  Items of a level
+// with fewer than kWideLevelItems 32-row items use the wide form for
+// supernodes whose rows are at least kWideRowMin long.
+constexpr int kItemWideBit = 1 << 30;
+constexpr int kWideLevelItems = 1024;
+constexpr int kWideRowMin = 64;
 constexpr int kMaxFrontW = 2048;   // largest supernode width held in LDS
 
 // Iteration control block (device memory, one per mesh).

@@ -527,82 +527,83 @@ DEV void b_rhs(const DevMesh& d, int bid, int add_pin, int check_done) {
 __global__ void __launch_bounds__(kBlock) k_rhs(DevMesh d, int add_pin, int check_done) { b_rhs(d, blockIdx.x, add_pin, check_done); }
 
 // Packed-row products of the triangular sweeps.  A workgroup (4 waves) owns
-// kTriRows output rows; each wave splits into 8 groups of 8 lanes and a group
-// computes one row at a time: lanes stride the packed row (8 consecutive
-// doubles per step, 4 steps in flight), then reduce within the group.  The
-// vector the rows multiply lives in LDS, loaded in chunks of kVecChunk.
+// 256 / LPR output rows; each wave splits into 64 / LPR groups of LPR lanes and
+// a group computes one row: lanes stride the packed row (LPR consecutive
+// doubles per step, 4 steps in flight), then reduce within the group.  Work
+// items of supernodes with long rows on sparse levels use LPR = 32 (8 rows per
+// workgroup) so that the few supernodes near the root still spread over many
+// compute units; the rest use LPR = 8 (32 rows).  The vector the rows multiply
+// lives in LDS, loaded in chunks of kVecChunk.
 constexpr int kVecChunk = 2048;
 
-template <bool kFwd>
+template <bool kFwd, int LPR>
 DEV void row_products(const double* __restrict__ V, int64_t base, int w, int h, int r0, int nrows,
-                      const double* vec, int vbase, int vlen, double (&acc)[kTriRows / 32][3]) {
+                      const double* vec, int vbase, int vlen, double (&acc)[3]) {
+  constexpr int G = 64 / LPR;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int g = lane >> 3, l = lane & 7;
-#pragma unroll
-  for (int k = 0; k < kTriRows / 32; ++k) {
-    const int rr = (k * 4 + wave) * 8 + g;  // row handled by this group in round k
-    const int r = r0 + rr;
-    double a0 = 0, a1 = 0, a2 = 0;
-    if (rr < nrows) {
-      // forward: row r has length (r < w ? r+1 : w), starts at column 0
-      // backward: row r (a column of L) covers vector entries [r, h)
-      int64_t roff;
-      int lo, hi;
-      if (kFwd) {
-        roff = r < w ? (int64_t)r * (r + 1) / 2 : (int64_t)w * (w + 1) / 2 + (int64_t)(r - w) * w;
-        lo = 0;
-        hi = r < w ? r + 1 : w;
-      } else {
-        roff = (int64_t)r * h - (int64_t)r * (r - 1) / 2;
-        lo = r;
-        hi = h;
-      }
-      // intersect with the vector chunk [vbase, vbase + vlen)
-      const int c0 = max(lo, vbase), c1 = min(hi, vbase + vlen);
-      const double* row = V + base + roff - lo;
-      int c = c0 + l;
-      for (; c + 24 < c1; c += 32) {
-        const double x0 = row[c], x1 = row[c + 8], x2 = row[c + 16], x3 = row[c + 24];
-        const double* v0 = vec + 3 * (c - vbase);
-        a0 += x0 * v0[0] + x1 * v0[24] + x2 * v0[48] + x3 * v0[72];
-        a1 += x0 * v0[1] + x1 * v0[25] + x2 * v0[49] + x3 * v0[73];
-        a2 += x0 * v0[2] + x1 * v0[26] + x2 * v0[50] + x3 * v0[74];
-      }
-      for (; c < c1; c += 8) {
-        const double x0 = row[c];
-        const double* v0 = vec + 3 * (c - vbase);
-        a0 += x0 * v0[0];
-        a1 += x0 * v0[1];
-        a2 += x0 * v0[2];
-      }
+  const int g = lane / LPR, l = lane % LPR;
+  const int rr = wave * G + g;  // row handled by this group
+  const int r = r0 + rr;
+  double a0 = 0, a1 = 0, a2 = 0;
+  if (rr < nrows) {
+    // forward: row r has length (r < w ? r+1 : w), starts at column 0
+    // backward: row r (a column of L) covers vector entries [r, h)
+    int64_t roff;
+    int lo, hi;
+    if (kFwd) {
+      roff = r < w ? (int64_t)r * (r + 1) / 2 : (int64_t)w * (w + 1) / 2 + (int64_t)(r - w) * w;
+      lo = 0;
+      hi = r < w ? r + 1 : w;
+    } else {
+      roff = (int64_t)r * h - (int64_t)r * (r - 1) / 2;
+      lo = r;
+      hi = h;
     }
-#pragma unroll
-    for (int off = 4; off > 0; off >>= 1) {
-      a0 += __shfl_xor(a0, off);
-      a1 += __shfl_xor(a1, off);
-      a2 += __shfl_xor(a2, off);
+    // intersect with the vector chunk [vbase, vbase + vlen)
+    const int c0 = max(lo, vbase), c1 = min(hi, vbase + vlen);
+    const double* row = V + base + roff - lo;
+    int c = c0 + l;
+    for (; c + 3 * LPR < c1; c += 4 * LPR) {
+      const double x0 = row[c], x1 = row[c + LPR], x2 = row[c + 2 * LPR], x3 = row[c + 3 * LPR];
+      const double* v0 = vec + 3 * (c - vbase);
+      a0 += x0 * v0[0] + x1 * v0[3 * LPR] + x2 * v0[6 * LPR] + x3 * v0[9 * LPR];
+      a1 += x0 * v0[1] + x1 * v0[3 * LPR + 1] + x2 * v0[6 * LPR + 1] + x3 * v0[9 * LPR + 1];
+      a2 += x0 * v0[2] + x1 * v0[3 * LPR + 2] + x2 * v0[6 * LPR + 2] + x3 * v0[9 * LPR + 2];
     }
-    acc[k][0] += a0;
-    acc[k][1] += a1;
-    acc[k][2] += a2;
+    for (; c < c1; c += LPR) {
+      const double x0 = row[c];
+      const double* v0 = vec + 3 * (c - vbase);
+      a0 += x0 * v0[0];
+      a1 += x0 * v0[1];
+      a2 += x0 * v0[2];
+    }
   }
+#pragma unroll
+  for (int off = LPR / 2; off > 0; off >>= 1) {
+    a0 += __shfl_xor(a0, off);
+    a1 += __shfl_xor(a1, off);
+    a2 += __shfl_xor(a2, off);
+  }
+  acc[0] += a0;
+  acc[1] += a1;
+  acc[2] += a2;
 }
 
-// Forward sweep of one level.  Work item (s, r0): rows [r0, r0 + kTriRows) of
+// Work items carry the lanes-per-row choice in bit 30 of their first row.
+constexpr int kItemWide = kItemWideBit;
+
+// Forward sweep of one level.  Work item (s, r0): rows [r0, r0 + 256/LPR) of
 // supernode s.  Frontal vector f = [rhs at the columns; 0] + children's update
 // vectors; rows r < w give y = Linv f_top, rows r >= w give u = f_r - M_r f_top.
-DEV void b_fwd(const DevMesh& d, int bid, int check_done) {
-  if (check_done && d.ctl->done) return;
-  __shared__ double ft[kVecChunk * 3];
-  const int2 item = d.fwd_items[bid];
-  const int s = item.x, r0 = item.y;
+template <int LPR>
+DEV void fwd_item(const DevMesh& d, int s, int r0, double* ft) {
   const int w = d.sn_w[s], h = d.sn_h[s], col0 = d.sn_col0[s];
   const int fo = d.sn_front[s];
   const int t = threadIdx.x;
-  const int nrows = min(kTriRows, h - r0);
+  const int nrows = min(256 / LPR, h - r0);
   // the rows of this item need f_top entries [0, min(w, r0 + nrows))
   const int need = min(w, r0 + nrows);
-  double acc[kTriRows / 32][3] = {};
+  double acc[3] = {0, 0, 0};
   for (int vb = 0; vb < need; vb += kVecChunk) {
     const int vl = min(kVecChunk, need - vb);
     __syncthreads();
@@ -620,49 +621,50 @@ DEV void b_fwd(const DevMesh& d, int bid, int check_done) {
       ft[3 * k + 2] = a2;
     }
     __syncthreads();
-    row_products<true>(d.vals, d.sn_valoff[s], w, h, r0, nrows, ft, vb, vl, acc);
+    row_products<true, LPR>(d.vals, d.sn_valoff[s], w, h, r0, nrows, ft, vb, vl, acc);
   }
-  const int lane = t & 63, wave = t >> 6, g = lane >> 3, l = lane & 7;
-#pragma unroll
-  for (int k = 0; k < kTriRows / 32; ++k) {
-    const int rr = (k * 4 + wave) * 8 + g;
-    const int r = r0 + rr;
-    if (l == 0 && rr < nrows) {
-      if (r < w) {
-        d.ybuf[3 * (col0 + r)] = acc[k][0];
-        d.ybuf[3 * (col0 + r) + 1] = acc[k][1];
-        d.ybuf[3 * (col0 + r) + 2] = acc[k][2];
-      } else {
-        double b0 = 0, b1 = 0, b2 = 0;
-        for (int q = d.gptr[fo + r]; q < d.gptr[fo + r + 1]; ++q) {
-          const double* u = d.upd + 3 * (int64_t)d.gsrc[q];
-          b0 += u[0];
-          b1 += u[1];
-          b2 += u[2];
-        }
-        double* o = d.upd + 3 * (int64_t)(d.sn_rowoff[s] + r - w);
-        o[0] = b0 - acc[k][0];
-        o[1] = b1 - acc[k][1];
-        o[2] = b2 - acc[k][2];
+  const int lane = t & 63, wave = t >> 6, g = lane / LPR, l = lane % LPR;
+  const int rr = wave * (64 / LPR) + g;
+  const int r = r0 + rr;
+  if (l == 0 && rr < nrows) {
+    if (r < w) {
+      d.ybuf[3 * (col0 + r)] = acc[0];
+      d.ybuf[3 * (col0 + r) + 1] = acc[1];
+      d.ybuf[3 * (col0 + r) + 2] = acc[2];
+    } else {
+      double b0 = 0, b1 = 0, b2 = 0;
+      for (int q = d.gptr[fo + r]; q < d.gptr[fo + r + 1]; ++q) {
+        const double* u = d.upd + 3 * (int64_t)d.gsrc[q];
+        b0 += u[0];
+        b1 += u[1];
+        b2 += u[2];
       }
+      double* o = d.upd + 3 * (int64_t)(d.sn_rowoff[s] + r - w);
+      o[0] = b0 - acc[0];
+      o[1] = b1 - acc[1];
+      o[2] = b2 - acc[2];
     }
   }
+}
+DEV void b_fwd(const DevMesh& d, int bid, int check_done) {
+  if (check_done && d.ctl->done) return;
+  __shared__ double ft[kVecChunk * 3];
+  const int2 item = d.fwd_items[bid];
+  if (item.y & kItemWide) fwd_item<32>(d, item.x, item.y & ~kItemWide, ft);
+  else fwd_item<8>(d, item.x, item.y, ft);
 }
 __global__ void __launch_bounds__(kBlock) k_fwd(DevMesh d, int it0, int check_done) { b_fwd(d, it0 + (int)blockIdx.x, check_done); }
 
 // Backward sweep of one level with the transposed blocks.  Work item (s, c0):
-// columns [c0, c0 + kTriRows) of supernode s.  With z = [y_s; -x[rows]],
+// columns [c0, c0 + 256/LPR) of supernode s.  With z = [y_s; -x[rows]],
 //   x_c = sum_{r >= c} L^{-T}-block[c][r - c] z[r].
-DEV void b_bwd(const DevMesh& d, int bid, double* x, int check_done) {
-  if (check_done && d.ctl->done) return;
-  __shared__ double z[kVecChunk * 3];
-  const int2 item = d.bwd_items[bid];
-  const int s = item.x, c0 = item.y;
+template <int LPR>
+DEV void bwd_item(const DevMesh& d, int s, int c0, double* x, double* z) {
   const int w = d.sn_w[s], h = d.sn_h[s], col0 = d.sn_col0[s];
   const int t = threadIdx.x;
-  const int ncols = min(kTriRows, w - c0);
+  const int ncols = min(256 / LPR, w - c0);
   const int32_t* rows = d.rows + d.sn_rowoff[s];
-  double acc[kTriRows / 32][3] = {};
+  double acc[3] = {0, 0, 0};
   for (int vb = c0; vb < h; vb += kVecChunk) {
     const int vl = min(kVecChunk, h - vb);
     __syncthreads();
@@ -680,19 +682,23 @@ DEV void b_bwd(const DevMesh& d, int bid, double* x, int check_done) {
       }
     }
     __syncthreads();
-    row_products<false>(d.tvals, d.sn_valoff[s], w, h, c0, ncols, z, vb, vl, acc);
+    row_products<false, LPR>(d.tvals, d.sn_valoff[s], w, h, c0, ncols, z, vb, vl, acc);
   }
-  const int lane = t & 63, wave = t >> 6, g = lane >> 3, l = lane & 7;
-#pragma unroll
-  for (int k = 0; k < kTriRows / 32; ++k) {
-    const int cc = (k * 4 + wave) * 8 + g;
-    if (l == 0 && cc < ncols) {
-      const int c = c0 + cc;
-      x[3 * (col0 + c)] = acc[k][0];
-      x[3 * (col0 + c) + 1] = acc[k][1];
-      x[3 * (col0 + c) + 2] = acc[k][2];
-    }
+  const int lane = t & 63, wave = t >> 6, g = lane / LPR, l = lane % LPR;
+  const int cc = wave * (64 / LPR) + g;
+  if (l == 0 && cc < ncols) {
+    const int c = c0 + cc;
+    x[3 * (col0 + c)] = acc[0];
+    x[3 * (col0 + c) + 1] = acc[1];
+    x[3 * (col0 + c) + 2] = acc[2];
   }
+}
+DEV void b_bwd(const DevMesh& d, int bid, double* x, int check_done) {
+  if (check_done && d.ctl->done) return;
+  __shared__ double z[kVecChunk * 3];
+  const int2 item = d.bwd_items[bid];
+  if (item.y & kItemWide) bwd_item<32>(d, item.x, item.y & ~kItemWide, x, z);
+  else bwd_item<8>(d, item.x, item.y, x, z);
 }
 __global__ void __launch_bounds__(kBlock) k_bwd(DevMesh d, int it0, double* x, int check_done) { b_bwd(d, it0 + (int)blockIdx.x, x, check_done); }
 
@@ -858,239 +864,255 @@ __global__ void __launch_bounds__(kBlock) k_element(DevMesh d) { b_element<T>(d,
 // mode gradients gphi_j = sum_v phi_j(v) b_v.  Accumulates, per workgroup,
 //   Gram[(c,j),(c',j')] += w^2 gphi_j^T Z_{cc'} gphi_j'   (6 pairs c <= c')
 //   y[(c,j)]            += w (R D(gbar) gphi_j)[c]
-// A tile of 32 elements is staged in LDS (one thread per element builds Z).
-// Two groups of 128 threads then take alternate elements; in a group, thread
-// (pair, jb, qb) owns a 4x4 register tile of one 16x16 pair block and forms
-// h = Z_{cc'} gphi_j' for its 4 columns once per element; 12 more threads own
-// 4 entries of y each.  The two groups are added in a fixed order at the end.
+// Each wave owns a contiguous run of elements.  Phase A: one lane per element
+// (batches of kGramBatch) forms the six 3x3 coordinate-pair blocks of Z, R D(gbar)
+// and w into the wave's LDS rows.  Phase B, per element: lane (j, k) = (l % 16,
+// l / 16) computes gphi_j (all 3 components), and for each pair one 16x16x4
+// matrix-core product accumulates A = w^2 gphi[j][k] (k < 3, else 0) against
+// B = (Z_{cc'} gphi_j)[k], i.e. the 16x16 pair block.  Waves are added in a
+// fixed order at the end.
+constexpr int kGramBatch = 32;
+constexpr int kGramRow = 65;  // 54 block entries + 9 + 1, padded to an odd stride
+
+template <typename T>
+struct MfmaAcc;
+// 16x16x4 products; A[i][k] comes from lane i + 16 k, B[k][j] from lane j + 16 k,
+// and register r of lane l holds D[row(l, r)][l % 16] (the FP64 and FP32
+// forms distribute the rows differently).
+template <>
+struct MfmaAcc<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static DEV v4 mma(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static DEV int row(int l, int r) { return 4 * r + (l >> 4); }
+};
+template <>
+struct MfmaAcc<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static DEV v4 mma(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static DEV int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+
+// Z blocks of one element (phase A): zr[p * 9 + a * 3 + b] = Z[3c + a][3c' + b]
+// for the pairs p = (0,0) (0,1) (0,2) (1,1) (1,2) (2,2).
+template <typename T>
+DEV void gram_zblocks(const DevMesh& d, int i, T* zr) {
+  const int m = d.m;
+  T R[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) R[k] = (T)d.R[k * m + i];
+  const T* Lf = (const T*)d.Lf;
+  // explicit block inverses H^{-1} = L^{-T} L^{-1} (6x6 and 3x3, packed lower)
+  T Hs[21], Hk[6];
+  {
+    T Ls[21], Li[21];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) Ls[k] = Lf[k * m + i];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      Li[c * (c + 1) / 2 + c] = T(1) / Ls[c * (c + 1) / 2 + c];
+#pragma unroll
+      for (int r = c + 1; r < 6; ++r) {
+        T v = 0;
+#pragma unroll
+        for (int k = c; k < r; ++k) v += Ls[r * (r + 1) / 2 + k] * Li[k * (k + 1) / 2 + c];
+        Li[r * (r + 1) / 2 + c] = -v / Ls[r * (r + 1) / 2 + r];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+      for (int c = 0; c <= r; ++c) {
+        T v = 0;
+#pragma unroll
+        for (int k = r; k < 6; ++k) v += Li[k * (k + 1) / 2 + r] * Li[k * (k + 1) / 2 + c];
+        Hs[r * (r + 1) / 2 + c] = v;
+      }
+    T Lk[6], Lki[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Lk[k] = Lf[(21 + k) * m + i];
+    Lki[0] = T(1) / Lk[0];
+    Lki[2] = T(1) / Lk[2];
+    Lki[5] = T(1) / Lk[5];
+    Lki[1] = -Lk[1] * Lki[0] * Lki[2];
+    Lki[4] = -Lk[4] * Lki[2] * Lki[5];
+    Lki[3] = -(Lk[3] * Lki[0] + Lk[4] * Lki[1]) * Lki[5];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c <= r; ++c) {
+        T v = 0;
+#pragma unroll
+        for (int k = r; k < 3; ++k) v += Lki[k * (k + 1) / 2 + r] * Lki[k * (k + 1) / 2 + c];
+        Hk[r * (r + 1) / 2 + c] = v;
+      }
+  }
+  // per gradient-direction pair (dd <= dp): M[e][e'] = (Y H^{-1} Y^T)[(e,dd),(e',dp)],
+  // then Z[(c,dd),(c',dp)] = (R M R^T)[c][c'], stored in the block of (min, max)(c, c')
+#pragma unroll
+  for (int dd = 0; dd < 3; ++dd)
+#pragma unroll
+    for (int dp = dd; dp < 3; ++dp) {
+      T Mx[3][3];
+#pragma unroll
+      for (int e = 0; e < 3; ++e)
+#pragma unroll
+        for (int ep = 0; ep < 3; ++ep) {
+          const int A = 3 * e + dd, B = 3 * ep + dp;
+          T v = 0;
+#pragma unroll
+          for (int pa = 0; pa < 2; ++pa)
+#pragma unroll
+            for (int pb = 0; pb < 2; ++pb) {
+              const int ya = kYof[A][pa], yb = kYof[B][pb];
+              if (ya >= 0 && yb >= 0 && (ya < 6) == (yb < 6)) {
+                const T cv = T(kYvf[A][pa] * kYvf[B][pb]);
+                if (ya < 6) {
+                  const int lo = ya < yb ? ya : yb, hi = ya < yb ? yb : ya;
+                  v += cv * Hs[hi * (hi + 1) / 2 + lo];
+                } else {
+                  const int lo = (ya < yb ? ya : yb) - 6, hi = (ya < yb ? yb : ya) - 6;
+                  v += cv * Hk[hi * (hi + 1) / 2 + lo];
+                }
+              }
+            }
+          Mx[e][ep] = v;
+        }
+      T RM[3][3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int ep = 0; ep < 3; ++ep)
+          RM[c][ep] = R[3 * c] * Mx[0][ep] + R[3 * c + 1] * Mx[1][ep] + R[3 * c + 2] * Mx[2][ep];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int cp = 0; cp < 3; ++cp) {
+          if (dd == dp && cp < c) continue;
+          const T v = RM[c][0] * R[3 * cp] + RM[c][1] * R[3 * cp + 1] + RM[c][2] * R[3 * cp + 2];
+          // v = Z[3c + dd][3cp + dp]
+          if (c <= cp) {
+            const int p = c == 0 ? cp : (c == 1 ? 2 + cp : 5);
+            zr[p * 9 + dd * 3 + dp] = v;
+            if (dd != dp && c == cp) zr[p * 9 + dp * 3 + dd] = v;
+          } else {
+            const int p = cp == 0 ? c : (cp == 1 ? 2 + c : 5);
+            zr[p * 9 + dp * 3 + dd] = v;
+          }
+        }
+    }
+}
+
 template <typename T>
 DEV void b_gram(const DevMesh& d, int bid) {
   if (d.ctl->done) return;
-  constexpr int TE = 32;
-  __shared__ T zs[TE][45];
-  __shared__ T gp[TE][kMaxK1][3];
-  __shared__ T fg[TE][9];
-  __shared__ T ws[TE];
-  __shared__ double comb[108][16];
-  const int t = threadIdx.x;
+  typedef typename MfmaAcc<T>::v4 v4;
+  // wave tiles of phase A, reused for the final combination of the waves
+  constexpr size_t kTileBytes = sizeof(T) * (kBlock / 64) * kGramBatch * kGramRow;
+  constexpr size_t kCombBytes = sizeof(double) * 3 * 64 * 25;
+  __shared__ double sbuf[((kTileBytes > kCombBytes ? kTileBytes : kCombBytes) + 7) / 8];
+  T(*zl)[kGramBatch][kGramRow] = reinterpret_cast<T(*)[kGramBatch][kGramRow]>(sbuf);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int m = d.m;
   const int per = (m + d.nbg - 1) / d.nbg;
   const int e0 = bid * per, e1 = min(m, e0 + per);
+  const int perw = (per + 3) / 4;
+  const int w0 = min(e1, e0 + wave * perw), w1 = min(e1, w0 + perw);
   const int k1 = d.k1;
-  const int grp = t >> 7, tl = t & 127;
-  const bool gth = tl < 96, yth = tl >= 96 && tl < 108;
-  const int pair = tl >> 4, jb = (tl & 15) >> 2, qb = tl & 3;
-  const int pc = pair < 3 ? 0 : (pair < 5 ? 1 : 2);
-  const int pcp = pair < 3 ? pair : (pair < 5 ? pair - 2 : 2);
-  const int yc = (tl - 96) >> 2, yb = (tl - 96) & 3;
-  int zoff[3][3];
+  const int j = lane & 15, k = lane >> 4, kk = k < 3 ? k : 2;
+  T(*zw)[kGramRow] = zl[wave];
+  v4 acc[6];
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+  for (int p = 0; p < 6; ++p) acc[p] = v4{0, 0, 0, 0};
+  T yacc = 0;
+  for (int base = w0; base < w1; base += kGramBatch) {
+    const int ne = min(kGramBatch, w1 - base);
+    if (lane < ne) {
+      const int i = base + lane;
+      T zr[54];
+      gram_zblocks<T>(d, i, zr);
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const int A = 3 * pc + a, B = 3 * pcp + b;
-      const int lo = A < B ? A : B, hi = A < B ? B : A;
-      zoff[a][b] = lo * 9 - lo * (lo - 1) / 2 + (hi - lo);
-    }
-  T acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0;
-  for (int base = e0; base < e1; base += TE) {
-    const int ne = min(TE, e1 - base);
-    __syncthreads();
-    if (t < ne) {
-      const int i = base + t;
-      T R[9];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) R[k] = (T)d.R[k * m + i];
-      const T* Lf = (const T*)d.Lf;
+      for (int q = 0; q < 54; ++q) zw[lane][q] = zr[q];
       const T* gbar = (const T*)d.gbar;
-      // explicit block inverses H^{-1} = L^{-T} L^{-1} (6x6 and 3x3, packed lower)
-      T Hs[21], Hk[6];
-      {
-        T Ls[21], Li[21];
-#pragma unroll
-        for (int k = 0; k < 21; ++k) Ls[k] = Lf[k * m + i];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-          Li[c * (c + 1) / 2 + c] = T(1) / Ls[c * (c + 1) / 2 + c];
-#pragma unroll
-          for (int r = c + 1; r < 6; ++r) {
-            T v = 0;
-#pragma unroll
-            for (int k = c; k < r; ++k) v += Ls[r * (r + 1) / 2 + k] * Li[k * (k + 1) / 2 + c];
-            Li[r * (r + 1) / 2 + c] = -v / Ls[r * (r + 1) / 2 + r];
-          }
-        }
-#pragma unroll
-        for (int r = 0; r < 6; ++r)
-#pragma unroll
-          for (int c = 0; c <= r; ++c) {
-            T v = 0;
-#pragma unroll
-            for (int k = r; k < 6; ++k) v += Li[k * (k + 1) / 2 + r] * Li[k * (k + 1) / 2 + c];
-            Hs[r * (r + 1) / 2 + c] = v;
-          }
-        T Lk[6], Lki[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) Lk[k] = Lf[(21 + k) * m + i];
-        Lki[0] = T(1) / Lk[0];
-        Lki[2] = T(1) / Lk[2];
-        Lki[5] = T(1) / Lk[5];
-        Lki[1] = -Lk[1] * Lki[0] * Lki[2];
-        Lki[4] = -Lk[4] * Lki[2] * Lki[5];
-        Lki[3] = -(Lk[3] * Lki[0] + Lk[4] * Lki[1]) * Lki[5];
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-          for (int c = 0; c <= r; ++c) {
-            T v = 0;
-#pragma unroll
-            for (int k = r; k < 3; ++k) v += Lki[k * (k + 1) / 2 + r] * Lki[k * (k + 1) / 2 + c];
-            Hk[r * (r + 1) / 2 + c] = v;
-          }
-      }
-      // Z_X[(e,dd),(e',dd')] = sum Y H^{-1} Y^T (rotated frame), then per
-      // (dd <= dd') block Z[(c,dd),(c',dd')] = (R M R^T)[c][c'] with
-      // M[e][e'] = Z_X[(e,dd),(e',dd')]
-#pragma unroll
-      for (int dd = 0; dd < 3; ++dd)
-#pragma unroll
-        for (int dp = dd; dp < 3; ++dp) {
-          T Mx[3][3];
-#pragma unroll
-          for (int e = 0; e < 3; ++e)
-#pragma unroll
-            for (int ep = 0; ep < 3; ++ep) {
-              const int A = 3 * e + dd, B = 3 * ep + dp;
-              T v = 0;
-#pragma unroll
-              for (int pa = 0; pa < 2; ++pa)
-#pragma unroll
-                for (int pb = 0; pb < 2; ++pb) {
-                  const int ya = kYof[A][pa], yb = kYof[B][pb];
-                  if (ya >= 0 && yb >= 0 && (ya < 6) == (yb < 6)) {
-                    const T cv = T(kYvf[A][pa] * kYvf[B][pb]);
-                    if (ya < 6) {
-                      const int lo = ya < yb ? ya : yb, hi = ya < yb ? yb : ya;
-                      v += cv * Hs[hi * (hi + 1) / 2 + lo];
-                    } else {
-                      const int lo = (ya < yb ? ya : yb) - 6, hi = (ya < yb ? yb : ya) - 6;
-                      v += cv * Hk[hi * (hi + 1) / 2 + lo];
-                    }
-                  }
-                }
-              Mx[e][ep] = v;
-            }
-          T RM[3][3];
-#pragma unroll
-          for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int ep = 0; ep < 3; ++ep)
-              RM[c][ep] = R[3 * c] * Mx[0][ep] + R[3 * c + 1] * Mx[1][ep] + R[3 * c + 2] * Mx[2][ep];
-#pragma unroll
-          for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int cp = 0; cp < 3; ++cp) {
-              if (dd == dp && cp < c) continue;
-              const T v = RM[c][0] * R[3 * cp] + RM[c][1] * R[3 * cp + 1] + RM[c][2] * R[3 * cp + 2];
-              const int A = 3 * c + dd, B = 3 * cp + dp;
-              const int lo = A < B ? A : B, hi = A < B ? B : A;
-              zs[t][lo * 9 - lo * (lo - 1) / 2 + (hi - lo)] = v;
-            }
-        }
       double gbd[9], D[9], RD[9], Rd[9];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        gbd[k] = (double)gbar[k * m + i];
-        Rd[k] = (double)R[k];
+      for (int q = 0; q < 9; ++q) {
+        gbd[q] = (double)gbar[q * m + i];
+        Rd[q] = (double)(T)d.R[q * m + i];
       }
       from_y<double>(gbd, D);
       matmul3(Rd, D, RD);
 #pragma unroll
-      for (int k = 0; k < 9; ++k) fg[t][k] = (T)RD[k];
-      ws[t] = (T)d.w[i];
+      for (int q = 0; q < 9; ++q) zw[lane][54 + q] = (T)RD[q];
+      zw[lane][63] = (T)d.w[i];
     }
-    for (int idx = t; idx < ne * kMaxK1; idx += kBlock) {
-      const int el = idx / kMaxK1, j = idx % kMaxK1;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int el = 0; el < ne; ++el) {
       const int i = base + el;
+      const T* zr = zw[el];
       T g0 = 0, g1 = 0, g2 = 0;
       if (j < k1) {
         double b[4][3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
+        for (int v = 0; v < 3; ++v)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) b[k][c] = d.dminv[(3 * k + c) * m + i];
+          for (int c = 0; c < 3; ++c) b[v][c] = d.dminv[(3 * v + c) * m + i];
 #pragma unroll
         for (int c = 0; c < 3; ++c) b[3][c] = -(b[0][c] + b[1][c] + b[2][c]);
         double a0 = 0, a1 = 0, a2 = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const double ph = d.phi[(int64_t)kMaxK1 * d.vid[k * m + i] + j];
-          a0 += ph * b[k][0];
-          a1 += ph * b[k][1];
-          a2 += ph * b[k][2];
+        for (int v = 0; v < 4; ++v) {
+          const double ph = d.phi[(int64_t)kMaxK1 * d.vid[v * m + i] + j];
+          a0 += ph * b[v][0];
+          a1 += ph * b[v][1];
+          a2 += ph * b[v][2];
         }
         g0 = (T)a0;
         g1 = (T)a1;
         g2 = (T)a2;
       }
-      gp[el][j][0] = g0;
-      gp[el][j][1] = g1;
-      gp[el][j][2] = g2;
-    }
-    __syncthreads();
-    for (int el = grp; el < ne; el += 2) {
-      const T wv = ws[el];
-      if (gth) {
-        // Z_{c c'} block (3x3) from the packed upper triangle
-        T zb[3][3];
+      const T wv = zr[63];
+      const T gk = k == 0 ? g0 : (k == 1 ? g1 : g2);
+      const T av = k < 3 ? wv * wv * gk : T(0);
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int b = 0; b < 3; ++b) zb[a][b] = zs[el][zoff[a][b]];
-        T hh[3][4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const T g0 = gp[el][4 * qb + q][0], g1 = gp[el][4 * qb + q][1], g2 = gp[el][4 * qb + q][2];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) hh[a][q] = zb[a][0] * g0 + zb[a][1] * g1 + zb[a][2] * g2;
-        }
-        const T w2 = wv * wv;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const T g0 = w2 * gp[el][4 * jb + a][0], g1 = w2 * gp[el][4 * jb + a][1], g2 = w2 * gp[el][4 * jb + a][2];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) acc[a][q] += g0 * hh[0][q] + g1 * hh[1][q] + g2 * hh[2][q];
-        }
-      } else if (yth) {
-        const T f0 = wv * fg[el][3 * yc], f1 = wv * fg[el][3 * yc + 1], f2 = wv * fg[el][3 * yc + 2];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-          acc[0][a] += f0 * gp[el][4 * yb + a][0] + f1 * gp[el][4 * yb + a][1] + f2 * gp[el][4 * yb + a][2];
+      for (int p = 0; p < 6; ++p) {
+        const T bv = zr[p * 9 + kk * 3] * g0 + zr[p * 9 + kk * 3 + 1] * g1 + zr[p * 9 + kk * 3 + 2] * g2;
+        acc[p] = MfmaAcc<T>::mma(av, bv, acc[p]);
       }
+      if (k < 3) yacc += wv * (zr[54 + 3 * k] * g0 + zr[54 + 3 * k + 1] * g1 + zr[54 + 3 * k + 2] * g2);
     }
+    __builtin_amdgcn_wave_barrier();
   }
-  // combine the two groups in a fixed order, then write the partial sums
+  // add the waves in a fixed order (0 + 1 + 2 + 3) through LDS, then write
   __syncthreads();
-  if (grp == 1 && tl < 108)
+  double* comb = sbuf;
+  if (wave > 0) {
+    double* o = comb + (size_t)(wave - 1) * 64 * 25;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int p = 0; p < 6; ++p)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) comb[tl][4 * a + q] = (double)acc[a][q];
+      for (int r = 0; r < 4; ++r) o[(p * 4 + r) * 64 + lane] = (double)acc[p][r];
+    o[24 * 64 + lane] = (double)yacc;
+  }
   __syncthreads();
-  double* out = d.part_gram + (int64_t)kGramEntries * bid;
-  if (grp == 0 && gth) {
+  if (wave == 0) {
+    double* out = d.part_gram + (int64_t)kGramEntries * bid;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int p = 0; p < 6; ++p)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        out[pair * 256 + (4 * jb + a) * 16 + 4 * qb + q] = (double)acc[a][q] + comb[tl][4 * a + q];
-  } else if (grp == 0 && yth) {
+      for (int r = 0; r < 4; ++r) {
+        double v = (double)acc[p][r];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) out[1536 + yc * 16 + 4 * yb + a] = (double)acc[0][a] + comb[tl][a];
+        for (int w = 0; w < 3; ++w) v += comb[(size_t)w * 64 * 25 + (p * 4 + r) * 64 + lane];
+        out[p * 256 + MfmaAcc<T>::row(lane, r) * 16 + j] = v;
+      }
+    if (k < 3) {
+      double v = (double)yacc;
+#pragma unroll
+      for (int w = 0; w < 3; ++w) v += comb[(size_t)w * 64 * 25 + 24 * 64 + lane];
+      out[1536 + k * 16 + j] = v;
+    }
   }
 }
 template <typename T>
@@ -1197,60 +1219,60 @@ DEV void b_control_a(const DevMesh& d, int bid) {
     if (stop) ctl->done = 1;
   }
   __syncthreads();
-  if (flag || K == 0 || t >= 64) return;
-  // ---- the first wave alone from here (LDS accesses of one wave execute in
-  // program order, so no barrier is needed).  The padded 48 x 48 matrix is
-  // copied column-major (CmT[k][t] = C[t][k]) so that lane t's row is read
-  // without bank conflicts; pivot columns are broadcast through colbuf.
-  __shared__ double CmT[48][64];
-  __shared__ double colbuf[64];
-  for (int k = 0; k < 48; ++k) CmT[k][t] = (t < 48 && k <= t) ? Cm[t][k] : 0.0;
-  __builtin_amdgcn_wave_barrier();
-  int bad = 0;
-  for (int j = 0; j < 48; ++j) {
-    const double dj = CmT[j][j];
-    bad |= !(dj > 0);
-    const double piv = dj > 0 ? sqrt(dj) : 1.0;
-    const double own = CmT[j][t];
-    const double lij = (t > j) ? own / piv : (t == j ? piv : 0.0);
-    if (t >= j) CmT[j][t] = lij;
-    colbuf[t] = lij;
-    __builtin_amdgcn_wave_barrier();
-    // branch-free trailing update (rows k > t are multiplied by 0)
-#pragma unroll 8
-    for (int k = j + 1; k < 48; ++k) {
-      const double mk = (k <= t) ? lij : 0.0;
-      CmT[k][t] -= mk * colbuf[k];
+  if (flag || K == 0) return;
+  // Cholesky of the padded 48 x 48 system by the whole workgroup, one barrier
+  // per column: step j subtracts C[r][j] C[c][j] / C[j][j] from every entry
+  // (r, c) with j < c <= r; the columns are scaled by 1 / sqrt(C[j][j]) at the
+  // end.  A non-positive pivot marks the system as failed (z = 0 below).
+  for (int j = 0; j < 47; ++j) {
+    const double dj = Cm[j][j];
+    const double inv = dj > 0 ? 1.0 / dj : 0.0;
+    const int n = 47 - j;
+    for (int idx = t; idx < n * n; idx += kCtlThreads) {
+      const int r = j + 1 + idx / n, c = j + 1 + idx % n;
+      if (c <= r) Cm[r][c] -= Cm[r][j] * Cm[c][j] * inv;
     }
-    __builtin_amdgcn_wave_barrier();
+    __syncthreads();
   }
-  // forward substitution L u = y (lane t holds y_t; L[t][i] = CmT[i][t])
+  __shared__ double piv[48];
+  __shared__ int nbad;
+  if (t == 0) nbad = 0;
+  __syncthreads();
+  if (t < 48) {
+    const double dj = Cm[t][t];
+    if (!(dj > 0)) atomicAdd(&nbad, 1);
+    piv[t] = dj > 0 ? sqrt(dj) : 1.0;
+  }
+  __syncthreads();
+  for (int idx = t; idx < 48 * 48; idx += kCtlThreads) {
+    const int r = idx / 48, c = idx % 48;
+    if (c < r) Cm[r][c] /= piv[c];
+    else if (c == r) Cm[r][c] = piv[c];
+  }
+  __syncthreads();
+  const int bad = nbad > 0;
+  for (int idx = t; idx < 48 * 48; idx += kCtlThreads) {
+    const int r = idx / 48, c = idx % 48;
+    d.cfac[idx] = c <= r ? Cm[r][c] : 0.0;
+  }
+  if (t >= 64) return;
+  // substitutions in the first wave: lane t holds entry t; the newly solved
+  // entry is broadcast with readlane
   double yt = t < 48 ? yv[t] : 0.0;
   for (int i = 0; i < 48; ++i) {
-    const double lti = CmT[i][t];
-    double ui = (t == i) ? yt / lti : 0.0;
-    ui = __shfl(ui, i);
+    const double ui = bcast_lane(yt, i) / Cm[i][i];
     if (t == i) yt = ui;
-    else if (t > i) yt -= lti * ui;
+    else if (t > i && t < 48) yt -= Cm[t][i] * ui;
   }
-  // row-major copy for the backward substitution (L[i][t] = Cm[i][t])
-  for (int k = 0; k < 48; ++k)
-    if (t < 48) Cm[t][k] = CmT[k][t];
-  __builtin_amdgcn_wave_barrier();
   for (int i = 47; i >= 0; --i) {
-    const double lit = (t < 48) ? Cm[i][t] : 0.0;
-    const double lii = CmT[i][i];
-    double zi = (t == i) ? yt / lii : 0.0;
-    zi = __shfl(zi, i);
+    const double zi = bcast_lane(yt, i) / Cm[i][i];
     if (t == i) yt = zi;
-    else if (t < i) yt -= lit * zi;
+    else if (t < i) yt -= Cm[i][t] * zi;
   }
   if (t < 48) yv[t] = yt;
   __builtin_amdgcn_wave_barrier();
   if (t == 0 && bad) ctl->chol_fail += 1;
   if (t == 0) d.cfac_ok[0] = !bad;
-  for (int r = t; r < 48; r += 64)
-    for (int k = 0; k < 48; ++k) d.cfac[r * 48 + k] = k <= r ? Cm[r][k] : 0.0;
   if (t < 48) {
     const int c = t / kMaxK1, j = t % kMaxK1;
     d.zbuf[t] = (!bad && j < k1) ? yv[c * k1 + j] : 0.0;
