@@ -200,8 +200,10 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
     pl.nlevels = fac.nlevels;
     pl.fwd_ptr.assign(fac.nlevels + 1, 0);
     pl.bwd_ptr.assign(fac.nlevels + 1, 0);
-    // Levels with few work items at 32 rows per item split the supernodes
-    // with long rows into items of 8 rows (32 lanes per row) instead.
+    // Backward levels with few work items at 32 columns per item split the
+    // supernodes with long rows into items of 8 (32 lanes per row) instead.
+    // Forward items stay at 32 rows: each item assembles its frontal vector
+    // from the children's updates, which narrower items would repeat.
     auto sparse_level = [&](int L, bool fwd_dir) {
       int64_t items = 0;
       for (int s = 0; s < fac.ns; ++s)
@@ -209,10 +211,9 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
       return items < emu::kWideLevelItems;
     };
     for (int L = 0; L < fac.nlevels; ++L) {
-      const bool sparse = sparse_level(L, true);
       for (int s = 0; s < fac.ns; ++s)
         if (fac.level[s] == L) {
-          const bool wide = sparse && fac.w[s] >= emu::kWideRowMin;
+          const bool wide = false;
           const int step = wide ? 8 : 32;
           for (int r = 0; r < fac.h[s]; r += step) fwd.push_back(make_int2(s, r | (wide ? emu::kItemWideBit : 0)));
         }

@@ -385,23 +385,101 @@ struct NDBuilder {
   }
 };
 
+// The separators of the top levels of the dissection are merged, level by
+// level while the total width stays within max_w, into one dense root
+// supernode: its factor is dense (the blocks between sibling separators fill
+// in), but the top of the elimination tree then costs one level of the
+// triangular sweeps instead of several.  Leaves met on the way stay children.
+// The width is capped at kMergeWidth and at n_free / 16 (small meshes keep a
+// sparse top).
+static constexpr int kMergeWidth = 1536;
+
+static int merge_top_separators(NDBuilder& nb, int root, size_t max_w) {
+  std::vector<int> absorbed{root};
+  std::vector<int> frontier = nb.nodes[root].children;
+  size_t width = nb.nodes[root].cols.size();
+  for (;;) {
+    size_t add = 0;
+    bool any = false;
+    for (int c : frontier)
+      if (!nb.nodes[c].children.empty()) {
+        add += nb.nodes[c].cols.size();
+        any = true;
+      }
+    if (!any || width + add > max_w) break;
+    std::vector<int> next;
+    for (int c : frontier) {
+      if (nb.nodes[c].children.empty()) {
+        next.push_back(c);
+      } else {
+        absorbed.push_back(c);
+        for (int k : nb.nodes[c].children) next.push_back(k);
+      }
+    }
+    width += add;
+    frontier.swap(next);
+  }
+  if (absorbed.size() == 1) return root;
+  NDNode merged;
+  // deeper separators first, the top separator last (their original order)
+  for (auto it = absorbed.rbegin(); it != absorbed.rend(); ++it)
+    merged.cols.insert(merged.cols.end(), nb.nodes[*it].cols.begin(), nb.nodes[*it].cols.end());
+  merged.children = frontier;
+  nb.nodes.push_back(std::move(merged));
+  return (int)nb.nodes.size() - 1;
+}
+
 // ------------------------------------------------------------------ dense kernels
 // In-place Cholesky of the leading w x w block of a row-major matrix with
-// leading dimension ld (lower triangle).  Returns false on a non-positive pivot.
-static bool dense_chol(int w, double* A, int64_t ld) {
-  for (int j = 0; j < w; ++j) {
-    double* rj = A + j * ld;
-    double s = rj[j];
-    for (int k = 0; k < j; ++k) s -= rj[k] * rj[k];
-    if (!(s > 0) || !std::isfinite(s)) return false;
-    double d = std::sqrt(s);
-    rj[j] = d;
-    double inv = 1.0 / d;
-    for (int i = j + 1; i < w; ++i) {
-      double* ri = A + i * ld;
-      double t = ri[j];
-      for (int k = 0; k < j; ++k) t -= ri[k] * rj[k];
-      ri[j] = t * inv;
+// leading dimension ld (lower triangle), right-looking in panels of 64 columns
+// (panel solves and trailing updates split over rows when `par`).  Returns
+// false on a non-positive pivot.
+static bool dense_chol(int w, double* A, int64_t ld, bool par) {
+  constexpr int NB = 64;
+  for (int j0 = 0; j0 < w; j0 += NB) {
+    const int j1 = std::min(w, j0 + NB);
+    for (int j = j0; j < j1; ++j) {
+      double* rj = A + j * ld;
+      double s = rj[j];
+      for (int k = j0; k < j; ++k) s -= rj[k] * rj[k];
+      if (!(s > 0) || !std::isfinite(s)) return false;
+      const double d = std::sqrt(s);
+      rj[j] = d;
+      const double inv = 1.0 / d;
+      for (int i = j + 1; i < j1; ++i) {
+        double* ri = A + i * ld;
+        double t = ri[j];
+        for (int k = j0; k < j; ++k) t -= ri[k] * rj[k];
+        ri[j] = t * inv;
+      }
+    }
+    if (j1 == w) break;
+    auto panel = [&](int64_t ii) {
+      double* ri = A + (j1 + ii) * ld;
+      for (int j = j0; j < j1; ++j) {
+        const double* rj = A + j * ld;
+        double t = ri[j];
+        for (int k = j0; k < j; ++k) t -= ri[k] * rj[k];
+        ri[j] = t / rj[j];
+      }
+    };
+    auto trail = [&](int64_t ii) {
+      const int i = j1 + (int)ii;
+      double* ri = A + (int64_t)i * ld;
+      for (int k = j1; k <= i; ++k) {
+        const double* rk = A + (int64_t)k * ld;
+        double t = 0;
+        for (int j = j0; j < j1; ++j) t += ri[j] * rk[j];
+        ri[k] -= t;
+      }
+    };
+    const int64_t rows = w - j1;
+    if (par && rows > 128) {
+      parallel_for(rows, panel, 16);
+      parallel_for(rows, trail, 8);
+    } else {
+      for (int64_t r = 0; r < rows; ++r) panel(r);
+      for (int64_t r = 0; r < rows; ++r) trail(r);
     }
   }
   return true;
@@ -412,7 +490,7 @@ static void front_factor(Factor& fac, int s, std::vector<double>& Fm, int h,
   const int w = fac.w[s];
   double* F = Fm.data();
   const int64_t ld = h;
-  if (!dense_chol(w, F, ld)) fail(EMU_E_SINGULAR, "ACAP operator is not positive definite "
+  if (!dense_chol(w, F, ld, par)) fail(EMU_E_SINGULAR, "ACAP operator is not positive definite "
                                   "(a connected part of the mesh has no pinned vertex)");
   const int hb = h - w;
   // TRSM: rows r >= w:  L_od[r] = F[r] L_dd^{-T}
@@ -443,8 +521,9 @@ static void front_factor(Factor& fac, int s, std::vector<double>& Fm, int h,
   // Linv = L_dd^{-1} (lower, packed rows) and M = L_od Linv
   double* out = fac.vals.data() + fac.valoff[s];
   std::vector<double> Linv((size_t)w * w, 0.0);
-  for (int c = 0; c < w; ++c) {
+  auto inv_col = [&](int64_t cc) {
     // column c of the inverse: forward substitution L x = e_c
+    const int c = (int)cc;
     Linv[(size_t)c * w + c] = 1.0 / F[c * ld + c];
     for (int r = c + 1; r < w; ++r) {
       const double* rr = F + r * ld;
@@ -452,7 +531,9 @@ static void front_factor(Factor& fac, int s, std::vector<double>& Fm, int h,
       for (int k = c; k < r; ++k) t += rr[k] * Linv[(size_t)k * w + c];
       Linv[(size_t)r * w + c] = -t / rr[r];
     }
-  }
+  };
+  if (par && w > 128) parallel_for(w, inv_col, 8);
+  else for (int c = 0; c < w; ++c) inv_col(c);
   int64_t o = 0;
   for (int r = 0; r < w; ++r)
     for (int c = 0; c <= r; ++c) out[o++] = Linv[(size_t)r * w + c];
@@ -528,6 +609,7 @@ static void order_and_factor(HostMesh& hm) {
   std::vector<int32_t> all(nf);
   std::iota(all.begin(), all.end(), 0);
   std::vector<int> roots = nb.build(all);
+  for (int& r : roots) r = merge_top_separators(nb, r, std::min<size_t>(kMergeWidth, nf / 16));
 
   // postorder numbering of supernodes and columns
   Factor& fac = hm.fac;

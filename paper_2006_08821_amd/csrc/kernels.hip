@@ -245,6 +245,62 @@ DEV void polar3(const double* X, double* R) {
     for (int j = 0; j < 3; ++j) R[3 * i + j] = u1[i] * v1[j] + u2[i] * v2[j] + u3[i] * v3[j];
 }
 
+// The Jacobi-based polar factor out of line (by value, so nothing is forced
+// into scratch memory): the element pass uses it only where the Newton
+// iteration declines (inverted or nearly singular elements).
+struct Mat3 {
+  double v[9];
+};
+DEV Mat3 load_mat3(const double* a) {
+  Mat3 m;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) m.v[k] = a[k];
+  return m;
+}
+__device__ __noinline__ Mat3 polar3_fallback(Mat3 X) {
+  Mat3 R;
+  polar3(X.v, R.v);
+  return R;
+}
+
+// Orthogonal polar factor by the scaled Newton iteration
+//   X <- (z X + X^{-T} / z) / 2,  z = |det X|^{-1/3}  (determinant scaling),
+// which converges quadratically to the rotation of X when det X > 0.  Returns
+// false (R untouched) for det X <= 0, a tiny determinant or no convergence in
+// 12 steps; the caller then uses polar3.
+DEV bool polar3_newton(const double* X0, double* R) {
+  double X[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) X[k] = X0[k];
+  double nx = 0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) nx += X[k] * X[k];
+  double dt = det3(X);
+  if (!(dt > 1e-12 * nx * sqrt(nx))) return false;
+  for (int it = 0; it < 12; ++it) {
+    double C[9];
+    cof3<double>(X, C);  // X^{-T} = cof(X) / det X
+    const double z = it < 6 ? cbrt(1.0 / dt) : 1.0;
+    const double a = 0.5 * z, b = 0.5 / (z * dt);
+    double diff = 0, nrm = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double y = a * X[k] + b * C[k];
+      diff += (y - X[k]) * (y - X[k]);
+      nrm += y * y;
+      X[k] = y;
+    }
+    if (it >= 6 && diff <= 1e-30 * nrm) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) R[k] = X[k];
+      return true;
+    }
+    dt = det3(X);
+    if (!(dt > 0)) return false;
+  }
+  return false;
+}
+
 // ------------------------------------------------------------------ element Hessian
 // Core 9x9 Hessian of Psi at the symmetric S (row-major index 3a+i for F_ai):
 //   mu delta + kappa d2J/dF2 + phi (I (x) u u^T),  kappa = lhat (J-1) - mu,
@@ -507,20 +563,32 @@ __global__ void __launch_bounds__(kBlock) k_scatter_F(DevMesh d) {
 
 // right-hand side of the ACAP solve: fixed-order sum of element contributions
 // at each free vertex, plus (optionally) the constant pinned term -L_fp qbar_p
+// Four lanes per vertex take interleaved entries of its incidence list and are
+// added in a fixed order.
+constexpr int kRhsLanes = 4;
 DEV void b_rhs(const DevMesh& d, int bid, int add_pin, int check_done) {
   if (check_done && d.ctl->done) return;
-  int f = bid * blockDim.x + threadIdx.x;
-  if (f >= d.nf) return;
+  const int f = bid * (kBlock / kRhsLanes) + (int)threadIdx.x / kRhsLanes;
+  const int sub = threadIdx.x % kRhsLanes;
   double acc[3] = {0, 0, 0};
+  if (f < d.nf) {
+    const int k0 = d.inc_ptr[f], k1 = d.inc_ptr[f + 1];
+    for (int k = k0 + sub; k < k1; k += kRhsLanes) {
+      const int code = d.inc[k];
+      const double* src = d.contrib + (int64_t)12 * (code >> 2) + 3 * (code & 3);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[c] += src[c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    acc[c] += __shfl_xor(acc[c], 1);
+    acc[c] += __shfl_xor(acc[c], 2);
+  }
+  if (f >= d.nf || sub != 0) return;
   if (add_pin)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc[c] = d.pin_rhs[3 * f + c];
-  for (int k = d.inc_ptr[f]; k < d.inc_ptr[f + 1]; ++k) {
-    int code = d.inc[k];
-    const double* src = d.contrib + (int64_t)12 * (code >> 2) + 3 * (code & 3);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) acc[c] += src[c];
-  }
+    for (int c = 0; c < 3; ++c) acc[c] += d.pin_rhs[3 * f + c];
 #pragma unroll
   for (int c = 0; c < 3; ++c) d.rhs[3 * f + c] = acc[c];
 }
@@ -563,6 +631,18 @@ DEV void row_products(const double* __restrict__ V, int64_t base, int w, int h, 
     const int c0 = max(lo, vbase), c1 = min(hi, vbase + vlen);
     const double* row = V + base + roff - lo;
     int c = c0 + l;
+    for (; c + 7 * LPR < c1; c += 8 * LPR) {  // 8 loads in flight per lane
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = row[c + u * LPR];
+      const double* v0 = vec + 3 * (c - vbase);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a0 += x[u] * v0[3 * u * LPR];
+        a1 += x[u] * v0[3 * u * LPR + 1];
+        a2 += x[u] * v0[3 * u * LPR + 2];
+      }
+    }
     for (; c + 3 * LPR < c1; c += 4 * LPR) {
       const double x0 = row[c], x1 = row[c + LPR], x2 = row[c + 2 * LPR], x3 = row[c + 3 * LPR];
       const double* v0 = vec + 3 * (c - vbase);
@@ -729,10 +809,10 @@ DEV void b_element(const DevMesh& d, int bid) {
   Ctl* ctl = d.ctl;
   if (ctl->done) return;
   __shared__ DD sh[2 * kBlock];
-  __shared__ int shc[2][kBlock];
+  __shared__ int shc[kBlock];
   const double sigma = ctl->sigma;
   DD acc[2] = {DD{0, 0}, DD{0, 0}};
-  int nclamp = 0, ninv = 0;
+  int ninv = 0;
   const int m = d.m;
   for (int i = bid * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
     Elem e;
@@ -747,7 +827,11 @@ DEV void b_element(const DevMesh& d, int bid) {
       from_y<double>(py, D);
 #pragma unroll
       for (int k = 0; k < 9; ++k) X[k] = S[k] + sigma * D[k];
-      polar3(X, Rx);
+      if (!polar3_newton(X, Rx)) {
+        const Mat3 r = polar3_fallback(load_mat3(X));
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Rx[k] = r.v[k];
+      }
       matmul3(R, Rx, Rn);
       matTmul3(Rx, X, Sn);
       double sy[9];
@@ -796,13 +880,57 @@ DEV void b_element(const DevMesh& d, int bid) {
     acc[1] = dd_add_d(acc[1], gn);
     double gy[9];
     to_y<double, double>(G, gy);
+    T* gyo = (T*)d.gbar;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) gyo[k * m + i] = (T)gy[k];
+  }
+  block_reduce_dd<2>(acc, sh);
+  shc[threadIdx.x] = ninv;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) shc[threadIdx.x] += shc[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    d.part_e[2 * bid] = acc[0].hi;
+    d.part_e[2 * bid + 1] = acc[0].lo;
+    d.part_g[2 * bid] = acc[1].hi;
+    d.part_g[2 * bid + 1] = acc[1].lo;
+    d.part_cnt[2 * bid + 1] = shc[0];
+  }
+}
+
+// Hessian blocks of the element pass: at the state left by b_element, the two
+// clamped blocks + beta I in the rotated basis (precision T), their Cholesky
+// factors, and gbar = H^{-1} g (g read from gbar, overwritten in place).
+template <typename T>
+DEV void b_element_hess(const DevMesh& d, int bid) {
+  Ctl* ctl = d.ctl;
+  if (ctl->done) return;
+  __shared__ int shc[kBlock];
+  int nclamp = 0;
+  const int m = d.m;
+  for (int i = bid * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
+    double S[9];
+    load_S(d, i, S);
+    const double vol = d.vol[i], mu = d.mu[i], lhat = d.lhat[i];
+    const double beta = d.alpha * d.w[i];
+    double u[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[c] = d.fib[c * m + i];
+    const int g = d.grp[i];
+    const double afk = (g >= 0 ? d.act[g] : 0.0) * d.kf;
+    const double J = det3(S);
+    double C[9];
+    cof3<double>(S, C);
+    const double kap = lhat * (J - 1.0) - mu;
     // Hessian blocks in the rotated basis (precision T)
     T St[9], ut[3];
 #pragma unroll
     for (int k = 0; k < 9; ++k) St[k] = (T)S[k];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) ut[k] = (T)e.u[k];
-    const T muT = (T)e.mu, kapT = (T)kap, phiT = (T)(2.0 * afk), volT = (T)e.vol, lhT = (T)e.lhat;
+    for (int k = 0; k < 3; ++k) ut[k] = (T)u[k];
+    const T muT = (T)mu, kapT = (T)kap, phiT = (T)(2.0 * afk), volT = (T)vol, lhT = (T)lhat;
     T cy[9];
     to_y<T, double>(C, cy);
     T Hs[6][6], Hk[3][3];
@@ -818,14 +946,14 @@ DEV void b_element(const DevMesh& d, int bid) {
     T Ls[21], Lk[6];
     nclamp += clamp_add_factor<T, 6>(Hs, (T)beta, Ls);
     nclamp += clamp_add_factor<T, 3>(Hk, (T)beta, Lk);
+    T* gbar = (T*)d.gbar;
     T gs[6], gk[3];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) gs[k] = (T)gy[k];
+    for (int k = 0; k < 6; ++k) gs[k] = gbar[k * m + i];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) gk[k] = (T)gy[6 + k];
+    for (int k = 0; k < 3; ++k) gk[k] = gbar[(6 + k) * m + i];
     chol_solve<T, 6>(Ls, gs);
     chol_solve<T, 3>(Lk, gk);
-    T* gbar = (T*)d.gbar;
     T* Lf = (T*)d.Lf;
 #pragma unroll
     for (int k = 0; k < 6; ++k) gbar[k * m + i] = gs[k];
@@ -836,28 +964,18 @@ DEV void b_element(const DevMesh& d, int bid) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) Lf[(21 + k) * m + i] = Lk[k];
   }
-  block_reduce_dd<2>(acc, sh);
-  shc[0][threadIdx.x] = nclamp;
-  shc[1][threadIdx.x] = ninv;
+  shc[threadIdx.x] = nclamp;
   __syncthreads();
   for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      shc[0][threadIdx.x] += shc[0][threadIdx.x + s];
-      shc[1][threadIdx.x] += shc[1][threadIdx.x + s];
-    }
+    if (threadIdx.x < s) shc[threadIdx.x] += shc[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    d.part_e[2 * bid] = acc[0].hi;
-    d.part_e[2 * bid + 1] = acc[0].lo;
-    d.part_g[2 * bid] = acc[1].hi;
-    d.part_g[2 * bid + 1] = acc[1].lo;
-    d.part_cnt[2 * bid] = shc[0][0];
-    d.part_cnt[2 * bid + 1] = shc[1][0];
-  }
+  if (threadIdx.x == 0) d.part_cnt[2 * bid] = shc[0];
 }
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_element(DevMesh d) { b_element<T>(d, blockIdx.x); }
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_element_hess(DevMesh d) { b_element_hess<T>(d, blockIdx.x); }
 
 // --------------------------------------------------------------- Woodbury Gram
 // Per element: Z = T H^{-1} T^T (9x9, F coordinates; T = (R (x) I) Y) and the
@@ -865,14 +983,15 @@ __global__ void __launch_bounds__(kBlock) k_element(DevMesh d) { b_element<T>(d,
 //   Gram[(c,j),(c',j')] += w^2 gphi_j^T Z_{cc'} gphi_j'   (6 pairs c <= c')
 //   y[(c,j)]            += w (R D(gbar) gphi_j)[c]
 // Each wave owns a contiguous run of elements.  Phase A: one lane per element
-// (batches of kGramBatch) forms the six 3x3 coordinate-pair blocks of Z, R D(gbar)
-// and w into the wave's LDS rows.  Phase B, per element: lane (j, k) = (l % 16,
-// l / 16) computes gphi_j (all 3 components), and for each pair one 16x16x4
+// (batches of kGramBatch) forms the six 3x3 coordinate-pair blocks of Z, R D(gbar),
+// w and the 16 mode gradients into the wave's LDS rows.  Phase B, per element:
+// lane (j, k) = (l % 16, l / 16) reads gphi_j, and for each pair one 16x16x4
 // matrix-core product accumulates A = w^2 gphi[j][k] (k < 3, else 0) against
 // B = (Z_{cc'} gphi_j)[k], i.e. the 16x16 pair block.  Waves are added in a
 // fixed order at the end.
-constexpr int kGramBatch = 32;
-constexpr int kGramRow = 65;  // 54 block entries + 9 + 1, padded to an odd stride
+constexpr int kGramBatch = 16;
+constexpr int kGramRow = 65;   // 54 block entries + 9 + 1, padded to an odd stride
+constexpr int kGramGRow = 49;  // 16 mode gradients x 3, padded
 
 template <typename T>
 struct MfmaAcc;
@@ -1006,12 +1125,16 @@ template <typename T>
 DEV void b_gram(const DevMesh& d, int bid) {
   if (d.ctl->done) return;
   typedef typename MfmaAcc<T>::v4 v4;
-  // wave tiles of phase A, reused for the final combination of the waves
-  constexpr size_t kTileBytes = sizeof(T) * (kBlock / 64) * kGramBatch * kGramRow;
+  // wave tiles of phase A (Z blocks, R D(gbar), w, mode gradients), reused for
+  // the final combination of the waves
+  constexpr size_t kTileBytes = sizeof(T) * (kBlock / 64) * kGramBatch * (kGramRow + kGramGRow);
   constexpr size_t kCombBytes = sizeof(double) * 3 * 64 * 25;
   __shared__ double sbuf[((kTileBytes > kCombBytes ? kTileBytes : kCombBytes) + 7) / 8];
-  T(*zl)[kGramBatch][kGramRow] = reinterpret_cast<T(*)[kGramBatch][kGramRow]>(sbuf);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  T(*zw)[kGramRow] = reinterpret_cast<T(*)[kGramRow]>(sbuf) + wave * kGramBatch;
+  T(*gw)[kGramGRow] =
+      reinterpret_cast<T(*)[kGramGRow]>(reinterpret_cast<T*>(sbuf) + (kBlock / 64) * kGramBatch * kGramRow) +
+      wave * kGramBatch;
   const int m = d.m;
   const int per = (m + d.nbg - 1) / d.nbg;
   const int e0 = bid * per, e1 = min(m, e0 + per);
@@ -1019,7 +1142,6 @@ DEV void b_gram(const DevMesh& d, int bid) {
   const int w0 = min(e1, e0 + wave * perw), w1 = min(e1, w0 + perw);
   const int k1 = d.k1;
   const int j = lane & 15, k = lane >> 4, kk = k < 3 ? k : 2;
-  T(*zw)[kGramRow] = zl[wave];
   v4 acc[6];
 #pragma unroll
   for (int p = 0; p < 6; ++p) acc[p] = v4{0, 0, 0, 0};
@@ -1044,34 +1166,42 @@ DEV void b_gram(const DevMesh& d, int bid) {
 #pragma unroll
       for (int q = 0; q < 9; ++q) zw[lane][54 + q] = (T)RD[q];
       zw[lane][63] = (T)d.w[i];
+      // mode gradients gphi_j = sum_v phi_j(v) b_v, all 16 modes (zero rows
+      // of phi beyond k1)
+      double b[4][3];
+#pragma unroll
+      for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) b[v][c] = d.dminv[(3 * v + c) * m + i];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) b[3][c] = -(b[0][c] + b[1][c] + b[2][c]);
+      double gg[kMaxK1][3];
+#pragma unroll
+      for (int q = 0; q < kMaxK1; ++q) gg[q][0] = gg[q][1] = gg[q][2] = 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double2* ph = reinterpret_cast<const double2*>(d.phi + (int64_t)kMaxK1 * d.vid[v * m + i]);
+#pragma unroll
+        for (int q2 = 0; q2 < kMaxK1 / 2; ++q2) {
+          const double2 pv = ph[q2];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            gg[2 * q2][c] += pv.x * b[v][c];
+            gg[2 * q2 + 1][c] += pv.y * b[v][c];
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kMaxK1; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gw[lane][3 * q + c] = q < k1 ? (T)gg[q][c] : T(0);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (int el = 0; el < ne; ++el) {
-      const int i = base + el;
       const T* zr = zw[el];
-      T g0 = 0, g1 = 0, g2 = 0;
-      if (j < k1) {
-        double b[4][3];
-#pragma unroll
-        for (int v = 0; v < 3; ++v)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) b[v][c] = d.dminv[(3 * v + c) * m + i];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) b[3][c] = -(b[0][c] + b[1][c] + b[2][c]);
-        double a0 = 0, a1 = 0, a2 = 0;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const double ph = d.phi[(int64_t)kMaxK1 * d.vid[v * m + i] + j];
-          a0 += ph * b[v][0];
-          a1 += ph * b[v][1];
-          a2 += ph * b[v][2];
-        }
-        g0 = (T)a0;
-        g1 = (T)a1;
-        g2 = (T)a2;
-      }
+      const T g0 = gw[el][3 * j], g1 = gw[el][3 * j + 1], g2 = gw[el][3 * j + 2];
       const T wv = zr[63];
       const T gk = k == 0 ? g0 : (k == 1 ? g1 : g2);
       const T av = k < 3 ? wv * wv * gk : T(0);
@@ -1083,6 +1213,8 @@ DEV void b_gram(const DevMesh& d, int bid) {
       if (k < 3) yacc += wv * (zr[54 + 3 * k] * g0 + zr[54 + 3 * k + 1] * g1 + zr[54 + 3 * k + 2] * g2);
     }
     __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   // add the waves in a fixed order (0 + 1 + 2 + 3) through LDS, then write
   __syncthreads();
@@ -1221,19 +1353,46 @@ DEV void b_control_a(const DevMesh& d, int bid) {
   __syncthreads();
   if (flag || K == 0) return;
   // Cholesky of the padded 48 x 48 system by the whole workgroup, one barrier
-  // per column: step j subtracts C[r][j] C[c][j] / C[j][j] from every entry
-  // (r, c) with j < c <= r; the columns are scaled by 1 / sqrt(C[j][j]) at the
-  // end.  A non-positive pivot marks the system as failed (z = 0 below).
+  // per column.  Thread t owns the lower-triangle entries e = t + 256 q (kept
+  // in registers); step j subtracts C[r][j] C[c][j] / C[j][j] from every owned
+  // (r, c) with c > j and publishes column j + 1 through LDS.  The columns are
+  // scaled by 1 / sqrt(C[j][j]) at the end.  A non-positive pivot marks the
+  // system as failed (z = 0 below).
+  constexpr int kOwn = (48 * 49 / 2 + kCtlThreads - 1) / kCtlThreads;
+  int er[kOwn], ec[kOwn];
+  double ev[kOwn];
+#pragma unroll
+  for (int q = 0; q < kOwn; ++q) {
+    int e = t + q * kCtlThreads, r = 0;
+    if (e >= 48 * 49 / 2) e = -1;
+    if (e >= 0)
+      while ((r + 1) * (r + 2) / 2 <= e) ++r;
+    er[q] = e >= 0 ? r : 0;
+    ec[q] = e >= 0 ? e - r * (r + 1) / 2 : 48;  // 48: not owned
+    ev[q] = e >= 0 ? Cm[er[q]][ec[q]] : 0.0;
+  }
   for (int j = 0; j < 47; ++j) {
     const double dj = Cm[j][j];
     const double inv = dj > 0 ? 1.0 / dj : 0.0;
-    const int n = 47 - j;
-    for (int idx = t; idx < n * n; idx += kCtlThreads) {
-      const int r = j + 1 + idx / n, c = j + 1 + idx % n;
-      if (c <= r) Cm[r][c] -= Cm[r][j] * Cm[c][j] * inv;
+    double lr[kOwn], lc[kOwn];
+#pragma unroll
+    for (int q = 0; q < kOwn; ++q) {
+      const bool act = ec[q] > j && ec[q] < 48;
+      lr[q] = act ? Cm[er[q]][j] : 0.0;
+      lc[q] = act ? Cm[ec[q]][j] : 0.0;
+    }
+    // (column j + 1 is written while column j is read: disjoint entries)
+#pragma unroll
+    for (int q = 0; q < kOwn; ++q) {
+      ev[q] -= lr[q] * lc[q] * inv;
+      if (ec[q] == j + 1) Cm[er[q]][ec[q]] = ev[q];
     }
     __syncthreads();
   }
+#pragma unroll
+  for (int q = 0; q < kOwn; ++q)
+    if (ec[q] < 48) Cm[er[q]][ec[q]] = ev[q];
+  __syncthreads();
   __shared__ double piv[48];
   __shared__ int nbad;
   if (t == 0) nbad = 0;
@@ -1814,6 +1973,8 @@ __global__ void __launch_bounds__(kBlock) k_scale_free(DevMesh d, const double* 
   }
 EMU_BATCHED(kb_element64, kBlock, b_element<double>(d, e.y))
 EMU_BATCHED(kb_element32, kBlock, b_element<float>(d, e.y))
+EMU_BATCHED(kb_element_hess64, kBlock, b_element_hess<double>(d, e.y))
+EMU_BATCHED(kb_element_hess32, kBlock, b_element_hess<float>(d, e.y))
 EMU_BATCHED(kb_gram64, kBlock, b_gram<double>(d, e.y))
 EMU_BATCHED(kb_gram32, kBlock, b_gram<float>(d, e.y))
 EMU_BATCHED(kb_gram_reduce, kBlock, b_gram_reduce(d, e.y))
@@ -1837,6 +1998,7 @@ __global__ void __launch_bounds__(64) kb_gather_ctl(const DevMesh* __restrict__ 
 }
 
 static inline int blocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+static inline int rhs_blocks(int64_t nf) { return blocks(nf * kRhsLanes); }
 
 void launch_init_rest(const DevMesh& d, hipStream_t st) {
   hipLaunchKernelGGL(k_init_rest, dim3(blocks(d.m)), dim3(kBlock), 0, st, d);
@@ -1854,7 +2016,7 @@ void launch_scatter_F(const DevMesh& d, hipStream_t st) {
   hipLaunchKernelGGL(k_scatter_F, dim3(blocks(d.m)), dim3(kBlock), 0, st, d);
 }
 void launch_solve(const DevMesh& d, const SolvePlan& pl, int add_pin, double* x, int check_done, hipStream_t st) {
-  hipLaunchKernelGGL(k_rhs, dim3(blocks(d.nf)), dim3(kBlock), 0, st, d, add_pin, check_done);
+  hipLaunchKernelGGL(k_rhs, dim3(rhs_blocks(d.nf)), dim3(kBlock), 0, st, d, add_pin, check_done);
   for (int L = 0; L < pl.nlevels; ++L) {
     int n0 = pl.fwd_ptr[L], n1 = pl.fwd_ptr[L + 1];
     if (n1 > n0) hipLaunchKernelGGL(k_fwd, dim3(n1 - n0), dim3(kBlock), 0, st, d, n0, check_done);
@@ -1876,7 +2038,7 @@ void launch_sweeps(const DevMesh& d, const SolvePlan& pl, double* x, hipStream_t
 }
 void launch_field_solve(const DevMesh& d, const SolvePlan& pl, const double* V, double* x, hipStream_t st) {
   hipLaunchKernelGGL(k_contrib_field, dim3(blocks(d.m)), dim3(kBlock), 0, st, d, V);
-  hipLaunchKernelGGL(k_rhs, dim3(blocks(d.nf)), dim3(kBlock), 0, st, d, 0, 0);
+  hipLaunchKernelGGL(k_rhs, dim3(rhs_blocks(d.nf)), dim3(kBlock), 0, st, d, 0, 0);
   launch_sweeps(d, pl, x, st);
 }
 void launch_weighted_grad(const DevMesh& d, const double* x, double* out, hipStream_t st) {
@@ -1911,9 +2073,11 @@ void launch_set_pins(const DevMesh& d, hipStream_t st) {
 void launch_iteration(const DevMesh& d, const SolvePlan& pl, hipStream_t st) {
   if (d.mixed) {
     hipLaunchKernelGGL(k_element<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
+    hipLaunchKernelGGL(k_element_hess<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
     hipLaunchKernelGGL(k_gram<float>, dim3(d.nbg), dim3(kBlock), 0, st, d);
   } else {
     hipLaunchKernelGGL(k_element<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
+    hipLaunchKernelGGL(k_element_hess<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
     hipLaunchKernelGGL(k_gram<double>, dim3(d.nbg), dim3(kBlock), 0, st, d);
   }
   hipLaunchKernelGGL(k_gram_reduce, dim3((kGramEntries + 15) / 16), dim3(kBlock), 0, st, d);
@@ -1932,8 +2096,13 @@ void launch_iteration(const DevMesh& d, const SolvePlan& pl, hipStream_t st) {
 void launch_class(int k, const DevMesh& d, const SolvePlan& pl, hipStream_t st) {
   switch (k) {
     case 0:
-      if (d.mixed) hipLaunchKernelGGL(k_element<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
-      else hipLaunchKernelGGL(k_element<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
+      if (d.mixed) {
+        hipLaunchKernelGGL(k_element<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
+        hipLaunchKernelGGL(k_element_hess<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
+      } else {
+        hipLaunchKernelGGL(k_element<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
+        hipLaunchKernelGGL(k_element_hess<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
+      }
       break;
     case 1:
       if (d.mixed) hipLaunchKernelGGL(k_gram<float>, dim3(d.nbg), dim3(kBlock), 0, st, d);
@@ -1946,7 +2115,7 @@ void launch_class(int k, const DevMesh& d, const SolvePlan& pl, hipStream_t st) 
       if (d.mixed) hipLaunchKernelGGL(k_direction<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
       else hipLaunchKernelGGL(k_direction<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
       break;
-    case 6: hipLaunchKernelGGL(k_rhs, dim3(blocks(d.nf)), dim3(kBlock), 0, st, d, 0, 1); break;
+    case 6: hipLaunchKernelGGL(k_rhs, dim3(rhs_blocks(d.nf)), dim3(kBlock), 0, st, d, 0, 1); break;
     case 7:
       for (int L = 0; L < pl.nlevels; ++L) {
         int n0 = pl.fwd_ptr[L], n1 = pl.fwd_ptr[L + 1];
@@ -1970,9 +2139,11 @@ void launch_class(int k, const DevMesh& d, const SolvePlan& pl, hipStream_t st) 
 void launch_evaluate(const DevMesh& d, hipStream_t st) {
   if (d.mixed) {
     hipLaunchKernelGGL(k_element<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
+    hipLaunchKernelGGL(k_element_hess<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
     hipLaunchKernelGGL(k_gram<float>, dim3(d.nbg), dim3(kBlock), 0, st, d);
   } else {
     hipLaunchKernelGGL(k_element<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
+    hipLaunchKernelGGL(k_element_hess<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
     hipLaunchKernelGGL(k_gram<double>, dim3(d.nbg), dim3(kBlock), 0, st, d);
   }
   hipLaunchKernelGGL(k_gram_reduce, dim3((kGramEntries + 15) / 16), dim3(kBlock), 0, st, d);
@@ -1992,6 +2163,7 @@ static inline void launch_map(void (*k)(const DevMesh*, const int2*), const Batc
 void launch_batch_iteration(const BatchPlan& b, hipStream_t st) {
   if (b.n_meshes == 0) return;
   launch_map(b.mixed ? kb_element32 : kb_element64, b, b.element, kBlock, st);
+  launch_map(b.mixed ? kb_element_hess32 : kb_element_hess64, b, b.element, kBlock, st);
   launch_map(b.mixed ? kb_gram32 : kb_gram64, b, b.gram, kBlock, st);
   launch_map(kb_gram_reduce, b, b.gram_reduce, kBlock, st);
   launch_map(kb_control_a, b, b.one, kCtlThreads, st);
@@ -2027,7 +2199,7 @@ void batch_layout(const std::vector<const DevMesh*>& ms, const std::vector<const
   add(b.gram_reduce, [&](int) { return (kGramEntries + 15) / 16; });
   add(b.one, [&](int) { return 1; });
   add(b.uz, [&](int j) { return blocks(ms[j]->n); });
-  add(b.rhs, [&](int j) { return blocks(ms[j]->nf); });
+  add(b.rhs, [&](int j) { return rhs_blocks(ms[j]->nf); });
   add(b.add_q, [&](int j) { return blocks(3 * (int64_t)ms[j]->nf); });
   int nl = 0;
   for (int j = 0; j < nm; ++j) nl = std::max(nl, plans[j]->nlevels);

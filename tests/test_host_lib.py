@@ -141,3 +141,25 @@ def test_unpinned_component_is_singular():
     p.fiber = np.tile([0, 0, 1.0], (m, 1))
     p.group = np.zeros(m, np.int32)
     assert _err(p, n_modes=0) == 2
+
+
+def test_server_entry_points_reject_null_without_touching_a_device():
+    import ctypes as C
+    lib = _lib.load()
+    t = C.c_uint64()
+    assert lib.emu_server_submit(None, None, None, None, C.byref(t)) == 1
+    assert lib.emu_server_wait(None, C.c_uint64(1), None, None, None) == 1
+    assert lib.emu_server_report_get(None, None) == 1
+    assert lib.emu_server_destroy(None) == 0
+    assert lib.emu_server_create(None, None) == 1
+
+
+def test_server_create_reports_missing_device():
+    import ctypes as C
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = _lib.load()
+    h = C.c_void_p()
+    assert lib.emu_server_create(None, C.byref(h)) == 7  # EMU_E_HIP
+    assert not h.value
