@@ -84,19 +84,20 @@ def run(args):
     lines = {}
     for prec in (["fp64", "mixed"] if args.precision == "both" else [args.precision]):
         t0 = time.time()
-        mesh = Mesh(p, precision=prec)
+        mesh = Mesh(p, precision=prec, leaf_size=args.leaf_size)
         setup_s = time.time() - t0
         info = mesh.info()
         # warmup
         mesh.solve(grad_tol=0.0, max_iters=args.warmup, raise_on_error=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, st = mesh.solve(grad_tol=0.0, max_iters=args.steps, iters_per_sync=32, raise_on_error=False)
+        q, st = mesh.solve(grad_tol=0.0, max_iters=args.steps, iters_per_sync=32, raise_on_error=False)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         iters = max(1, st["iters"])
         prof = mesh.profile_kernels(reps=args.profile_reps)
-        lines[prec] = dict(mesh=mesh, info=info, st=st, dt=dt, iters=iters, prof=prof, setup_s=setup_s)
+        lines[prec] = dict(mesh=mesh, info=info, st=st, dt=dt, iters=iters, prof=prof, setup_s=setup_s,
+                           q=q.cpu().numpy())
         print(f"[bench] {prec}: {iters} iterations in {dt*1e3:.1f} ms ({dt/iters*1e3:.3f} ms/iter), "
               f"|g| {st['grad_norm']:.3e}, setup {setup_s:.1f} s", file=sys.stderr, flush=True)
     main = lines.get("fp64") or lines[args.precision]
@@ -139,8 +140,13 @@ def run(args):
     }
     if "mixed" in lines and "fp64" in lines:
         mx = lines["mixed"]
+        # position error of the mixed path against the FP64 path after the same
+        # number of iterations from the same start (relative to the displacement)
+        q64, qmx = lines["fp64"]["q"], mx["q"]
+        disp = np.abs(q64 - p.rest_xyz).max()
         out["mixed"] = {"value": m * mx["iters"] / mx["dt"], "ms_per_step": mx["dt"] / mx["iters"] * 1e3,
-                        "dtype": "f32 element / f64 operator", "kernel_ms": mx["prof"]}
+                        "dtype": "f32 element / f64 operator", "kernel_ms": mx["prof"],
+                        "position_err_vs_fp64": float(np.abs(qmx - q64).max() / disp) if disp > 0 else None}
     # frame solves of the activation ramp (warm-started), latency percentiles
     if args.frames > 0:
         mesh = main["mesh"]
@@ -284,6 +290,7 @@ def main():
     ap.add_argument("--frame-tol", type=float, default=1e-6)
     ap.add_argument("--frame-max-iters", type=int, default=400)
     ap.add_argument("--profile-reps", type=int, default=20)
+    ap.add_argument("--leaf-size", type=int, default=0, help="nested-dissection leaf size (0: library default)")
     ap.add_argument("--cpu-iters", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", type=int, default=48, help="requests of the serving trace (0: skip)")

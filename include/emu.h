@@ -147,6 +147,13 @@ emu_status emu_set_activation(emu_mesh* mesh, const double* a);
    unchanged, only the constant pinned right-hand side is recomputed. */
 emu_status emu_set_pin_targets(emu_mesh* mesh, const double* pin_xyz);
 
+/* Constant external vertex forces (Sec. 3.4; gravity is f_v = m_v g): the
+   solve then minimizes the separated energy minus the work f . q*(F) done on
+   the nearest continuous mesh.  f is host [n_vertices][3] (N), user vertex
+   order, copied; forces at pinned vertices do no work; NULL removes the
+   forces.  EMU_E_INVALID for non-finite entries. */
+emu_status emu_set_external_forces(emu_mesh* mesh, const double* f);
+
 /* Replace the low-rank modes (eq. low-rank): k1 = k/3 scalar modes, nu host
    [k1] > 0, phi host [k1][n] (values at pinned vertices are ignored). */
 emu_status emu_set_modes(emu_mesh* mesh, int32_t k1, const double* nu, const double* phi);

@@ -1,10 +1,10 @@
 """EMU quasi-Newton solver in deformation space (oracle part O1), FP64.
 
 Variables: one free deformation gradient F_i per tet (Sec. 3.1).  Objective,
-the separated energy (eq. separated, W = 0):
+the separated energy (eq. separated):
 
-    E(F) = sum_i vol_i Psi_i(F_i) + 1/2 sum_i beta_i |A_i(q*(F)) - F_i|^2,
-    beta_i = alpha w_i,
+    E(F) = sum_i vol_i Psi_i(F_i) + 1/2 sum_i beta_i |A_i(q*(F)) - F_i|^2 - W(q*(F)),
+    beta_i = alpha w_i,  W(q) = f . q  (constant external forces, Sec. 3.4; 0 if unset),
 
 with q*(F) the nearest continuous mesh (eq. acap) and A_i = G_i q.  One
 iteration, in the order of Sec. 3.2.1 and Algorithm 1 (with the readings of its
@@ -56,9 +56,14 @@ def element_energy(M, F, A, a_el):
 
 
 def grad_F(M, F, A, a_el):
-    """Exact dE/dF per element (envelope theorem): vol P(F) + beta (F - A)."""
-    return (M.vol[:, None, None] * mat.pk1(F, M.mu, M.lhat, a_el, M.kf, M.fiber)
-            + M.beta[:, None, None] * (F - A))
+    """Exact dE/dF per element (envelope theorem): vol P(F) + beta (F - A),
+    minus w_i G_i L_ff^{-1} f (the derivative of the external work f . q*(F),
+    Sec. 3.4) when forces are set."""
+    g = (M.vol[:, None, None] * mat.pk1(F, M.mu, M.lhat, a_el, M.kf, M.fiber)
+         + M.beta[:, None, None] * (F - A))
+    if M.vext is not None:
+        g = g - M.w[:, None, None] * msh.gather_A(M, M.vext)
+    return g
 
 
 def frame_basis(R):
@@ -131,11 +136,12 @@ def direction(M, H, g, chunk=4096, return_parts=False):
     return d
 
 
-def delta_energy(M, F, P, sigma, A, A_t, a_el):
+def delta_energy(M, F, P, sigma, A, A_t, a_el, dwork=0.0):
     """E(F + sigma P) - E(F) as a compensated sum of per-element differences.
     Each element difference is expanded exactly in sigma (|F+tP|^2, det(F+tP),
     |(F+tP)u|^2 and the ACAP residual) so that no two total energies are
-    subtracted; A_t is the trial's compatible gradient from its own ACAP solve."""
+    subtracted; A_t is the trial's compatible gradient from its own ACAP solve
+    and dwork = W(q_t) - W(q) the change of the external work."""
     t = sigma
     J = np.linalg.det(F)
     dJ = (t * np.einsum("iab,iab->i", mat.cof(F), P) + t * t * np.einsum("iab,iab->i", F, mat.cof(P))
@@ -149,7 +155,7 @@ def delta_energy(M, F, P, sigma, A, A_t, a_el):
     D = A - F
     dD = (A_t - A) - t * P
     dacap = 0.5 * M.beta * np.einsum("icd,icd->i", dD, 2 * D + dD)
-    return math.fsum(M.vol * dpsi + dacap)
+    return math.fsum(np.append(M.vol * dpsi + dacap, -dwork))
 
 
 def gradient_norm(M, F, a_el):
@@ -178,7 +184,7 @@ def solve(M, a, F0=None, tol=1e-8, max_iters=5000, sigma0=10.0, armijo_c=1e-4, r
         A = msh.gather_A(M, q)
         G = grad_F(M, F, A, a_el)
         gnorm = math.sqrt(math.fsum((G * G).reshape(-1)))
-        E0 = math.fsum(element_energy(M, F, A, a_el))
+        E0 = math.fsum(element_energy(M, F, A, a_el)) - msh.work(M, q)
         if history:
             hist.append(dict(E=E0, gnorm=gnorm))
         if callback is not None:
@@ -213,7 +219,10 @@ def solve(M, a, F0=None, tol=1e-8, max_iters=5000, sigma0=10.0, armijo_c=1e-4, r
                 stats["solves"] += 1
                 At = msh.gather_A(M, qt)
             stats["trials"] += 1
-            if delta_energy(M, F, P, sigma, A, At, a_el) <= armijo_c * sigma * gp:
+            dwork = 0.0
+            if M.fext is not None:
+                dwork = math.fsum((M.fext[M.free] * (qt - q)[M.free]).reshape(-1))
+            if delta_energy(M, F, P, sigma, A, At, a_el, dwork) <= armijo_c * sigma * gp:
                 accepted = True
                 break
             sigma *= rho

@@ -14,6 +14,12 @@ hess_A e = beta I - beta^2 (vol d2Psi(X*) + beta I)^{-1}.
 
 O3 -- plain FEM on sum_i vol_i Psi_i(G_i q), the continuous problem of
 eq. continuum discretized with linear tets; EMU approaches it as alpha grows.
+
+External forces (Sec. 3.4).  EMU's energy subtracts the work f . q*(F) of
+constant vertex forces through the nearest continuous mesh; since
+f . q*(F) = sum_i nu_i . F_i + const with nu_i = w_i G_i L_ff^{-1} f, the joint
+form above gains -nu_i . X in each element's prox (same minimizer, O2).  O3
+subtracts f . q directly (the alpha -> infinity limit of the same term).
 """
 from __future__ import annotations
 
@@ -48,18 +54,32 @@ def _scatter_grad(M, GA):
     return out
 
 
-def prox(M, A, a_el, tol=1e-13, max_iters=100):
-    """X* = argmin_X vol Psi(X) + 1/2 beta |A - X|^2 per element (damped Newton from X = A)."""
+def force_field(M):
+    """nu_i = w_i G_i L_ff^{-1} f: the deformation-space form of the external
+    work, f . q*(F) = sum_i nu_i . F_i + const (zero without forces)."""
+    if M.vext is None:
+        return np.zeros((M.m, 3, 3))
+    return M.w[:, None, None] * msh.gather_A(M, M.vext)
+
+
+def prox(M, A, a_el, tol=1e-13, max_iters=100, nu=None):
+    """X* = argmin_X vol Psi(X) + 1/2 beta |A - X|^2 - nu . X per element
+    (damped Newton from X = A; nu = 0 without external forces)."""
     X = A.copy()
     vol, beta = M.vol, M.beta
+    nu = np.zeros_like(A) if nu is None else nu
 
     def obj(X):
         D = A - X
-        return vol * mat.psi(X, M.mu, M.lhat, a_el, M.kf, M.fiber) + 0.5 * beta * np.einsum("icd,icd->i", D, D)
+        # the work term relative to X = A: the same minimizer without a large
+        # constant in the values the line search compares
+        return (vol * mat.psi(X, M.mu, M.lhat, a_el, M.kf, M.fiber) + 0.5 * beta * np.einsum("icd,icd->i", D, D)
+                + np.einsum("icd,icd->i", nu, D))
 
     scale = beta * (1.0 + np.sqrt(np.einsum("icd,icd->i", A, A)))
     for _ in range(max_iters):
-        g = vol[:, None, None] * mat.pk1(X, M.mu, M.lhat, a_el, M.kf, M.fiber) + beta[:, None, None] * (X - A)
+        g = (vol[:, None, None] * mat.pk1(X, M.mu, M.lhat, a_el, M.kf, M.fiber) + beta[:, None, None] * (X - A)
+             - nu)
         gn = np.sqrt(np.einsum("icd,icd->i", g, g))
         if np.all(gn <= tol * scale):
             break
@@ -69,8 +89,15 @@ def prox(M, A, a_el, tol=1e-13, max_iters=100):
         f0 = obj(X)
         t = np.ones(M.m)
         for _ls in range(30):
-            f1 = obj(X + t[:, None, None] * step)
+            Xt = X + t[:, None, None] * step
+            f1 = obj(Xt)
             bad = f1 > f0 + 1e-4 * t * np.einsum("icd,icd->i", g, step) + 1e-15 * np.abs(f0)
+            if bad.any():
+                # near the minimizer the decrease of the objective falls below
+                # its rounding; a step that shrinks the gradient is then taken
+                gt = (vol[:, None, None] * mat.pk1(Xt, M.mu, M.lhat, a_el, M.kf, M.fiber)
+                      + beta[:, None, None] * (Xt - A) - nu)
+                bad &= np.sqrt(np.einsum("icd,icd->i", gt, gt)) >= 0.5 * gn
             if not bad.any():
                 break
             t = np.where(bad, 0.5 * t, t)
@@ -86,11 +113,14 @@ def moreau_solve(M, a, q0=None, tol=1e-10, max_iters=200, history=False):
     q[M.pins] = M.pin_xyz
     hist = []
 
+    nu = force_field(M)
+
     def Ehat(q):
         A = msh.gather_A(M, q)
-        X, H = prox(M, A, a_el)
+        X, H = prox(M, A, a_el, nu=nu)
         D = A - X
-        e = M.vol * mat.psi(X, M.mu, M.lhat, a_el, M.kf, M.fiber) + 0.5 * M.beta * np.einsum("icd,icd->i", D, D)
+        e = (M.vol * mat.psi(X, M.mu, M.lhat, a_el, M.kf, M.fiber) + 0.5 * M.beta * np.einsum("icd,icd->i", D, D)
+             - np.einsum("icd,icd->i", nu, X))
         return math.fsum(e), A, X, H
 
     E, A, X, H = Ehat(q)
@@ -134,13 +164,16 @@ def fem_solve(M, a, q0=None, tol=1e-10, max_iters=200):
 
     def energy(q):
         A = msh.gather_A(M, q)
-        return math.fsum(M.vol * mat.psi(A, M.mu, M.lhat, a_el, M.kf, M.fiber)), A
+        return math.fsum(M.vol * mat.psi(A, M.mu, M.lhat, a_el, M.kf, M.fiber)) - msh.work(M, q), A
 
     E, A = energy(q)
     it = 0
     while True:
         P = M.vol[:, None, None] * mat.pk1(A, M.mu, M.lhat, a_el, M.kf, M.fiber)
-        grad = _scatter_grad(M, P)[M.free].reshape(-1)
+        grad = _scatter_grad(M, P)[M.free]
+        if M.fext is not None:
+            grad = grad - M.fext[M.free]
+        grad = grad.reshape(-1)
         gn = float(np.linalg.norm(grad))
         if gn <= tol or it >= max_iters:
             break

@@ -12,10 +12,13 @@
   rigid null space (Sec. 3.1).
 * Low-rank modes (eq. low-rank): the 16 lowest eigenpairs of L_ff, used as the
   48 coordinate modes e_c (x) phi_j.
+* External forces (Sec. 3.4): constant vertex forces f do the work
+  W(q) = sum_{v free} f_v . q_v; forces at pinned vertices do no work.
 """
 from __future__ import annotations
 
 import dataclasses
+import math
 
 import numpy as np
 import scipy.sparse as sp
@@ -49,6 +52,8 @@ class Mesh:
     lu: object              # factor of Lff
     nu: np.ndarray = None   # mode eigenvalues [k/3]
     phi: np.ndarray = None  # modes [k/3, n_f]
+    fext: np.ndarray = None  # external vertex forces [n,3] (None: W = 0)
+    vext: np.ndarray = None  # L_ff^{-1} f at free vertices, 0 at pins [n,3]
 
     @property
     def n(self):
@@ -180,3 +185,25 @@ def acap_solve(M, F, pinned=True):
 def acap_energy(M, q, F):
     D = gather_A(M, q) - F
     return 0.5 * np.sum(M.w * np.einsum("icd,icd->i", D, D))
+
+
+def set_external_forces(M, f):
+    """Constant external vertex forces f [n,3] (None removes them).  Also keeps
+    v = L_ff^{-1} f_f, the vertex field whose weighted gradient w_i G_i v is the
+    derivative of f . q*(F) with respect to F_i."""
+    if f is None:
+        M.fext = M.vext = None
+        return M
+    f = np.array(f, dtype=np.float64).reshape(M.n, 3)
+    M.fext = f
+    v = np.zeros((M.n, 3))
+    v[M.free] = M.lu.solve(np.asarray(f[M.free], order="F"))
+    M.vext = v
+    return M
+
+
+def work(M, q):
+    """External work W(q) = sum over free vertices of f . q (0 without forces)."""
+    if M.fext is None:
+        return 0.0
+    return math.fsum((M.fext[M.free] * q[M.free]).reshape(-1))

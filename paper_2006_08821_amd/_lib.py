@@ -89,6 +89,7 @@ SIGNATURES = {
     "emu_mesh_get_info": (C.c_int, [P, C.POINTER(MeshInfo)]),
     "emu_set_activation": (C.c_int, [P, DP]),
     "emu_set_pin_targets": (C.c_int, [P, DP]),
+    "emu_set_external_forces": (C.c_int, [P, DP]),
     "emu_set_modes": (C.c_int, [P, C.c_int32, DP, DP]),
     "emu_get_modes": (C.c_int, [P, DP, DP]),
     "emu_solve": (C.c_int, [P, C.POINTER(SolveOpts), P, C.POINTER(SolveStats), P]),

@@ -100,7 +100,9 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
   d.npins = hm.npins;
   d.ngroups = hm.ngroups;
   d.nb = std::max(1, std::min((m + emu::kBlock - 1) / emu::kBlock, 1024));
-  d.nbg = std::max(1, std::min((m + 63) / 64, 1024));
+  // Gram workgroups: one round at two workgroups per compute unit (fewer
+  // partial sums for the reduction that follows)
+  d.nbg = std::max(1, std::min((m + 63) / 64, 512));
   d.mixed = hm.precision == EMU_PRECISION_MIXED;
   d.alpha = hm.alpha;
   d.kf = hm.kf;
@@ -148,6 +150,7 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
     B.put(SLOT(nu), nu);
     std::vector<double> act(std::max(1, hm.ngroups), 0.0);
     B.put(SLOT(act), act);
+    B.put(SLOT(vext), zeros3);
     B.put(SLOT(pin_rhs), hm.pin_rhs);
     B.put(SLOT(pin_xyz), hm.pin_xyz);
   }
@@ -202,8 +205,9 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
     pl.bwd_ptr.assign(fac.nlevels + 1, 0);
     // Backward levels with few work items at 32 columns per item split the
     // supernodes with long rows into items of 8 (32 lanes per row) instead.
-    // Forward items stay at 32 rows: each item assembles its frontal vector
-    // from the children's updates, which narrower items would repeat.
+    // Forward items stay at 32 rows (each item assembles its frontal vector
+    // from the children's updates, which narrower items would repeat) except
+    // for wide root supernodes, whose few items would otherwise serialize.
     auto sparse_level = [&](int L, bool fwd_dir) {
       int64_t items = 0;
       for (int s = 0; s < fac.ns; ++s)
@@ -213,7 +217,7 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
     for (int L = 0; L < fac.nlevels; ++L) {
       for (int s = 0; s < fac.ns; ++s)
         if (fac.level[s] == L) {
-          const bool wide = false;
+          const bool wide = fac.parent[s] < 0 && fac.w[s] >= 256;
           const int step = wide ? 8 : 32;
           for (int r = 0; r < fac.h[s]; r += step) fwd.push_back(make_int2(s, r | (wide ? emu::kItemWideBit : 0)));
         }
@@ -381,6 +385,21 @@ void emu::launch_to_user_q(emu_mesh* M, double* out) {
 
 namespace {
 
+void update_ext_constant(emu_mesh* M) {
+  double c = 0;
+  for (size_t k = 0; k < M->vext.size(); ++k) c += M->vext[k] * M->hm.pin_rhs[k];
+  M->ext_c0 = c;
+}
+
+void drop_graph(emu_mesh* M) {  // kernels take the mesh by value: rebuild the graph
+  if (M->gexec) {
+    HIPCHK(hipGraphExecDestroy(M->gexec));
+    HIPCHK(hipGraphDestroy(M->graph));
+    M->gexec = nullptr;
+    M->graph = nullptr;
+  }
+}
+
 void backup_state(emu_mesh* M) {
   const size_t m = M->hm.m, n = M->hm.n;
   if (!M->R_bak) {
@@ -516,8 +535,49 @@ emu_status emu_set_pin_targets(emu_mesh* M, const double* pin_xyz) {
       if (!std::isfinite(pin_xyz[i])) throw emu::Error{EMU_E_INVALID, "non-finite pin target"};
     M->hm.pin_xyz.assign(pin_xyz, pin_xyz + 3 * (size_t)M->hm.npins);
     emu::recompute_pin_rhs(M->hm);
+    update_ext_constant(M);
     HIPCHK(hipStreamSynchronize(M->st));
     upload_pins(M);
+    M->converged = false;
+    return EMU_OK;
+  } catch (const emu::Error& e) {
+    return fail_with(e);
+  }
+}
+
+emu_status emu_set_external_forces(emu_mesh* M, const double* f) {
+  if (!M) {
+    emu::set_error("NULL argument");
+    return EMU_E_INVALID;
+  }
+  try {
+    const auto& hm = M->hm;
+    const int32_t n = hm.n, nf = hm.nf;
+    if (!f) {
+      M->vext.clear();
+      M->ext_c0 = 0;
+      HIPCHK(hipStreamSynchronize(M->st));
+      HIPCHK(hipMemset((void*)M->d.vext, 0, 24 * (size_t)n));
+      M->d.has_ext = 0;
+      drop_graph(M);
+      M->converged = false;
+      return EMU_OK;
+    }
+    for (int64_t k = 0; k < 3 * (int64_t)n; ++k)
+      if (!std::isfinite(f[k])) throw emu::Error{EMU_E_INVALID, "non-finite external force"};
+    // v = L_ff^{-1} f_f in factor order (three right-hand sides)
+    std::vector<double> b(3 * (size_t)nf), v(3 * (size_t)nf);
+    for (int32_t i = 0; i < nf; ++i)
+      for (int c = 0; c < 3; ++c) b[3 * (size_t)i + c] = f[3 * (size_t)hm.vold[i] + c];
+    emu::host_factor_solve(hm.fac, 3, b.data(), v.data());
+    M->vext = v;
+    update_ext_constant(M);
+    std::vector<double> full(3 * (size_t)n, 0.0);
+    std::copy(v.begin(), v.end(), full.begin());
+    HIPCHK(hipStreamSynchronize(M->st));
+    HIPCHK(hipMemcpy((void*)M->d.vext, full.data(), full.size() * 8, hipMemcpyHostToDevice));
+    M->d.has_ext = 1;
+    drop_graph(M);
     M->converged = false;
     return EMU_OK;
   } catch (const emu::Error& e) {
@@ -609,6 +669,7 @@ emu_status emu_solve(emu_mesh* M, const emu_solve_opts* opts, double* q_out, emu
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, M->ev_t0, M->ev_t1));
     emu::fill_stats(*M->h_ctl, stats, ms);
+    if (stats) stats->energy -= M->ext_c0;
     release_user_stream(M, stream);
     emu_status st = (emu_status)M->h_ctl->status;
     M->converged = st == EMU_OK;
@@ -683,7 +744,7 @@ emu_status emu_evaluate(emu_mesh* M, const double* F, double* q, double* energy,
     HIPCHK(hipStreamSynchronize(M->st));
     HIPCHK(hipGetLastError());
     release_user_stream(M, stream);
-    if (energy) *energy = M->h_ctl->energy;
+    if (energy) *energy = M->h_ctl->energy - M->ext_c0;
     if (grad_norm) *grad_norm = std::sqrt(std::max(0.0, M->h_ctl->gnorm2));
     return EMU_OK;
   } catch (const emu::Error& e) {

@@ -50,6 +50,7 @@ struct DevMesh {
   int32_t nb;          // workgroups of the element passes (fixed: deterministic sums)
   int32_t nbg;         // workgroups of the Woodbury Gram pass
   int32_t mixed;       // FP32 element Hessian / Gram / direction
+  int32_t has_ext;     // external vertex forces set (vext nonzero)
   double alpha, kf;
 
   // elements, internal order, structure of arrays
@@ -75,6 +76,7 @@ struct DevMesh {
   const double* phi;      // [n][16]
   const double* nu;       // [16]
   const double* act;      // [ngroups]
+  const double* vext;     // [n][3] L_ff^{-1} f at free vertices, 0 at pins
   const double* pin_rhs;  // [nf][3]
   const double* pin_xyz;  // [npins][3]  (internal ids nf..n-1)
   const int32_t* inc_ptr; // [nf+1]

@@ -864,7 +864,23 @@ DEV void b_element(const DevMesh& d, int bid) {
     const double afk = e.a * d.kf;
     const double psi = 0.5 * e.mu * (trSS - 3.0) - e.mu * (J - 1.0) + 0.5 * e.lhat * (J - 1.0) * (J - 1.0) +
                        afk * (Su[0] * Su[0] + Su[1] * Su[1] + Su[2] * Su[2]);
-    acc[0] = dd_add_d(acc[0], e.vol * psi + 0.5 * beta * dres);
+    // external work (Sec. 3.4): f . q*(F) = sum_i nu_i . F_i + const with
+    // nu_i = w_i G_i L_ff^{-1} f; in the rotated frame nu_rot = R^T nu
+    double nur[9];
+    if (d.has_ext) {
+      double nu[9];
+      gather_grad(d.vext, e, nu);
+      matTmul3(R, nu, nur);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) nur[k] *= e.w;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) nur[k] = 0.0;
+    }
+    double wext = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) wext += nur[k] * S[k];
+    acc[0] = dd_add_d(acc[0], e.vol * psi + 0.5 * beta * dres - wext);
     ninv += (J <= 0.0);
     const double kap = e.lhat * (J - 1.0) - e.mu;
     double G[9];
@@ -873,7 +889,7 @@ DEV void b_element(const DevMesh& d, int bid) {
 #pragma unroll
       for (int b = 0; b < 3; ++b)
         G[3 * a + b] = e.vol * (e.mu * S[3 * a + b] + kap * C[3 * a + b] + 2.0 * afk * Su[a] * e.u[b]) +
-                       beta * (S[3 * a + b] - At[3 * a + b]);
+                       beta * (S[3 * a + b] - At[3 * a + b]) - nur[3 * a + b];
     double gn = 0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) gn += G[k] * G[k];
@@ -1166,35 +1182,38 @@ DEV void b_gram(const DevMesh& d, int bid) {
 #pragma unroll
       for (int q = 0; q < 9; ++q) zw[lane][54 + q] = (T)RD[q];
       zw[lane][63] = (T)d.w[i];
-      // mode gradients gphi_j = sum_v phi_j(v) b_v, all 16 modes (zero rows
-      // of phi beyond k1)
-      double b[4][3];
+    }
+    {
+      // mode gradients gphi_j = sum_v phi_j(v) b_v: four lanes per element,
+      // four modes each (rows of phi are zero beyond k1 and at pins)
+      const int el = lane >> 2, q4 = 4 * (lane & 3);
+      if (el < ne) {
+        const int i = base + el;
+        double b[4][3];
 #pragma unroll
-      for (int v = 0; v < 3; ++v)
+        for (int v = 0; v < 3; ++v)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) b[v][c] = d.dminv[(3 * v + c) * m + i];
+          for (int c = 0; c < 3; ++c) b[v][c] = d.dminv[(3 * v + c) * m + i];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) b[3][c] = -(b[0][c] + b[1][c] + b[2][c]);
-      double gg[kMaxK1][3];
+        for (int c = 0; c < 3; ++c) b[3][c] = -(b[0][c] + b[1][c] + b[2][c]);
+        double gg[4][3];
 #pragma unroll
-      for (int q = 0; q < kMaxK1; ++q) gg[q][0] = gg[q][1] = gg[q][2] = 0.0;
+        for (int q = 0; q < 4; ++q) gg[q][0] = gg[q][1] = gg[q][2] = 0.0;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const double2* ph = reinterpret_cast<const double2*>(d.phi + (int64_t)kMaxK1 * d.vid[v * m + i]);
+        for (int v = 0; v < 4; ++v) {
+          const double2* ph = reinterpret_cast<const double2*>(d.phi + (int64_t)kMaxK1 * d.vid[v * m + i] + q4);
+          const double2 p0 = ph[0], p1 = ph[1];
+          const double pv[4] = {p0.x, p0.y, p1.x, p1.y};
 #pragma unroll
-        for (int q2 = 0; q2 < kMaxK1 / 2; ++q2) {
-          const double2 pv = ph[q2];
+          for (int q = 0; q < 4; ++q)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            gg[2 * q2][c] += pv.x * b[v][c];
-            gg[2 * q2 + 1][c] += pv.y * b[v][c];
-          }
+            for (int c = 0; c < 3; ++c) gg[q][c] += pv[q] * b[v][c];
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) gw[el][3 * (q4 + q) + c] = q4 + q < k1 ? (T)gg[q][c] : T(0);
       }
-#pragma unroll
-      for (int q = 0; q < kMaxK1; ++q)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) gw[lane][3 * q + c] = q < k1 ? (T)gg[q][c] : T(0);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1393,7 +1412,7 @@ DEV void b_control_a(const DevMesh& d, int bid) {
   for (int q = 0; q < kOwn; ++q)
     if (ec[q] < 48) Cm[er[q]][ec[q]] = ev[q];
   __syncthreads();
-  __shared__ double piv[48];
+  __shared__ double piv[48], invp[48];
   __shared__ int nbad;
   if (t == 0) nbad = 0;
   __syncthreads();
@@ -1401,6 +1420,7 @@ DEV void b_control_a(const DevMesh& d, int bid) {
     const double dj = Cm[t][t];
     if (!(dj > 0)) atomicAdd(&nbad, 1);
     piv[t] = dj > 0 ? sqrt(dj) : 1.0;
+    invp[t] = 1.0 / piv[t];
   }
   __syncthreads();
   for (int idx = t; idx < 48 * 48; idx += kCtlThreads) {
@@ -1419,12 +1439,12 @@ DEV void b_control_a(const DevMesh& d, int bid) {
   // entry is broadcast with readlane
   double yt = t < 48 ? yv[t] : 0.0;
   for (int i = 0; i < 48; ++i) {
-    const double ui = bcast_lane(yt, i) / Cm[i][i];
+    const double ui = bcast_lane(yt, i) * invp[i];
     if (t == i) yt = ui;
     else if (t > i && t < 48) yt -= Cm[t][i] * ui;
   }
   for (int i = 47; i >= 0; --i) {
-    const double zi = bcast_lane(yt, i) / Cm[i][i];
+    const double zi = bcast_lane(yt, i) * invp[i];
     if (t == i) yt = zi;
     else if (t < i) yt -= Cm[i][t] * zi;
   }
@@ -1582,6 +1602,16 @@ DEV void b_lscoef(const DevMesh& d, int bid) {
     for (int k = 0; k < 6; ++k) c[k] *= e.vol;
     c[0] += beta * r1;
     c[1] += 0.5 * beta * r2;
+    if (d.has_ext) {
+      // change of the external work along the step: nu . dF = (R^T nu) . D
+      double nu[9], nur[9];
+      gather_grad(d.vext, e, nu);
+      matTmul3(R, nu, nur);
+      double wd = 0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) wd += nur[k] * D[k];
+      c[0] -= e.w * wd;
+    }
 #pragma unroll
     for (int k = 0; k < 6; ++k) acc[k] = dd_add_d(acc[k], c[k]);
   }

@@ -69,6 +69,10 @@ struct emu_mesh {
   int graph_iters = 0;
   std::vector<double> act;
   bool converged = false;
+  // external forces: L_ff^{-1} f (factor order, free vertices) and the
+  // constant part of the work, f . q* = sum_i nu_i . F_i + ext_c0
+  std::vector<double> vext;
+  double ext_c0 = 0;
   // backup of the state for emu_evaluate
   double *R_bak = nullptr, *S_bak = nullptr, *q_bak = nullptr;
   // adjoint work arrays (allocated on first use)

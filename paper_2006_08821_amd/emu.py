@@ -166,6 +166,14 @@ class Mesh:
         p = np.ascontiguousarray(pin_xyz, np.float64)
         check(self._lib.emu_set_pin_targets(self._h, dptr(p)), "emu_set_pin_targets")
 
+    def set_external_forces(self, f):
+        """Constant vertex forces [n,3] (N), or None to remove them."""
+        if f is None:
+            check(self._lib.emu_set_external_forces(self._h, None), "emu_set_external_forces")
+            return
+        f = np.ascontiguousarray(f, np.float64).reshape(self.n, 3)
+        check(self._lib.emu_set_external_forces(self._h, dptr(f)), "emu_set_external_forces")
+
     def set_modes(self, nu, phi):
         nu = np.ascontiguousarray(nu, np.float64)
         phi = np.ascontiguousarray(phi, np.float64)

@@ -221,3 +221,59 @@ def test_full_size_limb_evaluate(torch):
     assert math.isclose(ev["grad_norm"], gn, rel_tol=1e-6)
     dg = ev["direction"].cpu().numpy()
     assert np.abs(dg - d).max() <= 1e-6 * np.abs(d).max()
+
+
+def _forces(M, seed=4, scale=1.0):
+    rng = np.random.default_rng(seed)
+    f = np.zeros((M.n, 3))
+    f[:, 0] = -0.02 * scale
+    f[:, 2] = 0.01 * scale * rng.normal(size=M.n)
+    return f
+
+
+def test_evaluate_with_external_forces(torch):
+    # Sec. 3.4: the work f . q*(F) adds -w G L^{-1} f to dE/dF and a linear
+    # term to the energy; q*, E, |g| and the direction against the oracle
+    p = wl.limb(4, 4, 12, n_groups=4, activation=[0.3, 0.6, 0.1, 0.9])
+    M = omesh.build(p)
+    f = _forces(M)
+    omesh.set_external_forces(M, f)
+    mesh = _mesh(p)
+    _share_modes(mesh, M)
+    mesh.set_external_forces(f)
+    rng = np.random.default_rng(12)
+    F = np.eye(3) + 0.05 * rng.normal(size=(M.m, 3, 3))
+    ev = mesh.evaluate(F)
+    a_el = omesh.activation_per_element(M, p.activation)
+    q = omesh.acap_solve(M, F)
+    A = omesh.gather_A(M, q)
+    E = math.fsum(oemu.element_energy(M, F, A, a_el)) - omesh.work(M, q)
+    g = oemu.grad_F(M, F, A, a_el)
+    gn = math.sqrt(math.fsum((g * g).reshape(-1)))
+    H = oemu.block_hessian(M, F, a_el, "split")
+    d = oemu.direction(M, H, g.reshape(M.m, 9)).reshape(M.m, 3, 3)
+    assert np.abs(ev["q"].cpu().numpy() - q).max() <= 1e-12 * np.abs(q).max()
+    assert math.isclose(ev["energy"], E, rel_tol=1e-11)
+    assert math.isclose(ev["grad_norm"], gn, rel_tol=1e-10)
+    assert np.abs(ev["direction"].cpu().numpy() - d).max() <= 1e-8 * np.abs(d).max()
+    # removing the forces restores the force-free evaluation
+    mesh.set_external_forces(None)
+    omesh.set_external_forces(M, None)
+    ev0 = mesh.evaluate(F)
+    E0 = math.fsum(oemu.element_energy(M, F, A, a_el))
+    assert math.isclose(ev0["energy"], E0, rel_tol=1e-11)
+
+
+def test_box_beam_solve_with_external_forces(torch):
+    # a loaded box beam: the converged positions equal the oracle's Moreau
+    # Newton minimizer with the same forces
+    p = wl.box_beam(activation=0.3)
+    M = omesh.build(p, modes=False)
+    f = _forces(M)
+    omesh.set_external_forces(M, f)
+    mesh = _mesh(p)
+    mesh.set_external_forces(f)
+    q, st = mesh.solve(grad_tol=1e-8, max_iters=4000)
+    assert st["status"] == 0, st
+    ref = ofem.moreau_solve(M, p.activation, tol=1e-11)["q"]
+    assert _disp_err(q.cpu().numpy(), ref, M.rest) <= 1e-6

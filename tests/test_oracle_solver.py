@@ -267,3 +267,97 @@ def test_adjoint_matches_finite_differences():
         Lp = adjoint.marker_loss(fem.moreau_solve(M, ap, q0=q, tol=1e-13)["q"], markers, target)[0]
         Lm = adjoint.marker_loss(fem.moreau_solve(M, am, q0=q, tol=1e-13)["q"], markers, target)[0]
         assert math.isclose((Lp - Lm) / (2 * h), g[k], rel_tol=1e-4, abs_tol=1e-12)
+
+
+# ---------------------------------------------------------------- external forces (Sec. 3.4)
+def _gravity_like(M, seed=4, scale=1.0):
+    rng = np.random.default_rng(seed)
+    f = np.zeros((M.n, 3))
+    f[:, 0] = -0.02 * scale
+    f[:, 2] = 0.01 * scale * rng.normal(size=M.n)
+    return f
+
+
+def test_external_work_gradient_matches_finite_differences():
+    # dE/dF of E(F) - f . q*(F): the work term enters as -w_i G_i L_ff^{-1} f
+    p = wl.tiny("cube2", activation=0.3)
+    M = msh.build(p)
+    msh.set_external_forces(M, _gravity_like(M))
+    a_el = msh.activation_per_element(M, p.activation)
+    F = np.eye(3) + 0.1 * RNG.normal(size=(M.m, 3, 3))
+
+    def E(F):
+        q = msh.acap_solve(M, F)
+        return math.fsum(emu.element_energy(M, F, msh.gather_A(M, q), a_el)) - msh.work(M, q)
+
+    q = msh.acap_solve(M, F)
+    g = emu.grad_F(M, F, msh.gather_A(M, q), a_el)
+    h = 1e-7
+    for i, c, d in [(0, 0, 0), (3, 1, 2), (7, 2, 1), (11, 0, 2)]:
+        Fp, Fm = F.copy(), F.copy()
+        Fp[i, c, d] += h
+        Fm[i, c, d] -= h
+        fd = (E(Fp) - E(Fm)) / (2 * h)
+        assert math.isclose(fd, g[i, c, d], rel_tol=1e-6, abs_tol=1e-12)
+
+
+def test_emu_with_forces_equals_moreau_newton():
+    # the force enters the joint (F, q) form as -nu_i . F_i; EMU and the
+    # Moreau Newton solve reach the same minimizer
+    p = wl.box_beam(2, 2, 8, activation=0.3)
+    M = msh.build(p)
+    msh.set_external_forces(M, _gravity_like(M))
+    o1 = emu.solve(M, p.activation, tol=1e-10, hessian="split", trials="affine")
+    assert o1["stats"]["converged"]
+    o2 = fem.moreau_solve(M, p.activation, tol=1e-12)
+    assert np.abs(o1["q"] - o2["q"]).max() <= 1e-6 * np.abs(o2["q"] - M.rest).max()
+    # and Algorithm 1's fresh solves per trial agree
+    o1f = emu.solve(M, p.activation, tol=1e-9, hessian="full", trials="fresh")
+    assert np.abs(o1f["q"] - o2["q"]).max() <= 1e-5 * np.abs(o2["q"] - M.rest).max()
+
+
+def _linear_elastic_stiffness(M):
+    # textbook small-strain stiffness of linear tets (Lame mu, lambda), assembled
+    # here from the hat gradients alone: K_i[(v,c),(w,d)] =
+    # vol (mu (delta_cd b_v.b_w + b_v[d] b_w[c]) + lambda b_v[c] b_w[d])
+    import scipy.sparse as sp
+    lam = M.lhat - M.mu
+    bb = np.einsum("ivk,iwk->ivw", M.b, M.b)
+    Ke = (M.mu[:, None, None, None, None] * (np.einsum("ivw,cd->ivcwd", bb, np.eye(3))
+                                              + np.einsum("ivd,iwc->ivcwd", M.b, M.b))
+          + lam[:, None, None, None, None] * np.einsum("ivc,iwd->ivcwd", M.b, M.b))
+    Ke *= M.vol[:, None, None, None, None]
+    dof = (3 * M.tets[:, :, None] + np.arange(3)[None, None, :]).reshape(-1, 12)
+    rows = np.repeat(dof, 12, axis=1).reshape(-1)
+    cols = np.tile(dof, (1, 12)).reshape(-1)
+    K = sp.coo_matrix((Ke.reshape(-1), (rows, cols)), shape=(3 * M.n, 3 * M.n)).tocsr()
+    fdof = (3 * M.free[:, None] + np.arange(3)[None, :]).reshape(-1)
+    return K[fdof][:, fdof].tocsc()
+
+
+def test_small_load_fem_matches_linear_elasticity():
+    # pins the sign and scale of the work term: a tiny load gives the
+    # small-strain displacement K^{-1} f of textbook linear elasticity
+    p = wl.box_beam(2, 2, 8, activation=0.0)
+    M = msh.build(p, modes=False)
+    f = _gravity_like(M, scale=1e-3)
+    msh.set_external_forces(M, f)
+    q = fem.fem_solve(M, np.zeros(1), tol=1e-14)["q"]
+    K = _linear_elastic_stiffness(M)
+    u = spla.spsolve(K, f[M.free].reshape(-1)).reshape(-1, 3)
+    du = q[M.free] - M.rest[M.free]
+    assert np.abs(du - u).max() <= 1e-3 * np.abs(u).max()
+
+
+def test_forces_alpha_to_infinity_approaches_fem():
+    p = wl.tiny("grid224", activation=0.0)
+    gaps = []
+    Mf = msh.build(p, modes=False)
+    f = _gravity_like(Mf, scale=0.1)
+    msh.set_external_forces(Mf, f)
+    qf = fem.fem_solve(Mf, np.zeros(1), tol=1e-12)["q"]
+    for ah in (10.0, 100.0, 1000.0):
+        M = msh.build(p, alpha_hat=ah, modes=False)
+        msh.set_external_forces(M, f)
+        gaps.append(np.abs(fem.moreau_solve(M, np.zeros(1), tol=1e-10, max_iters=60)["q"] - qf).max())
+    assert gaps[1] < 0.2 * gaps[0] and gaps[2] < 0.2 * gaps[1]
