@@ -1371,13 +1371,18 @@ DEV void b_control_a(const DevMesh& d, int bid) {
   }
   __syncthreads();
   if (flag || K == 0) return;
-  // Cholesky of the padded 48 x 48 system by the whole workgroup, one barrier
-  // per column.  Thread t owns the lower-triangle entries e = t + 256 q (kept
-  // in registers); step j subtracts C[r][j] C[c][j] / C[j][j] from every owned
-  // (r, c) with c > j and publishes column j + 1 through LDS.  The columns are
-  // scaled by 1 / sqrt(C[j][j]) at the end.  A non-positive pivot marks the
+  // Blocked Cholesky of the padded 48 x 48 system by the whole workgroup, in
+  // panels of four columns (two barriers per panel).  Phase A: every thread
+  // factors the 4x4 diagonal block (redundantly, from LDS) and thread t
+  // solves its row of the panel, L[t][jb..jb+3], into LDS.  Phase B: thread
+  // t owns the lower-triangle entries e = t + 256 q (kept in registers) and
+  // subtracts the panel's rank-4 product from those right of the panel; the
+  // entries of the next panel go to LDS.  A non-positive pivot marks the
   // system as failed (z = 0 below).
+  constexpr int NB = 4;
   constexpr int kOwn = (48 * 49 / 2 + kCtlThreads - 1) / kCtlThreads;
+  __shared__ double invp[48];
+  __shared__ int nbad;
   int er[kOwn], ec[kOwn];
   double ev[kOwn];
 #pragma unroll
@@ -1390,44 +1395,58 @@ DEV void b_control_a(const DevMesh& d, int bid) {
     ec[q] = e >= 0 ? e - r * (r + 1) / 2 : 48;  // 48: not owned
     ev[q] = e >= 0 ? Cm[er[q]][ec[q]] : 0.0;
   }
-  for (int j = 0; j < 47; ++j) {
-    const double dj = Cm[j][j];
-    const double inv = dj > 0 ? 1.0 / dj : 0.0;
-    double lr[kOwn], lc[kOwn];
+  int nbad_local = 0;
+  for (int jb = 0; jb < 48; jb += NB) {
+    double Lb[NB][NB], rdg[NB];
 #pragma unroll
-    for (int q = 0; q < kOwn; ++q) {
-      const bool act = ec[q] > j && ec[q] < 48;
-      lr[q] = act ? Cm[er[q]][j] : 0.0;
-      lc[q] = act ? Cm[ec[q]][j] : 0.0;
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j) {
+        double x = Cm[jb + i][jb + j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) x -= Lb[i][k] * Lb[j][k];
+        if (i == j) {
+          nbad_local += !(x > 0);
+          Lb[i][i] = x > 0 ? sqrt(x) : 1.0;
+          rdg[i] = 1.0 / Lb[i][i];
+        } else {
+          Lb[i][j] = x * rdg[j];
+        }
+      }
+    if (t >= jb && t < 48) {
+      if (t < jb + NB) {
+        const int i = t - jb;
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          if (j <= i) Cm[t][jb + j] = Lb[i][j];
+        invp[t] = rdg[i];
+      } else {
+        double l[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          double x = Cm[t][jb + k];
+#pragma unroll
+          for (int m = 0; m < k; ++m) x -= l[m] * Lb[k][m];
+          l[k] = x * rdg[k];
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k) Cm[t][jb + k] = l[k];
+      }
     }
-    // (column j + 1 is written while column j is read: disjoint entries)
+    __syncthreads();
 #pragma unroll
     for (int q = 0; q < kOwn; ++q) {
-      ev[q] -= lr[q] * lc[q] * inv;
-      if (ec[q] == j + 1) Cm[er[q]][ec[q]] = ev[q];
+      if (ec[q] >= jb + NB && ec[q] < 48) {
+        double s = 0;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) s += Cm[er[q]][jb + k] * Cm[ec[q]][jb + k];
+        ev[q] -= s;
+        if (ec[q] < jb + 2 * NB) Cm[er[q]][ec[q]] = ev[q];
+      }
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int q = 0; q < kOwn; ++q)
-    if (ec[q] < 48) Cm[er[q]][ec[q]] = ev[q];
-  __syncthreads();
-  __shared__ double piv[48], invp[48];
-  __shared__ int nbad;
-  if (t == 0) nbad = 0;
-  __syncthreads();
-  if (t < 48) {
-    const double dj = Cm[t][t];
-    if (!(dj > 0)) atomicAdd(&nbad, 1);
-    piv[t] = dj > 0 ? sqrt(dj) : 1.0;
-    invp[t] = 1.0 / piv[t];
-  }
-  __syncthreads();
-  for (int idx = t; idx < 48 * 48; idx += kCtlThreads) {
-    const int r = idx / 48, c = idx % 48;
-    if (c < r) Cm[r][c] /= piv[c];
-    else if (c == r) Cm[r][c] = piv[c];
-  }
+  if (t == 0) nbad = nbad_local;
   __syncthreads();
   const int bad = nbad > 0;
   for (int idx = t; idx < 48 * 48; idx += kCtlThreads) {
