@@ -171,9 +171,36 @@ def run(args):
                          "latency_ms_p99": float(np.percentile(lat, 99))}
     if args.serve > 0:
         out["serving"] = serving(args)
+    if args.alpha_search:
+        out["alpha_search"] = alpha_search_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args)
     return out
+
+
+def alpha_search_leg():
+    """Sec. 3.7 alpha search on the 4x4x16 box beam (a = 0.5): four candidates
+    alpha_hat = 1, 10, 100, 1000 to |g| <= 1e-6 |g_0| (at most 3000
+    iterations), as one batch on the serving loop and one after the other
+    through the single-mesh solve."""
+    import torch
+    from paper_2006_08821_amd import workloads as wl
+    from paper_2006_08821_amd.emu import Mesh, alpha_search
+    p = wl.box_beam(4, 4, 16, activation=0.5)
+    cands = (1.0, 10.0, 100.0, 1000.0)
+    r = alpha_search(p, alpha_hats=cands, grad_rtol=1e-6, max_iters=3000)
+    t0 = time.perf_counter()
+    seq = []
+    for a in cands:
+        pa = p.copy()
+        pa.alpha_hat = a
+        _, st = Mesh(pa).solve(grad_tol=0.0, grad_rtol=1e-6, max_iters=3000, warm_start=0, raise_on_error=False)
+        seq.append(st["iters"])
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    return {"workload": "box beam 4x4x16, a = 0.5", "alpha_hats": list(cands), "iters": r["iters"],
+            "chosen_alpha_hat": r["alpha_hat"], "batched_s": r["wall_s"], "one_at_a_time_s": t_seq,
+            "same_iters": seq == r["iters"]}
 
 
 def serving(args):
@@ -297,6 +324,7 @@ def main():
     ap.add_argument("--serve-rtol", type=float, default=1e-4)
     ap.add_argument("--serve-max-iters", type=int, default=300)
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--alpha-search", type=int, default=1, help="run the alpha-search leg (0: skip)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (for scaling HBM counters)")
     args = ap.parse_args()

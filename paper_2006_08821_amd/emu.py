@@ -341,3 +341,46 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def choose_alpha(alphas, iters, converged, spike=3.0):
+    """The weighting-parameter rule of Sec. 3.7: walk the candidates upward and
+    stop at the first one whose iteration count jumps by more than ``spike``
+    times the previous count (or that does not converge); return the
+    candidate just before the jump (the last candidate if none jumps).
+    ``alphas`` ascending; returns (alpha, index)."""
+    if len(alphas) == 0:
+        raise ValueError("no candidates")
+    for k in range(1, len(alphas)):
+        if not converged[k] or iters[k] > spike * max(1, iters[k - 1]):
+            return alphas[k - 1], k - 1
+    return alphas[-1], len(alphas) - 1
+
+
+def alpha_search(problem, alpha_hats=(1.0, 10.0, 100.0, 1e3, 1e4, 1e5), grad_rtol=1e-6, max_iters=5000,
+                 spike=3.0, precision="fp64", server=None):
+    """Sec. 3.7: solve the problem at its activations once per candidate
+    alpha_hat (cold start, |g| <= grad_rtol |g_0|), all candidates as one
+    batch on the serving loop, and pick alpha_hat by ``choose_alpha``.
+    Returns a dict with the choice, the per-candidate iteration counts and
+    statuses and the wall time of the batch."""
+    import time
+    alphas = sorted(float(a) for a in alpha_hats)
+    own = server is None
+    srv = Server() if own else server
+    t0 = time.perf_counter()
+    tickets = []
+    for a in alphas:
+        p = problem.copy()
+        p.alpha_hat = a
+        tickets.append(srv.submit(p, precision=precision, grad_tol=0.0, grad_rtol=grad_rtol,
+                                  max_iters=max_iters, warm_start=0))
+    res = [srv.wait(t) for t in tickets]
+    wall = time.perf_counter() - t0
+    if own:
+        srv.close()
+    iters = [st["iters"] for _, st, _ in res]
+    conv = [st["status"] == 0 for _, st, _ in res]
+    best, k = choose_alpha(alphas, iters, conv, spike)
+    return {"alpha_hat": best, "index": k, "alpha_hats": alphas, "iters": iters, "converged": conv,
+            "q": res[k][0], "wall_s": wall}
