@@ -58,14 +58,18 @@ GRAM_FLOPS_PER_ELEMENT = 9.6e3   # Z g (9x48x3 MAC) + 1176 x 3 MAC, x2 flops
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (profiles/*.md: FETCH_SIZE and WRITE_SIZE passes scaled by a plain copy
-    kernel), or None when the summary was taken on a different kernel source."""
+    kernel), or None when the summary was taken on a different kernel source
+    or build (the hash covers kernels.hip and the build flags in build.py)."""
     import glob
     import hashlib
-    src = os.path.join(ROOT, "paper_2006_08821_amd", "csrc", "kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    pkg = os.path.join(ROOT, "paper_2006_08821_amd")
+    h = hashlib.sha256()
+    for src in (os.path.join(pkg, "csrc", "kernels.hip"), os.path.join(pkg, "build.py")):
+        h.update(open(src, "rb").read())
+    sha = h.hexdigest()
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         lines = open(f).read().splitlines()
-        if f"kernels.hip sha256: {sha}" not in lines:
+        if f"kernels.hip + build.py sha256: {sha}" not in lines:
             continue
         for ln in lines:
             if ln.startswith(f"traffic: kernel={kernel} "):

@@ -4,6 +4,12 @@
 
 Host sources are compiled with g++, HIP sources with hipcc for gfx950; the
 shared library is linked with hipcc.  Every call rebuilds from source.
+
+HIP code is compiled with `-ffp-contract=on`: a multiply is fused into an add
+only within one source expression, chosen by the front end.  With the default
+(`fast`) the back end picks which product of `a*b + c*d` to fuse per inlining
+context, so the single-mesh and batched wrappers of one device body could
+round differently.
 """
 from __future__ import annotations
 
@@ -53,7 +59,7 @@ def build(verbose: bool = False) -> str:
             objs.append(o)
             jobs.append([hipcc, "-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",
                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                         "-munsafe-fp-atomics", "-c", os.path.join(CSRC, s), "-o", o])
+                         "-munsafe-fp-atomics", "-ffp-contract=on", "-c", os.path.join(CSRC, s), "-o", o])
         with ThreadPoolExecutor(max_workers=4) as ex:
             logs = list(ex.map(_run, jobs))
         if verbose:

@@ -36,16 +36,13 @@ def test_batched_alpha_search(torch):
     for it, ref, ok in zip(r["iters"], g["iters"], g["converged"]):
         if ok:
             assert close(it, ref), (r["iters"], g["iters"])
-    # and those of the single-mesh solves of each candidate (exactly, where
-    # the count is not set by rounding)
+    # and exactly those of the single-mesh solves of each candidate (the
+    # batched and single-mesh launches run the same arithmetic)
     for ah, it, ok in zip(r["alpha_hats"], r["iters"], r["converged"]):
         pa = p.copy()
         pa.alpha_hat = ah
         _, st = Mesh(pa).solve(grad_tol=0.0, grad_rtol=g["grad_rtol"], max_iters=g["max_iters"], warm_start=0,
                                raise_on_error=False)
         assert (st["status"] == 0) == ok
-        if it < 500:
-            assert st["iters"] == it, (ah, st["iters"], it)
-        elif ok:
-            assert close(st["iters"], it), (ah, st["iters"], it)
+        assert st["iters"] == it, (ah, st["iters"], it)
     assert np.isfinite(r["q"]).all()
