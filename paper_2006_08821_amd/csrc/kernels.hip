@@ -140,6 +140,9 @@ DEV void matTmul3(const double* A, const double* B, double* C) {  // A^T B
     for (int j = 0; j < 3; ++j) C[3 * i + j] = A[i] * B[j] + A[3 + i] * B[3 + j] + A[6 + i] * B[6 + j];
 }
 
+DEV double rsq(double x) { return rsqrt(x); }
+DEV float rsq(float x) { return rsqrtf(x); }
+
 // Symmetric eigen-decomposition by cyclic Jacobi, A (N x N, full) overwritten
 // with a diagonal, V columns = eigenvectors.
 template <typename T, int N>
@@ -165,7 +168,7 @@ DEV void jacobi_sym(T (&A)[N][N], T (&V)[N][N]) {
         if (apq != T(0)) {
           T theta = (A[qq][qq] - A[pp][pp]) / (T(2) * apq);
           T t = (theta >= T(0) ? T(1) : T(-1)) / (fabs(theta) + sqrt(theta * theta + T(1)));
-          T c = T(1) / sqrt(t * t + T(1)), s = t * c;
+          T c = rsq(t * t + T(1)), s = t * c;
 #pragma unroll
           for (int k = 0; k < N; ++k) {
             T akp = A[k][pp], akq = A[k][qq];
@@ -355,31 +358,35 @@ DEV bool chol_packed(const T (&A)[N][N], T* L) {
     if (!(s > T(0))) return false;
     T d = sqrt(s);
     L[j * (j + 1) / 2 + j] = d;
+    const T rd = T(1) / d;
 #pragma unroll
     for (int i = j + 1; i < N; ++i) {
       T t = A[i][j];
 #pragma unroll
       for (int k = 0; k < j; ++k) t -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
-      L[i * (i + 1) / 2 + j] = t / d;
+      L[i * (i + 1) / 2 + j] = t * rd;
     }
   }
   return true;
 }
 template <typename T, int N>
 DEV void chol_solve(const T* L, T* x) {  // in place: L L^T x = b
+  T rd[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) rd[i] = T(1) / L[i * (i + 1) / 2 + i];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     T t = x[i];
 #pragma unroll
     for (int k = 0; k < i; ++k) t -= L[i * (i + 1) / 2 + k] * x[k];
-    x[i] = t / L[i * (i + 1) / 2 + i];
+    x[i] = t * rd[i];
   }
 #pragma unroll
   for (int i = N - 1; i >= 0; --i) {
     T t = x[i];
 #pragma unroll
     for (int k = i + 1; k < N; ++k) t -= L[k * (k + 1) / 2 + i] * x[k];
-    x[i] = t / L[i * (i + 1) / 2 + i];
+    x[i] = t * rd[i];
   }
 }
 template <typename T, int N>
@@ -1043,14 +1050,15 @@ DEV void gram_zblocks(const DevMesh& d, int i, T* zr) {
 #pragma unroll
     for (int k = 0; k < 21; ++k) Ls[k] = Lf[k * m + i];
 #pragma unroll
+    for (int c = 0; c < 6; ++c) Li[c * (c + 1) / 2 + c] = T(1) / Ls[c * (c + 1) / 2 + c];
+#pragma unroll
     for (int c = 0; c < 6; ++c) {
-      Li[c * (c + 1) / 2 + c] = T(1) / Ls[c * (c + 1) / 2 + c];
 #pragma unroll
       for (int r = c + 1; r < 6; ++r) {
         T v = 0;
 #pragma unroll
         for (int k = c; k < r; ++k) v += Ls[r * (r + 1) / 2 + k] * Li[k * (k + 1) / 2 + c];
-        Li[r * (r + 1) / 2 + c] = -v / Ls[r * (r + 1) / 2 + r];
+        Li[r * (r + 1) / 2 + c] = -v * Li[r * (r + 1) / 2 + r];
       }
     }
 #pragma unroll
