@@ -166,8 +166,10 @@ DEV void jacobi_sym(T (&A)[N][N], T (&V)[N][N]) {
       for (int qq = pp + 1; qq < N; ++qq) {
         T apq = A[pp][qq];
         if (apq != T(0)) {
-          T theta = (A[qq][qq] - A[pp][pp]) / (T(2) * apq);
-          T t = (theta >= T(0) ? T(1) : T(-1)) / (fabs(theta) + sqrt(theta * theta + T(1)));
+          // tan of the rotation angle, t = sgn(theta) / (|theta| + sqrt(theta^2 + 1))
+          // with theta = dqp / (2 apq), written with a single division
+          const T dqp = A[qq][qq] - A[pp][pp];
+          T t = (dqp >= T(0) ? T(2) : T(-2)) * apq / (fabs(dqp) + sqrt(dqp * dqp + T(4) * apq * apq));
           T c = rsq(t * t + T(1)), s = t * c;
 #pragma unroll
           for (int k = 0; k < N; ++k) {
@@ -268,9 +270,11 @@ __device__ __noinline__ Mat3 polar3_fallback(Mat3 X) {
 
 // Orthogonal polar factor by the scaled Newton iteration
 //   X <- (z X + X^{-T} / z) / 2,  z = |det X|^{-1/3}  (determinant scaling),
-// which converges quadratically to the rotation of X when det X > 0.  Returns
-// false (R untouched) for det X <= 0, a tiny determinant or no convergence in
-// 12 steps; the caller then uses polar3.
+// which converges quadratically to the rotation of X when det X > 0.  The
+// scaling is applied while det X is away from 1 (|det X - 1| > 1e-2); the
+// unscaled steps near convergence stop once a step changes X by <= 1e-15
+// relative.  Returns false (R untouched) for det X <= 0, a tiny determinant or
+// no convergence in 12 steps; the caller then uses polar3.
 DEV bool polar3_newton(const double* X0, double* R) {
   double X[9];
 #pragma unroll
@@ -283,7 +287,8 @@ DEV bool polar3_newton(const double* X0, double* R) {
   for (int it = 0; it < 12; ++it) {
     double C[9];
     cof3<double>(X, C);  // X^{-T} = cof(X) / det X
-    const double z = it < 6 ? cbrt(1.0 / dt) : 1.0;
+    const bool scale = fabs(dt - 1.0) > 1e-2;
+    const double z = scale ? cbrt(1.0 / dt) : 1.0;
     const double a = 0.5 * z, b = 0.5 / (z * dt);
     double diff = 0, nrm = 0;
 #pragma unroll
@@ -293,7 +298,7 @@ DEV bool polar3_newton(const double* X0, double* R) {
       nrm += y * y;
       X[k] = y;
     }
-    if (it >= 6 && diff <= 1e-30 * nrm) {
+    if (!scale && diff <= 1e-30 * nrm) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) R[k] = X[k];
       return true;
