@@ -198,7 +198,18 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
       gsrc.insert(gsrc.end(), lists[i].begin(), lists[i].end());
       gptr[i + 1] = (int32_t)gsrc.size();
     }
-    std::vector<int2> fwd, bwd;
+    std::vector<emu::SweepItem> fwd, bwd;
+    auto item = [&](int s, int first) {
+      emu::SweepItem it;
+      it.valoff = fac.valoff[s];
+      it.first = first;
+      it.w = fac.w[s];
+      it.h = fac.h[s];
+      it.col0 = fac.col0[s];
+      it.front = front[s];
+      it.rowoff = fac.rowoff[s];
+      return it;
+    };
     auto& pl = im.plan;
     pl.nlevels = fac.nlevels;
     pl.fwd_ptr.assign(fac.nlevels + 1, 0);
@@ -219,7 +230,7 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
         if (fac.level[s] == L) {
           const bool wide = fac.parent[s] < 0 && fac.w[s] >= 256;
           const int step = wide ? 8 : 32;
-          for (int r = 0; r < fac.h[s]; r += step) fwd.push_back(make_int2(s, r | (wide ? emu::kItemWideBit : 0)));
+          for (int r = 0; r < fac.h[s]; r += step) fwd.push_back(item(s, r | (wide ? emu::kItemWideBit : 0)));
         }
       pl.fwd_ptr[L + 1] = (int)fwd.size();
     }
@@ -229,16 +240,10 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
         if (fac.level[s] == L) {
           const bool wide = sparse && fac.h[s] >= emu::kWideRowMin;
           const int step = wide ? 8 : 32;
-          for (int c = 0; c < fac.w[s]; c += step) bwd.push_back(make_int2(s, c | (wide ? emu::kItemWideBit : 0)));
+          for (int c = 0; c < fac.w[s]; c += step) bwd.push_back(item(s, c | (wide ? emu::kItemWideBit : 0)));
         }
       pl.bwd_ptr[k + 1] = (int)bwd.size();
     }
-    B.put(SLOT(sn_col0), fac.col0);
-    B.put(SLOT(sn_w), fac.w);
-    B.put(SLOT(sn_h), fac.h);
-    B.put(SLOT(sn_rowoff), fac.rowoff);
-    B.put(SLOT(sn_valoff), fac.valoff);
-    B.put(SLOT(sn_front), front);
     B.put(SLOT(rows), fac.rows);
     B.put(SLOT(vals), fac.vals);
     {

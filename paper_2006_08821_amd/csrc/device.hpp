@@ -45,6 +45,15 @@ struct Ctl {
 };
 
 // Plain pointers to every device array of a mesh (passed by value).
+// A work item of a triangular sweep with its supernode's metadata, read by
+// the workgroup in one scalar load: first row (forward) or column (backward),
+// with kItemWideBit marking 32 lanes per row; supernode width w, height h,
+// first column col0, frontal offset into gptr, row offset, value offset.
+struct SweepItem {
+  int64_t valoff;
+  int32_t first, w, h, col0, front, rowoff;
+};
+
 struct DevMesh {
   int32_t n, nf, m, k1, npins, ngroups;
   int32_t nb;          // workgroups of the element passes (fixed: deterministic sums)
@@ -83,19 +92,13 @@ struct DevMesh {
   const int32_t* inc;     // element*4 + local vertex
 
   // factor (partitioned-inverse supernodes)
-  const int32_t* sn_col0;
-  const int32_t* sn_w;
-  const int32_t* sn_h;
-  const int32_t* sn_rowoff;
-  const int64_t* sn_valoff;
-  const int32_t* sn_front;   // offset of the supernode's positions in gptr
   const int32_t* rows;
   const double* vals;         // forward blocks [Linv; M], packed rows
   const double* tvals;        // the same blocks transposed (columns of L as rows)
   const int32_t* gptr;       // [sum h + 1] children's update rows per front position
   const int32_t* gsrc;
-  const int2* fwd_items;     // (supernode, first row)
-  const int2* bwd_items;     // (supernode, first column)
+  const SweepItem* fwd_items;  // per forward work item: first row and its supernode
+  const SweepItem* bwd_items;  // per backward work item: first column and its supernode
   double* rhs;               // [nf][3]
   double* ybuf;              // [nf][3]
   double* xbuf;              // [nf][3]

@@ -688,9 +688,9 @@ constexpr int kItemWide = kItemWideBit;
 // supernode s.  Frontal vector f = [rhs at the columns; 0] + children's update
 // vectors; rows r < w give y = Linv f_top, rows r >= w give u = f_r - M_r f_top.
 template <int LPR>
-DEV void fwd_item(const DevMesh& d, int s, int r0, double* ft) {
-  const int w = d.sn_w[s], h = d.sn_h[s], col0 = d.sn_col0[s];
-  const int fo = d.sn_front[s];
+DEV void fwd_item(const DevMesh& d, const SweepItem& it, int r0, double* ft) {
+  const int w = it.w, h = it.h, col0 = it.col0;
+  const int fo = it.front;
   const int t = threadIdx.x;
   const int nrows = min(256 / LPR, h - r0);
   // the rows of this item need f_top entries [0, min(w, r0 + nrows))
@@ -713,7 +713,7 @@ DEV void fwd_item(const DevMesh& d, int s, int r0, double* ft) {
       ft[3 * k + 2] = a2;
     }
     __syncthreads();
-    row_products<true, LPR>(d.vals, d.sn_valoff[s], w, h, r0, nrows, ft, vb, vl, acc);
+    row_products<true, LPR>(d.vals, it.valoff, w, h, r0, nrows, ft, vb, vl, acc);
   }
   const int lane = t & 63, wave = t >> 6, g = lane / LPR, l = lane % LPR;
   const int rr = wave * (64 / LPR) + g;
@@ -731,7 +731,7 @@ DEV void fwd_item(const DevMesh& d, int s, int r0, double* ft) {
         b1 += u[1];
         b2 += u[2];
       }
-      double* o = d.upd + 3 * (int64_t)(d.sn_rowoff[s] + r - w);
+      double* o = d.upd + 3 * (int64_t)(it.rowoff + r - w);
       o[0] = b0 - acc[0];
       o[1] = b1 - acc[1];
       o[2] = b2 - acc[2];
@@ -739,11 +739,16 @@ DEV void fwd_item(const DevMesh& d, int s, int r0, double* ft) {
   }
 }
 DEV void b_fwd(const DevMesh& d, int bid, int check_done) {
-  if (check_done && d.ctl->done) return;
+  // the item and the stop flag are read in the same scalar round trip (the
+  // empty asm statement keeps the compiler from sinking the item load below
+  // the flag test)
+  const SweepItem it = d.fwd_items[bid];
+  const int done = check_done ? d.ctl->done : 0;
+  __asm__ volatile("" ::"s"(it.first), "s"(done));
+  if (done) return;
   __shared__ double ft[kVecChunk * 3];
-  const int2 item = d.fwd_items[bid];
-  if (item.y & kItemWide) fwd_item<32>(d, item.x, item.y & ~kItemWide, ft);
-  else fwd_item<8>(d, item.x, item.y, ft);
+  if (it.first & kItemWide) fwd_item<32>(d, it, it.first & ~kItemWide, ft);
+  else fwd_item<8>(d, it, it.first, ft);
 }
 __global__ void __launch_bounds__(kBlock) k_fwd(DevMesh d, int it0, int check_done) { b_fwd(d, it0 + (int)blockIdx.x, check_done); }
 
@@ -751,11 +756,11 @@ __global__ void __launch_bounds__(kBlock) k_fwd(DevMesh d, int it0, int check_do
 // columns [c0, c0 + 256/LPR) of supernode s.  With z = [y_s; -x[rows]],
 //   x_c = sum_{r >= c} L^{-T}-block[c][r - c] z[r].
 template <int LPR>
-DEV void bwd_item(const DevMesh& d, int s, int c0, double* x, double* z) {
-  const int w = d.sn_w[s], h = d.sn_h[s], col0 = d.sn_col0[s];
+DEV void bwd_item(const DevMesh& d, const SweepItem& it, int c0, double* x, double* z) {
+  const int w = it.w, h = it.h, col0 = it.col0;
   const int t = threadIdx.x;
   const int ncols = min(256 / LPR, w - c0);
-  const int32_t* rows = d.rows + d.sn_rowoff[s];
+  const int32_t* rows = d.rows + it.rowoff;
   double acc[3] = {0, 0, 0};
   for (int vb = c0; vb < h; vb += kVecChunk) {
     const int vl = min(kVecChunk, h - vb);
@@ -774,7 +779,7 @@ DEV void bwd_item(const DevMesh& d, int s, int c0, double* x, double* z) {
       }
     }
     __syncthreads();
-    row_products<false, LPR>(d.tvals, d.sn_valoff[s], w, h, c0, ncols, z, vb, vl, acc);
+    row_products<false, LPR>(d.tvals, it.valoff, w, h, c0, ncols, z, vb, vl, acc);
   }
   const int lane = t & 63, wave = t >> 6, g = lane / LPR, l = lane % LPR;
   const int cc = wave * (64 / LPR) + g;
@@ -786,11 +791,13 @@ DEV void bwd_item(const DevMesh& d, int s, int c0, double* x, double* z) {
   }
 }
 DEV void b_bwd(const DevMesh& d, int bid, double* x, int check_done) {
-  if (check_done && d.ctl->done) return;
+  const SweepItem it = d.bwd_items[bid];
+  const int done = check_done ? d.ctl->done : 0;
+  __asm__ volatile("" ::"s"(it.first), "s"(done));
+  if (done) return;
   __shared__ double z[kVecChunk * 3];
-  const int2 item = d.bwd_items[bid];
-  if (item.y & kItemWide) bwd_item<32>(d, item.x, item.y & ~kItemWide, x, z);
-  else bwd_item<8>(d, item.x, item.y, x, z);
+  if (it.first & kItemWide) bwd_item<32>(d, it, it.first & ~kItemWide, x, z);
+  else bwd_item<8>(d, it, it.first, x, z);
 }
 __global__ void __launch_bounds__(kBlock) k_bwd(DevMesh d, int it0, double* x, int check_done) { b_bwd(d, it0 + (int)blockIdx.x, x, check_done); }
 
