@@ -1475,17 +1475,27 @@ DEV void b_control_a(const DevMesh& d, int bid) {
   }
   if (t >= 64) return;
   // substitutions in the first wave: lane t holds entry t; the newly solved
-  // entry is broadcast with readlane
+  // entry is broadcast with readlane.  Lane t's row (forward) and column
+  // (backward) of L and the pivots are read from LDS ahead of the dependent
+  // chains, which then run on registers only.
   double yt = t < 48 ? yv[t] : 0.0;
+  double lv[48], ip[48];
+#pragma unroll
   for (int i = 0; i < 48; ++i) {
-    const double ui = bcast_lane(yt, i) * invp[i];
-    if (t == i) yt = ui;
-    else if (t > i && t < 48) yt -= Cm[t][i] * ui;
+    lv[i] = t < 48 && i < t ? Cm[t][i] : 0.0;
+    ip[i] = invp[i];
   }
+#pragma unroll
+  for (int i = 0; i < 48; ++i) {
+    const double ui = bcast_lane(yt, i) * ip[i];
+    yt = t == i ? ui : yt - lv[i] * ui;
+  }
+#pragma unroll
+  for (int i = 0; i < 48; ++i) lv[i] = t < 48 && i > t ? Cm[i][t] : 0.0;
+#pragma unroll
   for (int i = 47; i >= 0; --i) {
-    const double zi = bcast_lane(yt, i) * invp[i];
-    if (t == i) yt = zi;
-    else if (t < i) yt -= Cm[i][t] * zi;
+    const double zi = bcast_lane(yt, i) * ip[i];
+    yt = t == i ? zi : yt - lv[i] * zi;
   }
   if (t < 48) yv[t] = yt;
   __builtin_amdgcn_wave_barrier();
