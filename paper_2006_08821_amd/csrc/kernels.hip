@@ -35,6 +35,16 @@ DEV double bcast_lane(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// The stop flag, read in the same memory round trip as a first value of the
+// kernel's own data: the empty asm statement needs both values, so the
+// compiler issues the data load before the flag test instead of after it.
+template <typename V>
+DEV bool stopped(const DevMesh& d, V first) {
+  const int done = d.ctl->done;
+  __asm__ volatile("" ::"v"(first), "s"(done));
+  return done != 0;
+}
+
 constexpr double kRs2 = 0.70710678118654752440;  // 1/sqrt(2)
 
 struct DD {
@@ -579,8 +589,8 @@ __global__ void __launch_bounds__(kBlock) k_scatter_F(DevMesh d) {
 // added in a fixed order.
 constexpr int kRhsLanes = 4;
 DEV void b_rhs(const DevMesh& d, int bid, int add_pin, int check_done) {
-  if (check_done && d.ctl->done) return;
   const int f = bid * (kBlock / kRhsLanes) + (int)threadIdx.x / kRhsLanes;
+  if (check_done && stopped(d, f < d.nf ? d.inc_ptr[f] : 0)) return;
   const int sub = threadIdx.x % kRhsLanes;
   double acc[3] = {0, 0, 0};
   if (f < d.nf) {
@@ -810,9 +820,9 @@ __global__ void __launch_bounds__(kBlock) k_set_pins(DevMesh d) {
 }
 
 DEV void b_add_q(const DevMesh& d, int bid) {
-  if (d.ctl->done) return;
-  const double sg = d.ctl->sigma;
   int i = bid * blockDim.x + threadIdx.x;
+  if (stopped(d, i < 3 * d.nf ? d.dq[i] : 0.0)) return;
+  const double sg = d.ctl->sigma;
   if (i >= 3 * d.nf) return;
   d.q[i] += sg * d.dq[i];
 }
@@ -826,7 +836,10 @@ __global__ void __launch_bounds__(kBlock) k_add_q(DevMesh d) { b_add_q(d, blockI
 template <typename T>
 DEV void b_element(const DevMesh& d, int bid) {
   Ctl* ctl = d.ctl;
-  if (ctl->done) return;
+  {
+    const int i0 = bid * kBlock + threadIdx.x;
+    if (stopped(d, i0 < d.m ? d.vol[i0] : 0.0)) return;
+  }
   __shared__ DD sh[2 * kBlock];
   __shared__ int shc[kBlock];
   const double sigma = ctl->sigma;
@@ -940,8 +953,10 @@ DEV void b_element(const DevMesh& d, int bid) {
 // factors, and gbar = H^{-1} g (g read from gbar, overwritten in place).
 template <typename T>
 DEV void b_element_hess(const DevMesh& d, int bid) {
-  Ctl* ctl = d.ctl;
-  if (ctl->done) return;
+  {
+    const int i0 = bid * kBlock + threadIdx.x;
+    if (stopped(d, i0 < d.m ? d.vol[i0] : 0.0)) return;
+  }
   __shared__ int shc[kBlock];
   int nclamp = 0;
   const int m = d.m;
@@ -1292,10 +1307,10 @@ __global__ void __launch_bounds__(kBlock) k_gram(DevMesh d) { b_gram<T>(d, block
 // Partial Gram sums: 16 threads per entry sum interleaved workgroup partials,
 // then add their results in a fixed order.
 DEV void b_gram_reduce(const DevMesh& d, int bid) {
-  if (d.ctl->done) return;
   __shared__ double sh[16][17];
   const int t = threadIdx.x, part = t >> 4, el = t & 15;
   const int e = bid * 16 + el;
+  if (stopped(d, e < kGramEntries && part < d.nbg ? d.part_gram[(int64_t)part * kGramEntries + e] : 0.0)) return;
   double s0 = 0, s1 = 0;
   if (e < kGramEntries) {
     int b = part;
@@ -1510,8 +1525,8 @@ __global__ void __launch_bounds__(kCtlThreads) k_control_a(DevMesh d) { b_contro
 
 // uz[v][c] = sum_j z[(c,j)] phi_j(v)  (zero at pinned vertices)
 DEV void b_uz(const DevMesh& d, int bid) {
-  if (d.ctl->done) return;
   int v = bid * kBlock + threadIdx.x;
+  if (stopped(d, v < d.n ? d.phi[(int64_t)kMaxK1 * v] : 0.0)) return;
   if (v >= d.n) return;
   double a[3] = {0, 0, 0};
   if (d.k1 > 0) {
@@ -1532,8 +1547,10 @@ __global__ void __launch_bounds__(kBlock) k_uz(DevMesh d) { b_uz(d, blockIdx.x);
 // p = -d; g.p = (L^T gbar).(L^T p) per block; contributions of dF = R D(p).
 template <typename T>
 DEV void b_direction(const DevMesh& d, int bid) {
-  Ctl* ctl = d.ctl;
-  if (ctl->done) return;
+  {
+    const int i0 = bid * kBlock + threadIdx.x;
+    if (stopped(d, i0 < d.m ? d.w[i0] : 0.0)) return;
+  }
   __shared__ DD sh[kBlock];
   DD acc[1] = {DD{0, 0}};
   const int m = d.m;
@@ -1595,8 +1612,10 @@ __global__ void __launch_bounds__(kBlock) k_direction(DevMesh d) { b_direction<T
 // Line-search polynomial: E(sigma) - E(0) = sum_k c_k sigma^k (k = 1..6), exact
 // per element along F(sigma) = R (S + sigma D), A(sigma) = A + sigma dA.
 DEV void b_lscoef(const DevMesh& d, int bid) {
-  Ctl* ctl = d.ctl;
-  if (ctl->done) return;
+  {
+    const int i0 = bid * kBlock + threadIdx.x;
+    if (stopped(d, i0 < d.m ? d.vol[i0] : 0.0)) return;
+  }
   __shared__ DD sh[6 * kBlock];
   DD acc[6];
 #pragma unroll
@@ -1677,9 +1696,9 @@ __global__ void __launch_bounds__(kBlock) k_lscoef(DevMesh d) { b_lscoef(d, bloc
 // Single workgroup: Armijo backtracking on the exact polynomial (Algorithm 1).
 DEV void b_control_b(const DevMesh& d, int bid) {
   Ctl* ctl = d.ctl;
-  if (ctl->done) return;
-  __shared__ DD sh[kLsTerms * kBlock];
   const int t = threadIdx.x;
+  if (stopped(d, t < d.nb ? d.part_ls[2 * kLsTerms * t] : 0.0)) return;
+  __shared__ DD sh[kLsTerms * kBlock];
   DD acc[kLsTerms];
 #pragma unroll
   for (int k = 0; k < kLsTerms; ++k) acc[k] = DD{0, 0};
