@@ -71,20 +71,45 @@ DEV DD dd_add_d(DD x, double y) {
   return DD{h, e - (h - s)};
 }
 
-// Block-wide reduction of NV double-double values (kBlock threads); result valid
-// in thread 0.  Fixed tree order.
+// Block-wide reduction of NV double-double values (NT threads, whole waves);
+// result valid in thread 0.  Fixed order: a butterfly over the 64 lanes of
+// each wave (lane shuffles, no barrier), then thread 0 adds the wave sums in
+// wave order after one barrier.
 template <int NV, int NT = kBlock>
 DEV void block_reduce_dd(DD (&v)[NV], DD* sh) {
-  const int t = threadIdx.x;
-  for (int k = 0; k < NV; ++k) sh[k * NT + t] = v[k];
+  constexpr int W = NT / 64;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = dd_add(v[k], DD{__shfl_xor(v[k].hi, off), __shfl_xor(v[k].lo, off)});
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[k * W + wave] = v[k];
   __syncthreads();
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (t < s)
-      for (int k = 0; k < NV; ++k) sh[k * NT + t] = dd_add(sh[k * NT + t], sh[k * NT + t + s]);
-    __syncthreads();
-  }
   if (t == 0)
-    for (int k = 0; k < NV; ++k) v[k] = sh[k * NT];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      DD a = sh[k * W];
+#pragma unroll
+      for (int w = 1; w < W; ++w) a = dd_add(a, sh[k * W + w]);
+      v[k] = a;
+    }
+}
+// Block-wide integer sum (exact, so any order), valid in thread 0.
+template <int NT = kBlock>
+DEV int block_sum_int(int v, int* sh) {
+  constexpr int W = NT / 64;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((t & 63) == 0) sh[t >> 6] = v;
+  __syncthreads();
+  int a = 0;
+  if (t == 0)
+#pragma unroll
+    for (int w = 0; w < W; ++w) a += sh[w];
+  return a;
 }
 
 // ------------------------------------------------------------------ 3x3 helpers
@@ -933,18 +958,13 @@ DEV void b_element(const DevMesh& d, int bid) {
     for (int k = 0; k < 9; ++k) gyo[k * m + i] = (T)gy[k];
   }
   block_reduce_dd<2>(acc, sh);
-  shc[threadIdx.x] = ninv;
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) shc[threadIdx.x] += shc[threadIdx.x + s];
-    __syncthreads();
-  }
+  const int ninv_sum = block_sum_int(ninv, shc);
   if (threadIdx.x == 0) {
     d.part_e[2 * bid] = acc[0].hi;
     d.part_e[2 * bid + 1] = acc[0].lo;
     d.part_g[2 * bid] = acc[1].hi;
     d.part_g[2 * bid + 1] = acc[1].lo;
-    d.part_cnt[2 * bid + 1] = shc[0];
+    d.part_cnt[2 * bid + 1] = ninv_sum;
   }
 }
 
@@ -1014,13 +1034,8 @@ DEV void b_element_hess(const DevMesh& d, int bid) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) Lf[(21 + k) * m + i] = Lk[k];
   }
-  shc[threadIdx.x] = nclamp;
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) shc[threadIdx.x] += shc[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) d.part_cnt[2 * bid] = shc[0];
+  const int nclamp_sum = block_sum_int(nclamp, shc);
+  if (threadIdx.x == 0) d.part_cnt[2 * bid] = nclamp_sum;
 }
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_element(DevMesh d) { b_element<T>(d, blockIdx.x); }
@@ -1373,22 +1388,14 @@ DEV void b_control_a(const DevMesh& d, int bid) {
   }
   for (int r = t; r < 48; r += kCtlThreads) yv[r] = r < K ? d.gram[1536 + (r / k1) * 16 + (r % k1)] : 0.0;
   block_reduce_dd<2, kCtlThreads>(acc, sh);
-  cnt[0][t] = cl;
-  cnt[1][t] = inv;
-  __syncthreads();
-  for (int s2 = kCtlThreads / 2; s2 > 0; s2 >>= 1) {
-    if (t < s2) {
-      cnt[0][t] += cnt[0][t + s2];
-      cnt[1][t] += cnt[1][t + s2];
-    }
-    __syncthreads();
-  }
+  const int cl_sum = block_sum_int<kCtlThreads>(cl, cnt[0]);
+  const int inv_sum = block_sum_int<kCtlThreads>(inv, cnt[1]);
   if (t == 0) {
     const double g2 = acc[1].hi + acc[1].lo;
     ctl->energy = acc[0].hi + acc[0].lo;
     ctl->gnorm2 = g2;
-    ctl->clamped = cnt[0][0];
-    ctl->inverted = cnt[1][0];
+    ctl->clamped = cl_sum;
+    ctl->inverted = inv_sum;
     if (ctl->iter == 0 && ctl->gnorm0_2 < 0) ctl->gnorm0_2 = g2;
     int stop = 0;
     if (!(g2 == g2) || !(ctl->energy == ctl->energy) || g2 > 1e300) {
