@@ -177,9 +177,37 @@ def run(args):
         out["serving"] = serving(args)
     if args.alpha_search:
         out["alpha_search"] = alpha_search_leg()
+    if args.large:
+        out["largest_configuration"] = large_leg(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args)
     return out
+
+
+def large_leg(args):
+    """The largest configuration on one GPU: hinge limb 40x40x160 (1.536M
+    tets, four muscle groups at their first-frame activations); host setup
+    time, then the same timed iteration as the main line."""
+    import torch
+    from paper_2006_08821_amd import workloads as wl
+    from paper_2006_08821_amd.emu import Mesh
+    p = wl.hinge_limb(40, 40, 160, frames=1)[0]
+    t0 = time.time()
+    mesh = Mesh(p)
+    setup_s = time.time() - t0
+    info = mesh.info()
+    mesh.solve(grad_tol=0.0, max_iters=10, raise_on_error=False)
+    torch.cuda.synchronize()
+    steps = 50
+    t0 = time.perf_counter()
+    _, st = mesh.solve(grad_tol=0.0, max_iters=steps, iters_per_sync=32, raise_on_error=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    it = max(1, st["iters"])
+    return {"workload": "hinge limb 40x40x160", "tets": p.n_tets, "vertices": p.n_vertices,
+            "factor_nnz": info["factor_nnz"], "levels": info["n_levels"], "setup_s": setup_s,
+            "device_mb": info["device_bytes"] / 1e6, "iterations": it, "ms_per_step": 1e3 * dt / it,
+            "element_iterations_per_s": p.n_tets * it / dt}
 
 
 def alpha_search_leg():
@@ -329,6 +357,7 @@ def main():
     ap.add_argument("--serve-max-iters", type=int, default=300)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--alpha-search", type=int, default=1, help="run the alpha-search leg (0: skip)")
+    ap.add_argument("--large", type=int, default=0, help="run the largest configuration (1.5M tets) too")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (for scaling HBM counters)")
     args = ap.parse_args()

@@ -85,8 +85,11 @@ def hat_gradients(rest, tets):
     return b, vol
 
 
-def build(problem, alpha_hat=None, n_modes=None, weight_mode=0, modes=True):
-    """Set up the oracle mesh for a ``workloads.Problem``."""
+def build(problem, alpha_hat=None, n_modes=None, weight_mode=0, modes=True, factor=True):
+    """Set up the oracle mesh for a ``workloads.Problem``.  ``factor=False``
+    skips the sparse factorization (and the modes): the element formulas,
+    ``L``, ``scatter_GtWF`` and ``gather_A`` still work, which is what checks
+    at sizes the factorization would take too long for need."""
     alpha_hat = problem.alpha_hat if alpha_hat is None else alpha_hat
     n_modes = problem.n_modes if n_modes is None else n_modes
     rest = np.asarray(problem.rest_xyz, np.float64)
@@ -121,14 +124,14 @@ def build(problem, alpha_hat=None, n_modes=None, weight_mode=0, modes=True):
     fpos[free] = np.arange(free.size)
     Lff = L[free][:, free].tocsc()
     Lfp = L[free][:, pins].tocsr()
-    lu = spla.splu(Lff, permc_spec="MMD_AT_PLUS_A")
+    lu = spla.splu(Lff, permc_spec="MMD_AT_PLUS_A") if factor else None
     M = Mesh(rest=rest, tets=tets, b=b, vol=vol, mu=mu, lhat=lhat, fiber=fiber,
              group=group, w=w, beta=beta, alpha=alpha, mu_ref=mu_ref, kf=kf,
              pins=pins, pin_xyz=np.asarray(problem.pin_xyz, np.float64),
              free=free, fpos=fpos, L=L, Lff=Lff, Lfp=Lfp, lu=lu)
     if n_modes < 0:                       # default: 48 modes, capped by the mesh
         n_modes = min(48, 3 * (free.size - 1))
-    if modes and n_modes > 0:
+    if modes and factor and n_modes > 0:
         compute_modes(M, n_modes // 3)
     return M
 

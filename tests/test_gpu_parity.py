@@ -223,6 +223,36 @@ def test_full_size_limb_evaluate(torch):
     assert np.abs(dg - d).max() <= 1e-6 * np.abs(d).max()
 
 
+def test_largest_configuration_properties(torch):
+    # The largest configuration (hinge limb 40x40x160: 1.536M tets, 270k
+    # vertices, factor 151M entries) in the benchmark's launch configuration.
+    # The oracle cannot factor it in test time, so the checks are properties
+    # that hold at any size, with the oracle's element formulas and its
+    # Laplacian: the returned q is the ACAP minimizer for F (residual of the
+    # normal equations, pins at their targets), and the energy and gradient
+    # norm equal the element sums at (F, q).
+    p = wl.hinge_limb(40, 40, 160, frames=1)[0]
+    mesh = _mesh(p)
+    mesh.solve(grad_tol=0.0, max_iters=8, iters_per_sync=32, raise_on_error=False)
+    F, _ = mesh.get_state()
+    F = F.cpu().numpy()
+    ev = mesh.evaluate(F, direction=False)
+    q = ev["q"].cpu().numpy()
+    del mesh
+    M = omesh.build(p, modes=False, factor=False)
+    r = omesh.scatter_GtWF(M, F)[M.free]
+    res = M.Lff @ q[M.free] + M.Lfp @ M.pin_xyz - r
+    assert np.abs(res).max() <= 1e-10 * np.abs(r).max()
+    assert np.array_equal(q[M.pins], M.pin_xyz)
+    a_el = omesh.activation_per_element(M, p.activation)
+    A = omesh.gather_A(M, q)
+    E = math.fsum(oemu.element_energy(M, F, A, a_el))
+    assert math.isclose(ev["energy"], E, rel_tol=1e-11)
+    g = oemu.grad_F(M, F, A, a_el)
+    gn = math.sqrt(math.fsum((g * g).reshape(-1)))
+    assert math.isclose(ev["grad_norm"], gn, rel_tol=1e-9)
+
+
 def _forces(M, seed=4, scale=1.0):
     rng = np.random.default_rng(seed)
     f = np.zeros((M.n, 3))
