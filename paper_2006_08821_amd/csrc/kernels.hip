@@ -440,27 +440,128 @@ DEV void chol_lt_mul(const T* L, const T* x, T* y) {  // y = L^T x
   }
 }
 
+// A <- its positive semi-definite part (eigenvalues < 0 -> 0), by Jacobi.
+template <typename T, int N>
+DEV void clamp_psd_jacobi(T (&A)[N][N]) {
+  T V[N][N];
+  jacobi_sym<T, N>(A, V);
+  T lam[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) lam[k] = A[k][k] > T(0) ? A[k][k] : T(0);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      T s = 0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) s += V[i][k] * lam[k] * V[j][k];
+      A[i][j] = s;
+    }
+}
+
+DEV double acs(double x) { return acos(x); }
+DEV float acs(float x) { return acosf(x); }
+DEV double cs(double x) { return cos(x); }
+DEV float cs(float x) { return cosf(x); }
+
+// Unit eigenvector of the symmetric 3x3 A for its simple eigenvalue lam: the
+// longest of the cross products of two rows of A - lam I, normalized.
+template <typename T>
+DEV void eigvec3(const T (&A)[3][3], T lam, T* v) {
+  const T r[3][3] = {{A[0][0] - lam, A[0][1], A[0][2]},
+                     {A[1][0], A[1][1] - lam, A[1][2]},
+                     {A[2][0], A[2][1], A[2][2] - lam}};
+  T c[3][3];
+  const int pr[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+  T best = -1;
+  int kb = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T* a = r[pr[k][0]];
+    const T* b = r[pr[k][1]];
+    c[k][0] = a[1] * b[2] - a[2] * b[1];
+    c[k][1] = a[2] * b[0] - a[0] * b[2];
+    c[k][2] = a[0] * b[1] - a[1] * b[0];
+    const T n = c[k][0] * c[k][0] + c[k][1] * c[k][1] + c[k][2] * c[k][2];
+    if (n > best) {
+      best = n;
+      kb = k;
+    }
+  }
+  const T s = rsq(best);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) v[i] = (kb == 0 ? c[0][i] : (kb == 1 ? c[1][i] : c[2][i])) * s;
+}
+
+// PSD part of a symmetric 3x3 in closed form: the eigenvalues from the
+// trigonometric solution of the characteristic cubic (shifted by the mean
+// eigenvalue and scaled), then A+ = A - e3 v3 v3^T (one negative eigenvalue)
+// or e1 v1 v1^T (two).  Returns false, leaving A unchanged, when the kept and
+// the dropped eigenvalues are closer than 1e-4 of the largest magnitude (the
+// eigenvector would be inaccurate); the caller then uses Jacobi.
+template <typename T>
+DEV bool clamp_psd3_closed(T (&A)[3][3]) {
+  const T q = (A[0][0] + A[1][1] + A[2][2]) * T(1.0 / 3.0);
+  const T b00 = A[0][0] - q, b11 = A[1][1] - q, b22 = A[2][2] - q;
+  const T a01 = A[0][1], a02 = A[0][2], a12 = A[1][2];
+  const T p1 = a01 * a01 + a02 * a02 + a12 * a12;
+  const T p = sqrt((b00 * b00 + b11 * b11 + b22 * b22 + T(2) * p1) * T(1.0 / 6.0));
+  if (!(p > T(0))) {  // A = q I
+    if (q < T(0))
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) A[i][j] = T(0);
+    return true;
+  }
+  const T ip = T(1) / p;
+  const T c00 = b00 * ip, c11 = b11 * ip, c22 = b22 * ip, c01 = a01 * ip, c02 = a02 * ip, c12 = a12 * ip;
+  T r = T(0.5) * (c00 * (c11 * c22 - c12 * c12) - c01 * (c01 * c22 - c12 * c02) + c02 * (c01 * c12 - c11 * c02));
+  r = r < T(-1) ? T(-1) : (r > T(1) ? T(1) : r);
+  const T phi = acs(r) * T(1.0 / 3.0);
+  const T e1 = q + T(2) * p * cs(phi);
+  const T e3 = q + T(2) * p * cs(phi + T(2.0943951023931954923));  // + 2 pi / 3
+  const T e2 = T(3) * q - e1 - e3;
+  const T scale = fabs(e1) > fabs(e3) ? fabs(e1) : fabs(e3);
+  if (!(e1 > T(0))) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) A[i][j] = T(0);
+    return true;
+  }
+  if (!(e3 < T(0))) return true;  // already semi-definite
+  T v[3];
+  if (e2 >= T(0)) {
+    if (!(e2 - e3 > T(1e-4) * scale)) return false;
+    eigvec3<T>(A, e3, v);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) A[i][j] -= e3 * v[i] * v[j];
+  } else {
+    if (!(e1 - e2 > T(1e-4) * scale)) return false;
+    eigvec3<T>(A, e1, v);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) A[i][j] = e1 * v[i] * v[j];
+  }
+  return true;
+}
+
 // Make A positive semi-definite (eigenvalues < 0 -> 0) unless a Cholesky
 // factorization already succeeds; then add beta I and factor.  Returns 1 if
-// the clamp changed A.
+// the clamp changed A.  3x3 blocks take the closed form where it is accurate.
 template <typename T, int N>
 DEV int clamp_add_factor(T (&A)[N][N], T beta, T* L) {
   int clamped = 0;
   if (!chol_packed<T, N>(A, L)) {
-    T V[N][N];
-    jacobi_sym<T, N>(A, V);
-    T lam[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) lam[k] = A[k][k] > T(0) ? A[k][k] : T(0);
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        T s = 0;
-#pragma unroll
-        for (int k = 0; k < N; ++k) s += V[i][k] * lam[k] * V[j][k];
-        A[i][j] = s;
-      }
+    if constexpr (N == 3) {
+      if (!clamp_psd3_closed<T>(A)) clamp_psd_jacobi<T, 3>(A);
+    } else {
+      clamp_psd_jacobi<T, N>(A);
+    }
     clamped = 1;
   }
 #pragma unroll
