@@ -797,22 +797,24 @@ void recompute_pin_rhs(HostMesh& hm) {
 
 // ------------------------------------------------------------------ host solves
 void host_factor_solve(const Factor& f, int nrhs, const double* b, double* x) {
-  const int ns = f.ns;
-  // split the right-hand sides over threads
-  int T = std::max(1, std::min(n_threads(), nrhs));
-  int per = (nrhs + T - 1) / T;
-  std::vector<std::thread> th;
-  auto run = [&](int r0, int r1) {
-    const int nr = r1 - r0;
-    if (nr <= 0) return;
-    std::vector<double> y((size_t)f.nf * nr), u((size_t)f.rowoff[ns] * nr, 0.0);
-    std::vector<double> fr;
-    for (int s = 0; s < ns; ++s) {
+  // Both sweeps level by level (the supernodes of one level are independent),
+  // each supernode with all right-hand sides at once, so the factor is read
+  // once per sweep.  Per right-hand side the arithmetic and its order are those
+  // of a sequential sweep.
+  const int ns = f.ns, nr = nrhs;
+  if (nr <= 0) return;
+  std::vector<std::vector<int>> by_level(std::max<int32_t>(1, f.nlevels));
+  for (int s = 0; s < ns; ++s) by_level[f.level[s]].push_back(s);
+  std::vector<double> y((size_t)f.nf * nr), u((size_t)f.rowoff[ns] * nr, 0.0);
+  for (int lv = 0; lv < f.nlevels; ++lv) {
+    const auto& L = by_level[lv];
+    parallel_for((int64_t)L.size(), [&](int64_t idx) {
+      const int s = L[idx];
       const int w = f.w[s], h = f.h[s];
       const int32_t c0 = f.col0[s];
-      fr.assign((size_t)h * nr, 0.0);
+      std::vector<double> fr((size_t)h * nr, 0.0);
       for (int i = 0; i < w; ++i)
-        for (int r = 0; r < nr; ++r) fr[(size_t)i * nr + r] = b[(size_t)(c0 + i) * nrhs + r0 + r];
+        for (int r = 0; r < nr; ++r) fr[(size_t)i * nr + r] = b[(size_t)(c0 + i) * nrhs + r];
       const int32_t* rows_s = f.rows.data() + f.rowoff[s];
       for (int k = f.child_ptr[s]; k < f.child_ptr[s + 1]; ++k) {
         int c = f.child_idx[k];
@@ -826,32 +828,51 @@ void host_factor_solve(const Factor& f, int nrhs, const double* b, double* x) {
         }
       }
       const double* Lv = f.vals.data() + f.valoff[s];
-      int64_t o = 0;
-      for (int i = 0; i < w; ++i) {
-        for (int r = 0; r < nr; ++r) {
-          double t = 0;
-          for (int c = 0; c <= i; ++c) t += Lv[o + c] * fr[(size_t)c * nr + r];
-          y[(size_t)(c0 + i) * nr + r] = t;
+      const int64_t tri = (int64_t)w * (w + 1) / 2;
+      // rows of the block are independent: large blocks on levels with few
+      // supernodes split their rows over threads as well
+      const bool split = L.size() < 4 && (int64_t)w * h * nr > (1 << 22);
+      // the right-hand sides are the inner, contiguous loop (same order of
+      // the sum over c for each of them)
+      auto yrow = [&](int64_t i) {
+        const int64_t o = i * (i + 1) / 2;
+        double* t = y.data() + (size_t)(c0 + i) * nr;
+        for (int r = 0; r < nr; ++r) t[r] = 0;
+        for (int c = 0; c <= i; ++c) {
+          const double l = Lv[o + c];
+          const double* fc = fr.data() + (size_t)c * nr;
+          for (int r = 0; r < nr; ++r) t[r] += l * fc[r];
         }
-        o += i + 1;
-      }
-      for (int a = 0; a < h - w; ++a) {
-        const double* Mr = Lv + o + (int64_t)a * w;
-        for (int r = 0; r < nr; ++r) {
-          double t = fr[(size_t)(w + a) * nr + r];
-          for (int c = 0; c < w; ++c) t -= Mr[c] * fr[(size_t)c * nr + r];
-          u[(size_t)(f.rowoff[s] + a) * nr + r] = t;
+      };
+      auto urow = [&](int64_t a) {
+        const double* Mr = Lv + tri + a * w;
+        double* t = u.data() + (size_t)(f.rowoff[s] + a) * nr;
+        for (int r = 0; r < nr; ++r) t[r] = fr[(size_t)(w + a) * nr + r];
+        for (int c = 0; c < w; ++c) {
+          const double l = Mr[c];
+          const double* fc = fr.data() + (size_t)c * nr;
+          for (int r = 0; r < nr; ++r) t[r] -= l * fc[r];
         }
+      };
+      if (split) {
+        parallel_for(w, yrow, 16);
+        parallel_for(h - w, urow, 16);
+      } else {
+        for (int i = 0; i < w; ++i) yrow(i);
+        for (int a = 0; a < h - w; ++a) urow(a);
       }
-    }
-    std::vector<double> xs((size_t)f.nf * nr, 0.0);
-    std::vector<double> acc;
-    for (int s = ns - 1; s >= 0; --s) {
+    });
+  }
+  std::vector<double> xs((size_t)f.nf * nr, 0.0);
+  for (int lv = f.nlevels - 1; lv >= 0; --lv) {
+    const auto& L = by_level[lv];
+    parallel_for((int64_t)L.size(), [&](int64_t idx) {
+      const int s = L[idx];
       const int w = f.w[s], h = f.h[s];
       const int32_t c0 = f.col0[s];
       const double* Lv = f.vals.data() + f.valoff[s];
       const int32_t* rows_s = f.rows.data() + f.rowoff[s];
-      acc.assign((size_t)w * nr, 0.0);
+      std::vector<double> acc((size_t)w * nr, 0.0);
       int64_t o = 0;
       for (int i = 0; i < w; ++i) {
         for (int c = 0; c <= i; ++c)
@@ -866,13 +887,10 @@ void host_factor_solve(const Factor& f, int nrhs, const double* b, double* x) {
       }
       for (int c = 0; c < w; ++c)
         for (int r = 0; r < nr; ++r) xs[(size_t)(c0 + c) * nr + r] = acc[(size_t)c * nr + r];
-    }
-    for (int64_t i = 0; i < f.nf; ++i)
-      for (int r = 0; r < nr; ++r) x[(size_t)i * nrhs + r0 + r] = xs[(size_t)i * nr + r];
-  };
-  for (int t = 1; t < T; ++t) th.emplace_back(run, t * per, std::min(nrhs, (t + 1) * per));
-  run(0, std::min(nrhs, per));
-  for (auto& t : th) t.join();
+    });
+  }
+  for (int64_t i = 0; i < f.nf; ++i)
+    for (int r = 0; r < nr; ++r) x[(size_t)i * nrhs + r] = xs[(size_t)i * nr + r];
 }
 
 void host_lff_apply(const HostMesh& hm, int nrhs, const double* x, double* y) {
