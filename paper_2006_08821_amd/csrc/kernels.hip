@@ -1369,6 +1369,9 @@ DEV void b_gram(const DevMesh& d, int bid) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // branch-free body (lanes k = 3 add zero to y), two elements per step, so
+    // the LDS reads of the next element are issued under this one's products
+#pragma unroll 2
     for (int el = 0; el < ne; ++el) {
       const T* zr = zw[el];
       const T g0 = gw[el][3 * j], g1 = gw[el][3 * j + 1], g2 = gw[el][3 * j + 2];
@@ -1380,7 +1383,7 @@ DEV void b_gram(const DevMesh& d, int bid) {
         const T bv = zr[p * 9 + kk * 3] * g0 + zr[p * 9 + kk * 3 + 1] * g1 + zr[p * 9 + kk * 3 + 2] * g2;
         acc[p] = MfmaAcc<T>::mma(av, bv, acc[p]);
       }
-      if (k < 3) yacc += wv * (zr[54 + 3 * k] * g0 + zr[54 + 3 * k + 1] * g1 + zr[54 + 3 * k + 2] * g2);
+      yacc += (k < 3 ? wv : T(0)) * (zr[54 + 3 * kk] * g0 + zr[54 + 3 * kk + 1] * g1 + zr[54 + 3 * kk + 2] * g2);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
