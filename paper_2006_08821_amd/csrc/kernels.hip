@@ -1150,10 +1150,11 @@ __global__ void __launch_bounds__(kBlock) k_element_hess(DevMesh d) { b_element_
 //   y[(c,j)]            += w (R D(gbar) gphi_j)[c]
 // Each wave owns a contiguous run of elements.  Phase A: one lane per element
 // (batches of kGramBatch) forms the six 3x3 coordinate-pair blocks of Z, R D(gbar),
-// w and the 16 mode gradients into the wave's LDS rows.  Phase B, per element:
-// lane (j, k) = (l % 16, l / 16) reads gphi_j, and for each pair one 16x16x4
-// matrix-core product accumulates A = w^2 gphi[j][k] (k < 3, else 0) against
-// B = (Z_{cc'} gphi_j)[k], i.e. the 16x16 pair block.  Waves are added in a
+// w and the 16 mode gradients into the wave's LDS rows.  Phase B: for each
+// pair block, 16x16x4 matrix-core products whose K index runs over the
+// batch's (element e, coordinate k) pairs, four per product; lane
+// (j, s) = (l % 16, l / 16) supplies A = w_e^2 gphi_j[k] and
+// B = (Z_{cc'} gphi_j)[k] for the pair in K slot s.  Waves are added in a
 // fixed order at the end.
 constexpr int kGramBatch = 16;
 constexpr int kGramRow = 65;   // 54 block entries + 9 + 1, padded to an odd stride
@@ -1308,11 +1309,11 @@ DEV void b_gram(const DevMesh& d, int bid) {
   const int perw = (per + 3) / 4;
   const int w0 = min(e1, e0 + wave * perw), w1 = min(e1, w0 + perw);
   const int k1 = d.k1;
-  const int j = lane & 15, k = lane >> 4, kk = k < 3 ? k : 2;
+  const int j = lane & 15, k = lane >> 4;
   v4 acc[6];
 #pragma unroll
   for (int p = 0; p < 6; ++p) acc[p] = v4{0, 0, 0, 0};
-  T yacc = 0;
+  T y0 = 0, y1 = 0, y2 = 0;  // y[(c, j)] partials of this lane's K slot
   for (int base = w0; base < w1; base += kGramBatch) {
     const int ne = min(kGramBatch, w1 - base);
     if (lane < ne) {
@@ -1369,26 +1370,47 @@ DEV void b_gram(const DevMesh& d, int bid) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // branch-free body (lanes k = 3 add zero to y), two elements per step, so
-    // the LDS reads of the next element are issued under this one's products
+    // The K dimension of each product runs over (element, coordinate) pairs
+    // of the batch: step st takes the pairs f = 4 st + ks (ks = lane / 16, the
+    // lane's K slot) with element f / 3 and coordinate f % 3, so all four
+    // slots carry data (twelve products per pair block for sixteen elements
+    // instead of sixteen with one slot empty).  A lane's A value (row i) and
+    // B value (column j) both belong to its slot's pair.
+    const int nst = (3 * ne + 3) / 4;
 #pragma unroll 2
-    for (int el = 0; el < ne; ++el) {
-      const T* zr = zw[el];
-      const T g0 = gw[el][3 * j], g1 = gw[el][3 * j + 1], g2 = gw[el][3 * j + 2];
-      const T wv = zr[63];
-      const T gk = k == 0 ? g0 : (k == 1 ? g1 : g2);
-      const T av = k < 3 ? wv * wv * gk : T(0);
+    for (int st = 0; st < nst; ++st) {
+      const int f = 4 * st + k;
+      const bool valid = f < 3 * ne;
+      const int e = valid ? f / 3 : 0;
+      const int kc = valid ? f - 3 * e : 0;
+      const T* zr = zw[e];
+      const T g0 = gw[e][3 * j], g1 = gw[e][3 * j + 1], g2 = gw[e][3 * j + 2];
+      const T wv = valid ? zr[63] : T(0);
+      const T gk = kc == 0 ? g0 : (kc == 1 ? g1 : g2);
+      const T av = wv * wv * gk;
 #pragma unroll
       for (int p = 0; p < 6; ++p) {
-        const T bv = zr[p * 9 + kk * 3] * g0 + zr[p * 9 + kk * 3 + 1] * g1 + zr[p * 9 + kk * 3 + 2] * g2;
+        const T bv = zr[p * 9 + kc * 3] * g0 + zr[p * 9 + kc * 3 + 1] * g1 + zr[p * 9 + kc * 3 + 2] * g2;
         acc[p] = MfmaAcc<T>::mma(av, bv, acc[p]);
       }
-      yacc += (k < 3 ? wv : T(0)) * (zr[54 + 3 * kk] * g0 + zr[54 + 3 * kk + 1] * g1 + zr[54 + 3 * kk + 2] * g2);
+      const T yv = wv * (zr[54 + 3 * kc] * g0 + zr[54 + 3 * kc + 1] * g1 + zr[54 + 3 * kc + 2] * g2);
+      y0 += kc == 0 ? yv : T(0);
+      y1 += kc == 1 ? yv : T(0);
+      y2 += kc == 2 ? yv : T(0);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
+  // y[(c, j)]: add the four K slots of mode j (lanes j + 16 ks), then lane
+  // j + 16 c (c < 3) holds coordinate c
+#pragma unroll
+  for (int off = 16; off <= 32; off <<= 1) {
+    y0 += __shfl_xor(y0, off);
+    y1 += __shfl_xor(y1, off);
+    y2 += __shfl_xor(y2, off);
+  }
+  const T yacc = k == 0 ? y0 : (k == 1 ? y1 : y2);
   // add the waves in a fixed order (0 + 1 + 2 + 3) through LDS, then write
   __syncthreads();
   double* comb = sbuf;
