@@ -396,9 +396,8 @@ DEV bool chol_packed(const T (&A)[N][N], T* L) {
 #pragma unroll
     for (int k = 0; k < j; ++k) s -= L[j * (j + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
     if (!(s > T(0))) return false;
-    T d = sqrt(s);
-    L[j * (j + 1) / 2 + j] = d;
-    const T rd = T(1) / d;
+    const T rd = rsq(s);  // 1 / sqrt(s) without a division
+    L[j * (j + 1) / 2 + j] = s * rd;
 #pragma unroll
     for (int i = j + 1; i < N; ++i) {
       T t = A[i][j];
