@@ -193,10 +193,19 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
         }
       }
     }
-    std::vector<int32_t> gptr(front[fac.ns] + 1, 0), gsrc;
+    // per front position: the first two update rows inline and the range of
+    // the rest in gsrc (usually empty), so one load gives every index
+    std::vector<int4> gs4(front[fac.ns]);
+    std::vector<int32_t> gsrc;
     for (size_t i = 0; i < lists.size(); ++i) {
-      gsrc.insert(gsrc.end(), lists[i].begin(), lists[i].end());
-      gptr[i + 1] = (int32_t)gsrc.size();
+      const auto& l = lists[i];
+      int4 g;
+      g.x = l.size() > 0 ? l[0] : -1;
+      g.y = l.size() > 1 ? l[1] : -1;
+      g.z = (int32_t)gsrc.size();
+      for (size_t q = 2; q < l.size(); ++q) gsrc.push_back(l[q]);
+      g.w = (int32_t)gsrc.size();
+      gs4[i] = g;
     }
     std::vector<emu::SweepItem> fwd, bwd;
     auto item = [&](int s, int first) {
@@ -263,7 +272,7 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
       }
       B.put(SLOT(tvals), tv);
     }
-    B.put(SLOT(gptr), gptr);
+    B.put(SLOT(gs4), gs4);
     B.put(SLOT(gsrc), gsrc);
     B.put(SLOT(fwd_items), fwd);
     B.put(SLOT(bwd_items), bwd);

@@ -48,7 +48,7 @@ struct Ctl {
 // A work item of a triangular sweep with its supernode's metadata, read by
 // the workgroup in one scalar load: first row (forward) or column (backward),
 // with kItemWideBit marking 32 lanes per row; supernode width w, height h,
-// first column col0, frontal offset into gptr, row offset, value offset.
+// first column col0, frontal offset into gs4, row offset, value offset.
 struct SweepItem {
   int64_t valoff;
   int32_t first, w, h, col0, front, rowoff;
@@ -95,7 +95,8 @@ struct DevMesh {
   const int32_t* rows;
   const double* vals;         // forward blocks [Linv; M], packed rows
   const double* tvals;        // the same blocks transposed (columns of L as rows)
-  const int32_t* gptr;       // [sum h + 1] children's update rows per front position
+  const int4* gs4;           // [sum h] per front position: first two children's update rows
+                             // (-1: none) and the range [z, w) of the others in gsrc
   const int32_t* gsrc;
   const SweepItem* fwd_items;  // per forward work item: first row and its supernode
   const SweepItem* bwd_items;  // per backward work item: first column and its supernode

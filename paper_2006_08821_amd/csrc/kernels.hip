@@ -822,6 +822,30 @@ constexpr int kItemWide = kItemWideBit;
 // Forward sweep of one level.  Work item (s, r0): rows [r0, r0 + 256/LPR) of
 // supernode s.  Frontal vector f = [rhs at the columns; 0] + children's update
 // vectors; rows r < w give y = Linv f_top, rows r >= w give u = f_r - M_r f_top.
+// Sum of the children's update rows landing on front position pos (the
+// first two from the position's record, the rest from gsrc), in list order.
+DEV void gather_updates(const DevMesh& d, int pos, double& a0, double& a1, double& a2) {
+  const int4 g = d.gs4[pos];
+  if (g.x >= 0) {
+    const double* u = d.upd + 3 * (int64_t)g.x;
+    a0 += u[0];
+    a1 += u[1];
+    a2 += u[2];
+  }
+  if (g.y >= 0) {
+    const double* u = d.upd + 3 * (int64_t)g.y;
+    a0 += u[0];
+    a1 += u[1];
+    a2 += u[2];
+  }
+  for (int q = g.z; q < g.w; ++q) {
+    const double* u = d.upd + 3 * (int64_t)d.gsrc[q];
+    a0 += u[0];
+    a1 += u[1];
+    a2 += u[2];
+  }
+}
+
 template <int LPR>
 DEV void fwd_item(const DevMesh& d, const SweepItem& it, int r0, double* ft) {
   const int w = it.w, h = it.h, col0 = it.col0;
@@ -831,18 +855,20 @@ DEV void fwd_item(const DevMesh& d, const SweepItem& it, int r0, double* ft) {
   // the rows of this item need f_top entries [0, min(w, r0 + nrows))
   const int need = min(w, r0 + nrows);
   double acc[3] = {0, 0, 0};
+  // children's updates to this group's row (rows below the diagonal block),
+  // requested first so they overlap the frontal assembly
+  const int lane = t & 63, wave = t >> 6, g = lane / LPR, l = lane % LPR;
+  const int rr = wave * (64 / LPR) + g;
+  const int r = r0 + rr;
+  double b0 = 0, b1 = 0, b2 = 0;
+  if (l == 0 && rr < nrows && r >= w) gather_updates(d, fo + r, b0, b1, b2);
   for (int vb = 0; vb < need; vb += kVecChunk) {
     const int vl = min(kVecChunk, need - vb);
     __syncthreads();
     for (int k = t; k < vl; k += kBlock) {
       const int c = vb + k;
       double a0 = d.rhs[3 * (col0 + c)], a1 = d.rhs[3 * (col0 + c) + 1], a2 = d.rhs[3 * (col0 + c) + 2];
-      for (int q = d.gptr[fo + c]; q < d.gptr[fo + c + 1]; ++q) {
-        const double* u = d.upd + 3 * (int64_t)d.gsrc[q];
-        a0 += u[0];
-        a1 += u[1];
-        a2 += u[2];
-      }
+      gather_updates(d, fo + c, a0, a1, a2);
       ft[3 * k] = a0;
       ft[3 * k + 1] = a1;
       ft[3 * k + 2] = a2;
@@ -850,22 +876,12 @@ DEV void fwd_item(const DevMesh& d, const SweepItem& it, int r0, double* ft) {
     __syncthreads();
     row_products<true, LPR>(d.vals, it.valoff, w, h, r0, nrows, ft, vb, vl, acc);
   }
-  const int lane = t & 63, wave = t >> 6, g = lane / LPR, l = lane % LPR;
-  const int rr = wave * (64 / LPR) + g;
-  const int r = r0 + rr;
   if (l == 0 && rr < nrows) {
     if (r < w) {
       d.ybuf[3 * (col0 + r)] = acc[0];
       d.ybuf[3 * (col0 + r) + 1] = acc[1];
       d.ybuf[3 * (col0 + r) + 2] = acc[2];
     } else {
-      double b0 = 0, b1 = 0, b2 = 0;
-      for (int q = d.gptr[fo + r]; q < d.gptr[fo + r + 1]; ++q) {
-        const double* u = d.upd + 3 * (int64_t)d.gsrc[q];
-        b0 += u[0];
-        b1 += u[1];
-        b2 += u[2];
-      }
       double* o = d.upd + 3 * (int64_t)(it.rowoff + r - w);
       o[0] = b0 - acc[0];
       o[1] = b1 - acc[1];
