@@ -1470,6 +1470,7 @@ DEV void b_gram_reduce(const DevMesh& d, int bid) {
   double s0 = 0, s1 = 0;
   if (e < kGramEntries) {
     int b = part;
+#pragma unroll 4
     for (; b + 16 < d.nbg; b += 32) {
       s0 += d.part_gram[(int64_t)b * kGramEntries + e];
       s1 += d.part_gram[(int64_t)(b + 16) * kGramEntries + e];
@@ -1501,33 +1502,75 @@ DEV void b_control_a(const DevMesh& d, int bid) {
   __shared__ double yv[48];
   __shared__ int flag;
   const int t = threadIdx.x;
+  // Every global load of this prologue (the partial sums, the Gram entries
+  // of C and y) is issued before the first one is used: they are L2 misses
+  // (written by other workgroups), and one workgroup has nothing else to
+  // hide their latency behind.
+  const int k1 = d.k1, K = 3 * k1;
+  constexpr int kPU = 4;  // partials per thread in the first round (nb <= 1024)
+  double pe[kPU][2], pg[kPU][2];
+  int pc[kPU][2];
+#pragma unroll
+  for (int u = 0; u < kPU; ++u) {
+    const int b = t + u * kCtlThreads;
+    const bool ok = b < d.nb;
+    pe[u][0] = ok ? d.part_e[2 * b] : 0.0;
+    pe[u][1] = ok ? d.part_e[2 * b + 1] : 0.0;
+    pg[u][0] = ok ? d.part_g[2 * b] : 0.0;
+    pg[u][1] = ok ? d.part_g[2 * b + 1] : 0.0;
+    pc[u][0] = ok ? d.part_cnt[2 * b] : 0;
+    pc[u][1] = ok ? d.part_cnt[2 * b + 1] : 0;
+  }
+  // C = Lambda - alpha Gram, lower triangle, padded to 48 x 48 with the
+  // identity (unused modes); row r = (c, j) with c = r / k1, j = r % k1
+  constexpr int kCU = (48 * 48 + kCtlThreads - 1) / kCtlThreads;
+  double g1v[kCU], g2v[kCU], nuv[kCU];
+#pragma unroll
+  for (int u = 0; u < kCU; ++u) {
+    const int idx = t + u * kCtlThreads;
+    const int r = idx / 48, q = idx % 48;
+    const bool in = idx < 48 * 48 && q <= r && r < K;
+    const int c = (r >= k1) + (r >= 2 * k1), j = r - c * k1;
+    const int cp = (q >= k1) + (q >= 2 * k1), jp = q - cp * k1;
+    // lower triangle: c >= cp; the stored pair is (cp, c)
+    const int pair = cp == 0 ? c : (cp == 1 ? 2 + c : 5);
+    g1v[u] = in ? d.gram[pair * 256 + jp * 16 + j] : 0.0;
+    g2v[u] = in && c == cp ? d.gram[pair * 256 + j * 16 + jp] : 0.0;
+    nuv[u] = in && r == q ? d.nu[j] : 0.0;
+  }
+  const double yload = t < K ? d.gram[1536 + ((t >= k1) + (t >= 2 * k1)) * 16 + (t - ((t >= k1) + (t >= 2 * k1)) * k1)] : 0.0;
   DD acc[2] = {DD{0, 0}, DD{0, 0}};
   int cl = 0, inv = 0;
-  for (int b = t; b < d.nb; b += kCtlThreads) {
+#pragma unroll
+  for (int u = 0; u < kPU; ++u)
+    if (t + u * kCtlThreads < d.nb) {
+      acc[0] = dd_add(acc[0], DD{pe[u][0], pe[u][1]});
+      acc[1] = dd_add(acc[1], DD{pg[u][0], pg[u][1]});
+      cl += pc[u][0];
+      inv += pc[u][1];
+    }
+  for (int b = t + kPU * kCtlThreads; b < d.nb; b += kCtlThreads) {
     acc[0] = dd_add(acc[0], DD{d.part_e[2 * b], d.part_e[2 * b + 1]});
     acc[1] = dd_add(acc[1], DD{d.part_g[2 * b], d.part_g[2 * b + 1]});
     cl += d.part_cnt[2 * b];
     inv += d.part_cnt[2 * b + 1];
   }
-  // C and y do not depend on the convergence decision: load them now.  The
-  // system is padded to 48 x 48 with the identity (unused modes).
-  const int k1 = d.k1, K = 3 * k1;
-  for (int idx = t; idx < 48 * 48; idx += kCtlThreads) {
+#pragma unroll
+  for (int u = 0; u < kCU; ++u) {
+    const int idx = t + u * kCtlThreads;
     const int r = idx / 48, q = idx % 48;
-    if (q > r) continue;
-    double v = (r == q) ? 1.0 : 0.0;
-    if (r < K && q < K) {
-      const int c = r / k1, j = r % k1, cp = q / k1, jp = q % k1;
-      // lower triangle: c >= cp; the stored pair is (cp, c)
-      const int pair = cp == 0 ? c : (cp == 1 ? 2 + c : 5);
-      const double g1 = d.gram[pair * 256 + jp * 16 + j];
-      double g = g1;
-      if (c == cp) g = 0.5 * (g1 + d.gram[pair * 256 + j * 16 + jp]);
-      v = (r == q ? d.nu[j] : 0.0) - d.alpha * g;
+    if (idx < 48 * 48 && q <= r) {
+      double v = (r == q) ? 1.0 : 0.0;
+      if (r < K) {
+        const int c = (r >= k1) + (r >= 2 * k1);
+        const int cp = (q >= k1) + (q >= 2 * k1);
+        const double g = c == cp ? 0.5 * (g1v[u] + g2v[u]) : g1v[u];
+        v = nuv[u] - d.alpha * g;
+      }
+      Cm[r][q] = v;
     }
-    Cm[r][q] = v;
   }
-  for (int r = t; r < 48; r += kCtlThreads) yv[r] = r < K ? d.gram[1536 + (r / k1) * 16 + (r % k1)] : 0.0;
+  if (t < 48) yv[t] = yload;
   block_reduce_dd<2, kCtlThreads>(acc, sh);
   const int cl_sum = block_sum_int<kCtlThreads>(cl, cnt[0]);
   const int inv_sum = block_sum_int<kCtlThreads>(inv, cnt[1]);
@@ -1556,7 +1599,8 @@ DEV void b_control_a(const DevMesh& d, int bid) {
   if (flag || K == 0) return;
   // Blocked Cholesky of the padded 48 x 48 system by the whole workgroup, in
   // panels of four columns (two barriers per panel).  Phase A: every thread
-  // factors the 4x4 diagonal block (redundantly, from LDS) and thread t
+  // factors the 4x4 diagonal block (redundantly, from LDS; pivots by one
+  // reciprocal square root), thread 0 stores it and thread t below it
   // solves its row of the panel, L[t][jb..jb+3], into LDS.  Phase B: thread
   // t owns the lower-triangle entries e = t + 256 q (kept in registers) and
   // subtracts the panel's rank-4 product from those right of the panel; the
@@ -1570,10 +1614,14 @@ DEV void b_control_a(const DevMesh& d, int bid) {
   double ev[kOwn];
 #pragma unroll
   for (int q = 0; q < kOwn; ++q) {
-    int e = t + q * kCtlThreads, r = 0;
+    int e = t + q * kCtlThreads;
     if (e >= 48 * 49 / 2) e = -1;
-    if (e >= 0)
-      while ((r + 1) * (r + 2) / 2 <= e) ++r;
+    // row of packed lower-triangle entry e: r (r + 1) / 2 <= e < (r + 1) (r + 2) / 2,
+    // from the float root (within one of the exact value for e < 1176) and
+    // one correction each way
+    int r = e >= 0 ? (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f) : 0;
+    r += (r + 1) * (r + 2) / 2 <= e ? 1 : 0;
+    r -= r * (r + 1) / 2 > e ? 1 : 0;
     er[q] = e >= 0 ? r : 0;
     ec[q] = e >= 0 ? e - r * (r + 1) / 2 : 48;  // 48: not owned
     ev[q] = e >= 0 ? Cm[er[q]][ec[q]] : 0.0;
@@ -1590,31 +1638,32 @@ DEV void b_control_a(const DevMesh& d, int bid) {
         for (int k = 0; k < j; ++k) x -= Lb[i][k] * Lb[j][k];
         if (i == j) {
           nbad_local += !(x > 0);
-          Lb[i][i] = x > 0 ? sqrt(x) : 1.0;
-          rdg[i] = 1.0 / Lb[i][i];
+          const double rx = x > 0 ? rsq(x) : 1.0;
+          Lb[i][i] = x > 0 ? x * rx : 1.0;
+          rdg[i] = rx;
         } else {
           Lb[i][j] = x * rdg[j];
         }
       }
-    if (t >= jb && t < 48) {
-      if (t < jb + NB) {
-        const int i = t - jb;
+    if (t == 0) {
 #pragma unroll
-        for (int j = 0; j < NB; ++j)
-          if (j <= i) Cm[t][jb + j] = Lb[i][j];
-        invp[t] = rdg[i];
-      } else {
-        double l[NB];
+      for (int i = 0; i < NB; ++i) {
 #pragma unroll
-        for (int k = 0; k < NB; ++k) {
-          double x = Cm[t][jb + k];
-#pragma unroll
-          for (int m = 0; m < k; ++m) x -= l[m] * Lb[k][m];
-          l[k] = x * rdg[k];
-        }
-#pragma unroll
-        for (int k = 0; k < NB; ++k) Cm[t][jb + k] = l[k];
+        for (int j = 0; j <= i; ++j) Cm[jb + i][jb + j] = Lb[i][j];
+        invp[jb + i] = rdg[i];
       }
+    }
+    if (t >= jb + NB && t < 48) {
+      double l[NB];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        double x = Cm[t][jb + k];
+#pragma unroll
+        for (int m = 0; m < k; ++m) x -= l[m] * Lb[k][m];
+        l[k] = x * rdg[k];
+      }
+#pragma unroll
+      for (int k = 0; k < NB; ++k) Cm[t][jb + k] = l[k];
     }
     __syncthreads();
 #pragma unroll
