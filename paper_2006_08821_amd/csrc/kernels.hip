@@ -1194,9 +1194,11 @@ struct MfmaAcc<float> {
 };
 
 // Z blocks of one element (phase A): zr[p * 9 + a * 3 + b] = Z[3c + a][3c' + b]
-// for the pairs p = (0,0) (0,1) (0,2) (1,1) (1,2) (2,2).
+// for the pairs p = (0,0) (0,1) (0,2) (1,1) (1,2) (2,2).  The lane computes
+// the entries whose first F coordinate is c (c = 0, 1, 2: three lanes per
+// element share the work; c = 3 computes and stores nothing useful).
 template <typename T>
-DEV void gram_zblocks(const DevMesh& d, int i, T* zr) {
+DEV void gram_zblocks(const DevMesh& d, int i, int c, T* zr) {
   const int m = d.m;
   T R[9];
 #pragma unroll
@@ -1250,6 +1252,9 @@ DEV void gram_zblocks(const DevMesh& d, int i, T* zr) {
   }
   // per gradient-direction pair (dd <= dp): M[e][e'] = (Y H^{-1} Y^T)[(e,dd),(e',dp)],
   // then Z[(c,dd),(c',dp)] = (R M R^T)[c][c'], stored in the block of (min, max)(c, c')
+  const int cr = c < 2 ? c : 2;
+  const T Rc[3] = {cr == 0 ? R[0] : (cr == 1 ? R[3] : R[6]), cr == 0 ? R[1] : (cr == 1 ? R[4] : R[7]),
+                   cr == 0 ? R[2] : (cr == 1 ? R[5] : R[8])};
 #pragma unroll
   for (int dd = 0; dd < 3; ++dd)
 #pragma unroll
@@ -1279,28 +1284,24 @@ DEV void gram_zblocks(const DevMesh& d, int i, T* zr) {
             }
           Mx[e][ep] = v;
         }
-      T RM[3][3];
+      T RM[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
+      for (int ep = 0; ep < 3; ++ep) RM[ep] = Rc[0] * Mx[0][ep] + Rc[1] * Mx[1][ep] + Rc[2] * Mx[2][ep];
 #pragma unroll
-        for (int ep = 0; ep < 3; ++ep)
-          RM[c][ep] = R[3 * c] * Mx[0][ep] + R[3 * c + 1] * Mx[1][ep] + R[3 * c + 2] * Mx[2][ep];
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int cp = 0; cp < 3; ++cp) {
-          if (dd == dp && cp < c) continue;
-          const T v = RM[c][0] * R[3 * cp] + RM[c][1] * R[3 * cp + 1] + RM[c][2] * R[3 * cp + 2];
-          // v = Z[3c + dd][3cp + dp]
-          if (c <= cp) {
-            const int p = c == 0 ? cp : (c == 1 ? 2 + cp : 5);
-            zr[p * 9 + dd * 3 + dp] = v;
-            if (dd != dp && c == cp) zr[p * 9 + dp * 3 + dd] = v;
-          } else {
-            const int p = cp == 0 ? c : (cp == 1 ? 2 + c : 5);
-            zr[p * 9 + dp * 3 + dd] = v;
-          }
+      for (int cp = 0; cp < 3; ++cp) {
+        const T v = RM[0] * R[3 * cp] + RM[1] * R[3 * cp + 1] + RM[2] * R[3 * cp + 2];
+        // v = Z[3c + dd][3cp + dp]; for dd == dp the entries with cp < c
+        // are those of the lane of row cp
+        if (c > 2 || (dd == dp && cp < c)) continue;
+        if (c <= cp) {
+          const int p = c == 0 ? cp : (c == 1 ? 2 + cp : 5);
+          zr[p * 9 + dd * 3 + dp] = v;
+          if (dd != dp && c == cp) zr[p * 9 + dp * 3 + dd] = v;
+        } else {
+          const int p = cp == 0 ? c : (cp == 1 ? 2 + c : 5);
+          zr[p * 9 + dp * 3 + dd] = v;
         }
+      }
     }
 }
 
@@ -1331,31 +1332,28 @@ DEV void b_gram(const DevMesh& d, int bid) {
   T y0 = 0, y1 = 0, y2 = 0;  // y[(c, j)] partials of this lane's K slot
   for (int base = w0; base < w1; base += kGramBatch) {
     const int ne = min(kGramBatch, w1 - base);
-    if (lane < ne) {
-      const int i = base + lane;
-      T zr[54];
-      gram_zblocks<T>(d, i, zr);
-#pragma unroll
-      for (int q = 0; q < 54; ++q) zw[lane][q] = zr[q];
-      const T* gbar = (const T*)d.gbar;
-      double gbd[9], D[9], RD[9], Rd[9];
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        gbd[q] = (double)gbar[q * m + i];
-        Rd[q] = (double)(T)d.R[q * m + i];
-      }
-      from_y<double>(gbd, D);
-      matmul3(Rd, D, RD);
-#pragma unroll
-      for (int q = 0; q < 9; ++q) zw[lane][54 + q] = (T)RD[q];
-      zw[lane][63] = (T)d.w[i];
-    }
     {
-      // mode gradients gphi_j = sum_v phi_j(v) b_v: four lanes per element,
-      // four modes each (rows of phi are zero beyond k1 and at pins)
-      const int el = lane >> 2, q4 = 4 * (lane & 3);
+      // four lanes per element: lane s = 0, 1, 2 forms the Z entries and the
+      // row of R D(gbar) of F coordinate s, lane 3 stores w; each lane forms
+      // four of the sixteen mode gradients gphi_j = sum_v phi_j(v) b_v (rows
+      // of phi are zero beyond k1 and at pins)
+      const int el = lane >> 2, sl = lane & 3, q4 = 4 * sl;
       if (el < ne) {
         const int i = base + el;
+        gram_zblocks<T>(d, i, sl, zw[el]);
+        if (sl < 3) {
+          const T* gbar = (const T*)d.gbar;
+          double gbd[9], D[9];
+#pragma unroll
+          for (int q = 0; q < 9; ++q) gbd[q] = (double)gbar[q * m + i];
+          from_y<double>(gbd, D);
+          const double r0 = (double)(T)d.R[(3 * sl) * m + i], r1 = (double)(T)d.R[(3 * sl + 1) * m + i],
+                       r2 = (double)(T)d.R[(3 * sl + 2) * m + i];
+#pragma unroll
+          for (int q = 0; q < 3; ++q) zw[el][54 + 3 * sl + q] = (T)(r0 * D[q] + r1 * D[3 + q] + r2 * D[6 + q]);
+        } else {
+          zw[el][63] = (T)d.w[i];
+        }
         double b[4][3];
 #pragma unroll
         for (int v = 0; v < 3; ++v)
