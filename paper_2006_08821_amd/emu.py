@@ -224,9 +224,12 @@ class Mesh:
     def profile_kernels(self, reps=20):
         """Average device ms per kernel class (HIP events), {name: ms}."""
         t = self.torch
-        out = np.zeros(12)
+        names = []
+        while self._lib.emu_kernel_name(len(names)) is not None:
+            names.append(self._lib.emu_kernel_name(len(names)).decode())
+        out = np.zeros(len(names))
         check(self._lib.emu_profile_kernels(self._h, int(reps), dptr(out), _stream(t)), "emu_profile_kernels")
-        return {self._lib.emu_kernel_name(k).decode(): float(out[k]) for k in range(12)}
+        return {nm: float(out[k]) for k, nm in enumerate(names)}
 
     def evaluate(self, F, direction=True):
         """q*(F), E(F), |dE/dF| and the quasi-Newton direction at F (state unchanged)."""
