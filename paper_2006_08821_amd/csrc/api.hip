@@ -175,10 +175,15 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
   }
   // factor and level schedule
   {
-    std::vector<int32_t> front(fac.ns + 1, 0);
-    for (int s = 0; s < fac.ns; ++s) front[s + 1] = front[s] + fac.h[s];
-    // children's update rows by destination position in the parent front
-    std::vector<std::vector<int32_t>> lists(front[fac.ns]);
+    // Slot rows of the children's contributions: supernode s with nch
+    // children owns nch * h_s rows from slotbase[s]; child k (in child order)
+    // adds its update row for parent front position p into row
+    // slotbase[s] + k h_s + p.  Rows no child writes stay zero, so the parent
+    // adds all nch rows of a position without an index load.
+    std::vector<int32_t> slotbase(fac.ns + 1, 0);
+    for (int s = 0; s < fac.ns; ++s)
+      slotbase[s + 1] = slotbase[s] + (fac.child_ptr[s + 1] - fac.child_ptr[s]) * fac.h[s];
+    std::vector<int32_t> dst(std::max<int32_t>(1, fac.rowoff[fac.ns]), 0);
     for (int s = 0; s < fac.ns; ++s) {
       const int w = fac.w[s], h = fac.h[s];
       const int32_t c0 = fac.col0[s];
@@ -189,23 +194,9 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
         for (int a = 0; a < hb; ++a) {
           const int32_t v = fac.rows[fac.rowoff[c] + a];
           int p = v < c0 + w ? v - c0 : w + (int)(std::lower_bound(rs, rs + (h - w), v) - rs);
-          lists[front[s] + p].push_back(fac.rowoff[c] + a);
+          dst[fac.rowoff[c] + a] = slotbase[s] + (k - fac.child_ptr[s]) * h + p;
         }
       }
-    }
-    // per front position: the first two update rows inline and the range of
-    // the rest in gsrc (usually empty), so one load gives every index
-    std::vector<int4> gs4(front[fac.ns]);
-    std::vector<int32_t> gsrc;
-    for (size_t i = 0; i < lists.size(); ++i) {
-      const auto& l = lists[i];
-      int4 g;
-      g.x = l.size() > 0 ? l[0] : -1;
-      g.y = l.size() > 1 ? l[1] : -1;
-      g.z = (int32_t)gsrc.size();
-      for (size_t q = 2; q < l.size(); ++q) gsrc.push_back(l[q]);
-      g.w = (int32_t)gsrc.size();
-      gs4[i] = g;
     }
     std::vector<emu::SweepItem> fwd, bwd;
     auto item = [&](int s, int first) {
@@ -215,7 +206,9 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
       it.w = fac.w[s];
       it.h = fac.h[s];
       it.col0 = fac.col0[s];
-      it.front = front[s];
+      it.slotbase = slotbase[s];
+      it.nslot = fac.child_ptr[s + 1] - fac.child_ptr[s];
+      it.pad = 0;
       it.rowoff = fac.rowoff[s];
       return it;
     };
@@ -272,14 +265,13 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
       }
       B.put(SLOT(tvals), tv);
     }
-    B.put(SLOT(gs4), gs4);
-    B.put(SLOT(gsrc), gsrc);
+    B.put(SLOT(dst), dst);
     B.put(SLOT(fwd_items), fwd);
     B.put(SLOT(bwd_items), bwd);
     B.reserve(SLOT(rhs), 24 * (size_t)nf);
     B.reserve(SLOT(ybuf), 24 * (size_t)nf);
     B.reserve(SLOT(xbuf), 24 * (size_t)nf);
-    B.reserve(SLOT(upd), 24 * (size_t)std::max<int32_t>(1, fac.rowoff[fac.ns]));
+    B.put(SLOT(slots), std::vector<double>(3 * (size_t)std::max<int32_t>(1, slotbase[fac.ns]), 0.0));
   }
   B.reserve(SLOT(part_e), 16 * (size_t)d.nb);
   B.reserve(SLOT(part_g), 16 * (size_t)d.nb);

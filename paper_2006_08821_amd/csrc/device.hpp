@@ -48,10 +48,11 @@ struct Ctl {
 // A work item of a triangular sweep with its supernode's metadata, read by
 // the workgroup in one scalar load: first row (forward) or column (backward),
 // with kItemWideBit marking 32 lanes per row; supernode width w, height h,
-// first column col0, frontal offset into gs4, row offset, value offset.
+// first column col0, first slot row of the children's contributions and the
+// number of children (nslot), row offset, value offset.
 struct SweepItem {
   int64_t valoff;
-  int32_t first, w, h, col0, front, rowoff;
+  int32_t first, w, h, col0, slotbase, nslot, rowoff, pad;
 };
 
 struct DevMesh {
@@ -95,15 +96,15 @@ struct DevMesh {
   const int32_t* rows;
   const double* vals;         // forward blocks [Linv; M], packed rows
   const double* tvals;        // the same blocks transposed (columns of L as rows)
-  const int4* gs4;           // [sum h] per front position: first two children's update rows
-                             // (-1: none) and the range [z, w) of the others in gsrc
-  const int32_t* gsrc;
+  const int32_t* dst;        // per update row: its slot row (slotbase of the parent +
+                             // child index * parent height + position in the parent front)
   const SweepItem* fwd_items;  // per forward work item: first row and its supernode
   const SweepItem* bwd_items;  // per backward work item: first column and its supernode
   double* rhs;               // [nf][3]
   double* ybuf;              // [nf][3]
   double* xbuf;              // [nf][3]
-  double* upd;               // [rows][3]
+  double* slots;             // [sum nchildren * h][3] children's contributions per parent
+                             // front position; rows no child writes stay zero
 
   // reductions
   double* part_e;            // [nb][2]

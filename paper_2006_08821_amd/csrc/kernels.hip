@@ -821,25 +821,25 @@ constexpr int kItemWide = kItemWideBit;
 
 // Forward sweep of one level.  Work item (s, r0): rows [r0, r0 + 256/LPR) of
 // supernode s.  Frontal vector f = [rhs at the columns; 0] + children's update
-// vectors; rows r < w give y = Linv f_top, rows r >= w give u = f_r - M_r f_top.
-// Sum of the children's update rows landing on front position pos (the
-// first two from the position's record, the rest from gsrc), in list order.
-DEV void gather_updates(const DevMesh& d, int pos, double& a0, double& a1, double& a2) {
-  const int4 g = d.gs4[pos];
-  if (g.x >= 0) {
-    const double* u = d.upd + 3 * (int64_t)g.x;
-    a0 += u[0];
-    a1 += u[1];
-    a2 += u[2];
+// vectors; rows r < w give y = Linv f_top, rows r >= w give u = f_r - M_r f_top,
+// written to the slot row of the parent front position that row r lands on.
+// Sum of the children's slot rows of front position pos (zero where a child
+// has no update row), added in child order.
+DEV void gather_updates(const DevMesh& d, const SweepItem& it, int pos, double& a0, double& a1, double& a2) {
+  const double* u = d.slots + 3 * ((int64_t)it.slotbase + pos);
+  const int64_t step = 3 * (int64_t)it.h;
+  int k = 0;
+  for (; k + 1 < it.nslot; k += 2, u += 2 * step) {
+    const double x0 = u[0], x1 = u[1], x2 = u[2];
+    const double y0 = u[step], y1 = u[step + 1], y2 = u[step + 2];
+    a0 += x0;
+    a1 += x1;
+    a2 += x2;
+    a0 += y0;
+    a1 += y1;
+    a2 += y2;
   }
-  if (g.y >= 0) {
-    const double* u = d.upd + 3 * (int64_t)g.y;
-    a0 += u[0];
-    a1 += u[1];
-    a2 += u[2];
-  }
-  for (int q = g.z; q < g.w; ++q) {
-    const double* u = d.upd + 3 * (int64_t)d.gsrc[q];
+  if (k < it.nslot) {
     a0 += u[0];
     a1 += u[1];
     a2 += u[2];
@@ -849,7 +849,6 @@ DEV void gather_updates(const DevMesh& d, int pos, double& a0, double& a1, doubl
 template <int LPR>
 DEV void fwd_item(const DevMesh& d, const SweepItem& it, int r0, double* ft) {
   const int w = it.w, h = it.h, col0 = it.col0;
-  const int fo = it.front;
   const int t = threadIdx.x;
   const int nrows = min(256 / LPR, h - r0);
   // the rows of this item need f_top entries [0, min(w, r0 + nrows))
@@ -861,14 +860,18 @@ DEV void fwd_item(const DevMesh& d, const SweepItem& it, int r0, double* ft) {
   const int rr = wave * (64 / LPR) + g;
   const int r = r0 + rr;
   double b0 = 0, b1 = 0, b2 = 0;
-  if (l == 0 && rr < nrows && r >= w) gather_updates(d, fo + r, b0, b1, b2);
+  int32_t orow = 0;
+  if (l == 0 && rr < nrows && r >= w) {
+    orow = d.dst[it.rowoff + r - w];
+    gather_updates(d, it, r, b0, b1, b2);
+  }
   for (int vb = 0; vb < need; vb += kVecChunk) {
     const int vl = min(kVecChunk, need - vb);
     __syncthreads();
     for (int k = t; k < vl; k += kBlock) {
       const int c = vb + k;
       double a0 = d.rhs[3 * (col0 + c)], a1 = d.rhs[3 * (col0 + c) + 1], a2 = d.rhs[3 * (col0 + c) + 2];
-      gather_updates(d, fo + c, a0, a1, a2);
+      gather_updates(d, it, c, a0, a1, a2);
       ft[3 * k] = a0;
       ft[3 * k + 1] = a1;
       ft[3 * k + 2] = a2;
@@ -882,7 +885,7 @@ DEV void fwd_item(const DevMesh& d, const SweepItem& it, int r0, double* ft) {
       d.ybuf[3 * (col0 + r) + 1] = acc[1];
       d.ybuf[3 * (col0 + r) + 2] = acc[2];
     } else {
-      double* o = d.upd + 3 * (int64_t)(it.rowoff + r - w);
+      double* o = d.slots + 3 * (int64_t)orow;
       o[0] = b0 - acc[0];
       o[1] = b1 - acc[1];
       o[2] = b2 - acc[2];
