@@ -1499,7 +1499,7 @@ DEV void b_control_a(const DevMesh& d, int bid) {
   if (ctl->done) return;
   __shared__ DD sh[2 * kCtlThreads];
   __shared__ int cnt[2][kCtlThreads];
-  __shared__ double Cm[48][49];
+  __shared__ double Cm[49][49];  // C (48 x 48, lower) and y as row 48
   __shared__ double yv[48];
   __shared__ int flag;
   const int t = threadIdx.x;
@@ -1571,7 +1571,7 @@ DEV void b_control_a(const DevMesh& d, int bid) {
       Cm[r][q] = v;
     }
   }
-  if (t < 48) yv[t] = yload;
+  if (t < 48) Cm[48][t] = yload;
   block_reduce_dd<2, kCtlThreads>(acc, sh);
   const int cl_sum = block_sum_int<kCtlThreads>(cl, cnt[0]);
   const int inv_sum = block_sum_int<kCtlThreads>(inv, cnt[1]);
@@ -1599,7 +1599,9 @@ DEV void b_control_a(const DevMesh& d, int bid) {
   __syncthreads();
   if (flag || K == 0) return;
   // Blocked Cholesky of the padded 48 x 48 system by the whole workgroup, in
-  // panels of four columns (two barriers per panel).  Phase A: every thread
+  // panels of four columns (two barriers per panel), with y appended as row
+  // 48: the factor of [C y; y^T *] has (L^{-1} y)^T in that row, so the
+  // forward substitution comes with the factorization.  Phase A: every thread
   // factors the 4x4 diagonal block (redundantly, from LDS; pivots by one
   // reciprocal square root), thread 0 stores it and thread t below it
   // solves its row of the panel, L[t][jb..jb+3], into LDS.  Phase B: thread
@@ -1608,7 +1610,7 @@ DEV void b_control_a(const DevMesh& d, int bid) {
   // entries of the next panel go to LDS.  A non-positive pivot marks the
   // system as failed (z = 0 below).
   constexpr int NB = 4;
-  constexpr int kOwn = (48 * 49 / 2 + kCtlThreads - 1) / kCtlThreads;
+  constexpr int kOwn = (49 * 50 / 2 - 1 + kCtlThreads - 1) / kCtlThreads;
   __shared__ double invp[48];
   __shared__ int nbad;
   int er[kOwn], ec[kOwn];
@@ -1616,9 +1618,9 @@ DEV void b_control_a(const DevMesh& d, int bid) {
 #pragma unroll
   for (int q = 0; q < kOwn; ++q) {
     int e = t + q * kCtlThreads;
-    if (e >= 48 * 49 / 2) e = -1;
+    if (e >= 49 * 50 / 2 - 1) e = -1;  // every entry of rows 0..48 but (48, 48)
     // row of packed lower-triangle entry e: r (r + 1) / 2 <= e < (r + 1) (r + 2) / 2,
-    // from the float root (within one of the exact value for e < 1176) and
+    // from the float root (within one of the exact value for e < 1224) and
     // one correction each way
     int r = e >= 0 ? (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f) : 0;
     r += (r + 1) * (r + 2) / 2 <= e ? 1 : 0;
@@ -1654,7 +1656,7 @@ DEV void b_control_a(const DevMesh& d, int bid) {
         invp[jb + i] = rdg[i];
       }
     }
-    if (t >= jb + NB && t < 48) {
+    if (t >= jb + NB && t < 49) {
       double l[NB];
 #pragma unroll
       for (int k = 0; k < NB; ++k) {
@@ -1687,24 +1689,17 @@ DEV void b_control_a(const DevMesh& d, int bid) {
     d.cfac[idx] = c <= r ? Cm[r][c] : 0.0;
   }
   if (t >= 64) return;
-  // substitutions in the first wave: lane t holds entry t; the newly solved
-  // entry is broadcast with readlane.  Lane t's row (forward) and column
-  // (backward) of L and the pivots are read from LDS ahead of the dependent
-  // chains, which then run on registers only.
-  double yt = t < 48 ? yv[t] : 0.0;
+  // backward substitution L^T z = L^{-1} y in the first wave (the forward one
+  // is row 48 of the factor): lane t holds entry t; the newly solved entry is
+  // broadcast with readlane.  Lane t's column of L and the pivots are read
+  // from LDS ahead of the dependent chain, which then runs on registers only.
+  double yt = t < 48 ? Cm[48][t] : 0.0;
   double lv[48], ip[48];
 #pragma unroll
   for (int i = 0; i < 48; ++i) {
-    lv[i] = t < 48 && i < t ? Cm[t][i] : 0.0;
+    lv[i] = t < 48 && i > t ? Cm[i][t] : 0.0;
     ip[i] = invp[i];
   }
-#pragma unroll
-  for (int i = 0; i < 48; ++i) {
-    const double ui = bcast_lane(yt, i) * ip[i];
-    yt = t == i ? ui : yt - lv[i] * ui;
-  }
-#pragma unroll
-  for (int i = 0; i < 48; ++i) lv[i] = t < 48 && i > t ? Cm[i][t] : 0.0;
 #pragma unroll
   for (int i = 47; i >= 0; --i) {
     const double zi = bcast_lane(yt, i) * ip[i];
