@@ -96,6 +96,43 @@ DEV void block_reduce_dd(DD (&v)[NV], DD* sh) {
       v[k] = a;
     }
 }
+// block_reduce_dd of NV double-doubles together with two integer sums, all
+// behind one barrier (results in thread 0).
+template <int NV, int NT = kBlock>
+DEV void block_reduce_dd_int2(DD (&v)[NV], int& a, int& b, DD* sh, int* shi) {
+  constexpr int W = NT / 64;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = dd_add(v[k], DD{__shfl_xor(v[k].hi, off), __shfl_xor(v[k].lo, off)});
+    a += __shfl_xor(a, off);
+    b += __shfl_xor(b, off);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[k * W + wave] = v[k];
+    shi[wave] = a;
+    shi[W + wave] = b;
+  }
+  __syncthreads();
+  if (t == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      DD x = sh[k * W];
+#pragma unroll
+      for (int w = 1; w < W; ++w) x = dd_add(x, sh[k * W + w]);
+      v[k] = x;
+    }
+    a = 0;
+    b = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      a += shi[w];
+      b += shi[W + w];
+    }
+  }
+}
 // Block-wide integer sum (exact, so any order), valid in thread 0.
 template <int NT = kBlock>
 DEV int block_sum_int(int v, int* sh) {
@@ -1572,9 +1609,8 @@ DEV void b_control_a(const DevMesh& d, int bid) {
     }
   }
   if (t < 48) Cm[48][t] = yload;
-  block_reduce_dd<2, kCtlThreads>(acc, sh);
-  const int cl_sum = block_sum_int<kCtlThreads>(cl, cnt[0]);
-  const int inv_sum = block_sum_int<kCtlThreads>(inv, cnt[1]);
+  block_reduce_dd_int2<2, kCtlThreads>(acc, cl, inv, sh, cnt[0]);
+  const int cl_sum = cl, inv_sum = inv;
   if (t == 0) {
     const double g2 = acc[1].hi + acc[1].lo;
     ctl->energy = acc[0].hi + acc[0].lo;
@@ -1599,17 +1635,17 @@ DEV void b_control_a(const DevMesh& d, int bid) {
   __syncthreads();
   if (flag || K == 0) return;
   // Blocked Cholesky of the padded 48 x 48 system by the whole workgroup, in
-  // panels of four columns (two barriers per panel), with y appended as row
+  // panels of six columns (two barriers per panel), with y appended as row
   // 48: the factor of [C y; y^T *] has (L^{-1} y)^T in that row, so the
   // forward substitution comes with the factorization.  Phase A: every thread
-  // factors the 4x4 diagonal block (redundantly, from LDS; pivots by one
+  // factors the 6x6 diagonal block (redundantly, from LDS; pivots by one
   // reciprocal square root), thread 0 stores it and thread t below it
-  // solves its row of the panel, L[t][jb..jb+3], into LDS.  Phase B: thread
+  // solves its row of the panel, L[t][jb..jb+5], into LDS.  Phase B: thread
   // t owns the lower-triangle entries e = t + 256 q (kept in registers) and
-  // subtracts the panel's rank-4 product from those right of the panel; the
+  // subtracts the panel's rank-6 product from those right of the panel; the
   // entries of the next panel go to LDS.  A non-positive pivot marks the
   // system as failed (z = 0 below).
-  constexpr int NB = 4;
+  constexpr int NB = 6;
   constexpr int kOwn = (49 * 50 / 2 - 1 + kCtlThreads - 1) / kCtlThreads;
   __shared__ double invp[48];
   __shared__ int nbad;
