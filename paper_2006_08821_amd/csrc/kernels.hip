@@ -750,8 +750,19 @@ __global__ void __launch_bounds__(kBlock) k_scatter_F(DevMesh d) {
 // Four lanes per vertex take interleaved entries of its incidence list and are
 // added in a fixed order.
 constexpr int kRhsLanes = 4;
+// Workgroups are dispatched to the 8 XCDs in turn (workgroup b to XCD b % 8),
+// and each XCD has its own L2.  Passes whose neighbouring workgroups share
+// data (elements sharing vertices, vertices sharing elements) renumber the
+// workgroups so that each XCD gets a contiguous range: XCD x takes logical
+// blocks [x q + min(x, r), ...) for nb = 8 q + r.  A bijection on [0, nb).
+DEV int xcd_block(int bid, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = bid & 7;
+  return x * q + min(x, r) + (bid >> 3);
+}
+
 DEV void b_rhs(const DevMesh& d, int bid, int add_pin, int check_done) {
-  const int f = bid * (kBlock / kRhsLanes) + (int)threadIdx.x / kRhsLanes;
+  const int lb = xcd_block(bid, (d.nf * kRhsLanes + kBlock - 1) / kBlock);
+  const int f = lb * (kBlock / kRhsLanes) + (int)threadIdx.x / kRhsLanes;
   if (check_done && stopped(d, f < d.nf ? d.inc_ptr[f] : 0)) return;
   const int sub = threadIdx.x % kRhsLanes;
   double acc[3] = {0, 0, 0};
@@ -1018,7 +1029,7 @@ template <typename T>
 DEV void b_element(const DevMesh& d, int bid) {
   Ctl* ctl = d.ctl;
   {
-    const int i0 = bid * kBlock + threadIdx.x;
+    const int i0 = xcd_block(bid, d.nb) * kBlock + threadIdx.x;
     if (stopped(d, i0 < d.m ? d.vol[i0] : 0.0)) return;
   }
   __shared__ DD sh[2 * kBlock];
@@ -1027,7 +1038,7 @@ DEV void b_element(const DevMesh& d, int bid) {
   DD acc[2] = {DD{0, 0}, DD{0, 0}};
   int ninv = 0;
   const int m = d.m;
-  for (int i = bid * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
+  for (int i = xcd_block(bid, d.nb) * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
     Elem e;
     load_elem(d, i, e);
     double R[9], S[9];
@@ -1130,13 +1141,13 @@ DEV void b_element(const DevMesh& d, int bid) {
 template <typename T>
 DEV void b_element_hess(const DevMesh& d, int bid) {
   {
-    const int i0 = bid * kBlock + threadIdx.x;
+    const int i0 = xcd_block(bid, d.nb) * kBlock + threadIdx.x;
     if (stopped(d, i0 < d.m ? d.vol[i0] : 0.0)) return;
   }
   __shared__ int shc[kBlock];
   int nclamp = 0;
   const int m = d.m;
-  for (int i = bid * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
+  for (int i = xcd_block(bid, d.nb) * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
     double S[9];
     load_S(d, i, S);
     const double vol = d.vol[i], mu = d.mu[i], lhat = d.lhat[i];
@@ -1361,7 +1372,7 @@ DEV void b_gram(const DevMesh& d, int bid) {
       wave * kGramBatch;
   const int m = d.m;
   const int per = (m + d.nbg - 1) / d.nbg;
-  const int e0 = bid * per, e1 = min(m, e0 + per);
+  const int e0 = xcd_block(bid, d.nbg) * per, e1 = min(m, e0 + per);
   const int perw = (per + 3) / 4;
   const int w0 = min(e1, e0 + wave * perw), w1 = min(e1, w0 + perw);
   const int k1 = d.k1;
@@ -1777,7 +1788,7 @@ __global__ void __launch_bounds__(kBlock) k_uz(DevMesh d) { b_uz(d, blockIdx.x);
 template <typename T>
 DEV void b_direction(const DevMesh& d, int bid) {
   {
-    const int i0 = bid * kBlock + threadIdx.x;
+    const int i0 = xcd_block(bid, d.nb) * kBlock + threadIdx.x;
     if (stopped(d, i0 < d.m ? d.w[i0] : 0.0)) return;
   }
   __shared__ DD sh[kBlock];
@@ -1785,7 +1796,7 @@ DEV void b_direction(const DevMesh& d, int bid) {
   const int m = d.m;
   const T* Lf = (const T*)d.Lf;
   const T* gbar = (const T*)d.gbar;
-  for (int i = bid * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
+  for (int i = xcd_block(bid, d.nb) * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
     Elem e;
     load_elem(d, i, e);
     double R[9], Az[9], RA[9];
@@ -1842,7 +1853,7 @@ __global__ void __launch_bounds__(kBlock) k_direction(DevMesh d) { b_direction<T
 // per element along F(sigma) = R (S + sigma D), A(sigma) = A + sigma dA.
 DEV void b_lscoef(const DevMesh& d, int bid) {
   {
-    const int i0 = bid * kBlock + threadIdx.x;
+    const int i0 = xcd_block(bid, d.nb) * kBlock + threadIdx.x;
     if (stopped(d, i0 < d.m ? d.vol[i0] : 0.0)) return;
   }
   __shared__ DD sh[6 * kBlock];
@@ -1850,7 +1861,7 @@ DEV void b_lscoef(const DevMesh& d, int bid) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) acc[k] = DD{0, 0};
   const int m = d.m;
-  for (int i = bid * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
+  for (int i = xcd_block(bid, d.nb) * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
     Elem e;
     load_elem(d, i, e);
     double R[9], S[9], py[9], D[9], A[9], dA[9], At[9], dAt[9];
