@@ -952,7 +952,11 @@ DEV void b_fwd(const DevMesh& d, int bid, int check_done) {
   if (it.first & kItemWide) fwd_item<32>(d, it, it.first & ~kItemWide, ft);
   else fwd_item<8>(d, it, it.first, ft);
 }
-__global__ void __launch_bounds__(kBlock) k_fwd(DevMesh d, int it0, int check_done) { b_fwd(d, it0 + (int)blockIdx.x, check_done); }
+// consecutive items of a level mostly belong to one supernode and read the
+// same input vector: keep them on one XCD
+__global__ void __launch_bounds__(kBlock) k_fwd(DevMesh d, int it0, int check_done) {
+  b_fwd(d, it0 + xcd_block((int)blockIdx.x, (int)gridDim.x), check_done);
+}
 
 // Backward sweep of one level with the transposed blocks.  Work item (s, c0):
 // columns [c0, c0 + 256/LPR) of supernode s.  With z = [y_s; -x[rows]],
@@ -1001,7 +1005,9 @@ DEV void b_bwd(const DevMesh& d, int bid, double* x, int check_done) {
   if (it.first & kItemWide) bwd_item<32>(d, it, it.first & ~kItemWide, x, z);
   else bwd_item<8>(d, it, it.first, x, z);
 }
-__global__ void __launch_bounds__(kBlock) k_bwd(DevMesh d, int it0, double* x, int check_done) { b_bwd(d, it0 + (int)blockIdx.x, x, check_done); }
+__global__ void __launch_bounds__(kBlock) k_bwd(DevMesh d, int it0, double* x, int check_done) {
+  b_bwd(d, it0 + xcd_block((int)blockIdx.x, (int)gridDim.x), x, check_done);
+}
 
 // q = solution at free vertices, pin targets at pinned vertices
 __global__ void __launch_bounds__(kBlock) k_set_pins(DevMesh d) {
