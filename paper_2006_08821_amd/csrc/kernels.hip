@@ -1522,15 +1522,20 @@ DEV void b_gram_reduce(const DevMesh& d, int bid) {
   const int t = threadIdx.x, part = t >> 4, el = t & 15;
   const int e = bid * 16 + el;
   if (stopped(d, e < kGramEntries && part < d.nbg ? d.part_gram[(int64_t)part * kGramEntries + e] : 0.0)) return;
+  // partials part, part + 16, ... (nbg <= 512: at most 32 per thread), all
+  // requested before the first addition; even ones into s0, odd ones into s1
+  constexpr int kPer = 512 / 16;
+  double v[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int b = part + 16 * k;
+    v[k] = e < kGramEntries && b < d.nbg ? d.part_gram[(int64_t)b * kGramEntries + e] : 0.0;
+  }
   double s0 = 0, s1 = 0;
-  if (e < kGramEntries) {
-    int b = part;
-#pragma unroll 4
-    for (; b + 16 < d.nbg; b += 32) {
-      s0 += d.part_gram[(int64_t)b * kGramEntries + e];
-      s1 += d.part_gram[(int64_t)(b + 16) * kGramEntries + e];
-    }
-    if (b < d.nbg) s0 += d.part_gram[(int64_t)b * kGramEntries + e];
+#pragma unroll
+  for (int k = 0; k < kPer; k += 2) {
+    s0 += v[k];
+    s1 += v[k + 1];
   }
   sh[part][el] = s0 + s1;
   __syncthreads();
