@@ -768,6 +768,9 @@ DEV void b_rhs(const DevMesh& d, int bid, int add_pin, int check_done) {
   double acc[3] = {0, 0, 0};
   if (f < d.nf) {
     const int k0 = d.inc_ptr[f], k1 = d.inc_ptr[f + 1];
+    // unrolled so that several incidence codes, then their contributions,
+    // are in flight together (two dependent loads per entry)
+#pragma unroll 4
     for (int k = k0 + sub; k < k1; k += kRhsLanes) {
       const int code = d.inc[k];
       const double* src = d.contrib + (int64_t)12 * (code >> 2) + 3 * (code & 3);
