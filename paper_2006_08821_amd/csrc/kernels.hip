@@ -495,6 +495,70 @@ DEV void clamp_psd_jacobi(T (&A)[N][N]) {
     }
 }
 
+// The same projection for the rare indefinite 6x6 block, in place on a full
+// symmetric matrix W in LDS with the eigenvectors in V (LDS), rolled loops:
+// no scratch memory and few registers, so that it does not set the register
+// allocation of the Hessian pass.
+template <typename T, int N>
+DEV void clamp_psd_jacobi_lds(T (*W)[N], T (*V)[N]) {
+#pragma unroll 1
+  for (int i = 0; i < N; ++i)
+#pragma unroll 1
+    for (int j = 0; j < N; ++j) V[i][j] = i == j ? T(1) : T(0);
+#pragma unroll 1
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    T off = 0, dia = 0;
+#pragma unroll 1
+    for (int i = 0; i < N; ++i) {
+      dia += W[i][i] * W[i][i];
+#pragma unroll 1
+      for (int j = i + 1; j < N; ++j) off += W[i][j] * W[i][j];
+    }
+    if (!(off > T(1e-32) * dia)) break;
+#pragma unroll 1
+    for (int pp = 0; pp < N; ++pp)
+#pragma unroll 1
+      for (int qq = pp + 1; qq < N; ++qq) {
+        const T apq = W[pp][qq];
+        if (apq != T(0)) {
+          const T dqp = W[qq][qq] - W[pp][pp];
+          const T t = (dqp >= T(0) ? T(2) : T(-2)) * apq / (fabs(dqp) + sqrt(dqp * dqp + T(4) * apq * apq));
+          const T c = rsq(t * t + T(1)), s = t * c;
+#pragma unroll 1
+          for (int k = 0; k < N; ++k) {
+            const T akp = W[k][pp], akq = W[k][qq];
+            W[k][pp] = c * akp - s * akq;
+            W[k][qq] = s * akp + c * akq;
+          }
+#pragma unroll 1
+          for (int k = 0; k < N; ++k) {
+            const T apk = W[pp][k], aqk = W[qq][k];
+            W[pp][k] = c * apk - s * aqk;
+            W[qq][k] = s * apk + c * aqk;
+          }
+#pragma unroll 1
+          for (int k = 0; k < N; ++k) {
+            const T vkp = V[k][pp], vkq = V[k][qq];
+            V[k][pp] = c * vkp - s * vkq;
+            V[k][qq] = s * vkp + c * vkq;
+          }
+        }
+      }
+  }
+  T lam[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) lam[k] = W[k][k] > T(0) ? W[k][k] : T(0);
+#pragma unroll 1
+  for (int i = 0; i < N; ++i)
+#pragma unroll 1
+    for (int j = 0; j < N; ++j) {
+      T sm = 0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) sm += V[i][k] * lam[k] * V[j][k];
+      W[i][j] = sm;
+    }
+}
+
 DEV double acs(double x) { return acos(x); }
 DEV float acs(float x) { return acosf(x); }
 DEV double cs(double x) { return cos(x); }
@@ -589,17 +653,9 @@ DEV bool clamp_psd3_closed(T (&A)[3][3]) {
 // Make A positive semi-definite (eigenvalues < 0 -> 0) unless a Cholesky
 // factorization already succeeds; then add beta I and factor.  Returns 1 if
 // the clamp changed A.  3x3 blocks take the closed form where it is accurate.
+// L = chol(A + beta I) for a positive semi-definite A (A is modified).
 template <typename T, int N>
-DEV int clamp_add_factor(T (&A)[N][N], T beta, T* L) {
-  int clamped = 0;
-  if (!chol_packed<T, N>(A, L)) {
-    if constexpr (N == 3) {
-      if (!clamp_psd3_closed<T>(A)) clamp_psd_jacobi<T, 3>(A);
-    } else {
-      clamp_psd_jacobi<T, N>(A);
-    }
-    clamped = 1;
-  }
+DEV void add_factor(T (&A)[N][N], T beta, T* L) {
 #pragma unroll
   for (int k = 0; k < N; ++k) A[k][k] += beta;
   if (!chol_packed<T, N>(A, L)) {
@@ -611,6 +667,20 @@ DEV int clamp_add_factor(T (&A)[N][N], T beta, T* L) {
     for (int k = 0; k < N; ++k) A[k][k] += T(1e-12) * sc + T(1e-300);
     chol_packed<T, N>(A, L);
   }
+}
+
+template <typename T, int N>
+DEV int clamp_add_factor(T (&A)[N][N], T beta, T* L) {
+  int clamped = 0;
+  if (!chol_packed<T, N>(A, L)) {
+    if constexpr (N == 3) {
+      if (!clamp_psd3_closed<T>(A)) clamp_psd_jacobi<T, 3>(A);
+    } else {
+      clamp_psd_jacobi<T, N>(A);
+    }
+    clamped = 1;
+  }
+  add_factor<T, N>(A, beta, L);
   return clamped;
 }
 
@@ -1148,67 +1218,124 @@ DEV void b_element(const DevMesh& d, int bid) {
 // clamped blocks + beta I in the rotated basis (precision T), their Cholesky
 // factors, and gbar = H^{-1} g (g read from gbar, overwritten in place).
 template <typename T>
+DEV void hess_blocks(const DevMesh& d, int i, T (&Hs)[6][6], T (&Hk)[3][3]) {
+  const int m = d.m;
+  double S[9];
+  load_S(d, i, S);
+  const double vol = d.vol[i], mu = d.mu[i], lhat = d.lhat[i];
+  double u[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) u[c] = d.fib[c * m + i];
+  const int g = d.grp[i];
+  const double afk = (g >= 0 ? d.act[g] : 0.0) * d.kf;
+  const double J = det3(S);
+  double C[9];
+  cof3<double>(S, C);
+  const double kap = lhat * (J - 1.0) - mu;
+  // Hessian blocks in the rotated basis (precision T)
+  T St[9], ut[3];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) St[k] = (T)S[k];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) ut[k] = (T)u[k];
+  const T muT = (T)mu, kapT = (T)kap, phiT = (T)(2.0 * afk), volT = (T)vol, lhT = (T)lhat;
+  T cy[9];
+  to_y<T, double>(C, cy);
+#pragma unroll
+  for (int y = 0; y < 6; ++y)
+#pragma unroll
+    for (int z = 0; z < 6; ++z)
+      Hs[y][z] = volT * (hproj<T>(y, z, St, muT, kapT, phiT, ut) + lhT * cy[y] * cy[z]);
+#pragma unroll
+  for (int y = 0; y < 3; ++y)
+#pragma unroll
+    for (int z = 0; z < 3; ++z) Hk[y][z] = volT * hproj<T>(6 + y, 6 + z, St, muT, kapT, phiT, ut);
+}
+
+// Both blocks are clamped to their positive semi-definite part, beta I is
+// added and the results factored; gbar = H^{-1} g in place.  The elements of
+// a workgroup are taken in rounds of kBlock; a 6x6 block that is not positive
+// definite (rare) is parked, lower triangle, in its factor's place and
+// finished by thread 0 after the round with an LDS-resident Jacobi, so that
+// the eigen-decomposition holds no registers in the main loop.
+template <typename T>
 DEV void b_element_hess(const DevMesh& d, int bid) {
+  const int lb = xcd_block(bid, d.nb);
   {
-    const int i0 = xcd_block(bid, d.nb) * kBlock + threadIdx.x;
+    const int i0 = lb * kBlock + threadIdx.x;
     if (stopped(d, i0 < d.m ? d.vol[i0] : 0.0)) return;
   }
   __shared__ int shc[kBlock];
+  __shared__ int fix[kBlock];
+  __shared__ int nfix;
+  __shared__ T fixW[6][6], fixV[6][6];
   int nclamp = 0;
   const int m = d.m;
-  for (int i = xcd_block(bid, d.nb) * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
-    double S[9];
-    load_S(d, i, S);
-    const double vol = d.vol[i], mu = d.mu[i], lhat = d.lhat[i];
-    const double beta = d.alpha * d.w[i];
-    double u[3];
+  T* gbar = (T*)d.gbar;
+  T* Lf = (T*)d.Lf;
+  for (int base = lb * kBlock; base < m; base += d.nb * kBlock) {
+    if (threadIdx.x == 0) nfix = 0;
+    __syncthreads();
+    const int i = base + threadIdx.x;
+    if (i < m) {
+      T Hs[6][6], Hk[3][3];
+      hess_blocks<T>(d, i, Hs, Hk);
+      const T beta = (T)(d.alpha * d.w[i]);
+      {
+        T Ls[21];
+        if (chol_packed<T, 6>(Hs, Ls)) {
+          add_factor<T, 6>(Hs, beta, Ls);
+          T gs[6];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) u[c] = d.fib[c * m + i];
-    const int g = d.grp[i];
-    const double afk = (g >= 0 ? d.act[g] : 0.0) * d.kf;
-    const double J = det3(S);
-    double C[9];
-    cof3<double>(S, C);
-    const double kap = lhat * (J - 1.0) - mu;
-    // Hessian blocks in the rotated basis (precision T)
-    T St[9], ut[3];
+          for (int k = 0; k < 6; ++k) gs[k] = gbar[k * m + i];
+          chol_solve<T, 6>(Ls, gs);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) St[k] = (T)S[k];
+          for (int k = 0; k < 6; ++k) gbar[k * m + i] = gs[k];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) ut[k] = (T)u[k];
-    const T muT = (T)mu, kapT = (T)kap, phiT = (T)(2.0 * afk), volT = (T)vol, lhT = (T)lhat;
-    T cy[9];
-    to_y<T, double>(C, cy);
-    T Hs[6][6], Hk[3][3];
+          for (int k = 0; k < 21; ++k) Lf[k * m + i] = Ls[k];
+        } else {
 #pragma unroll
-    for (int y = 0; y < 6; ++y)
+          for (int r = 0; r < 6; ++r)
 #pragma unroll
-      for (int z = 0; z < 6; ++z)
-        Hs[y][z] = volT * (hproj<T>(y, z, St, muT, kapT, phiT, ut) + lhT * cy[y] * cy[z]);
+            for (int c = 0; c <= r; ++c) Lf[(r * (r + 1) / 2 + c) * m + i] = Hs[r][c];
+          fix[atomicAdd(&nfix, 1)] = i;
+        }
+      }
+      T Lk[6];
+      nclamp += clamp_add_factor<T, 3>(Hk, beta, Lk);
+      T gk[3];
 #pragma unroll
-    for (int y = 0; y < 3; ++y)
+      for (int k = 0; k < 3; ++k) gk[k] = gbar[(6 + k) * m + i];
+      chol_solve<T, 3>(Lk, gk);
 #pragma unroll
-      for (int z = 0; z < 3; ++z) Hk[y][z] = volT * hproj<T>(6 + y, 6 + z, St, muT, kapT, phiT, ut);
-    T Ls[21], Lk[6];
-    nclamp += clamp_add_factor<T, 6>(Hs, (T)beta, Ls);
-    nclamp += clamp_add_factor<T, 3>(Hk, (T)beta, Lk);
-    T* gbar = (T*)d.gbar;
-    T gs[6], gk[3];
+      for (int k = 0; k < 3; ++k) gbar[(6 + k) * m + i] = gk[k];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) gs[k] = gbar[k * m + i];
+      for (int k = 0; k < 6; ++k) Lf[(21 + k) * m + i] = Lk[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int q = 0; q < nfix; ++q) {
+        const int j = fix[q];
+#pragma unroll 1
+        for (int r = 0; r < 6; ++r)
+#pragma unroll 1
+          for (int c = 0; c <= r; ++c) fixW[r][c] = fixW[c][r] = Lf[(r * (r + 1) / 2 + c) * m + j];
+        clamp_psd_jacobi_lds<T, 6>(fixW, fixV);
+        T Ls[21];
+        add_factor<T, 6>(fixW, (T)(d.alpha * d.w[j]), Ls);
+        T gs[6];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) gk[k] = gbar[(6 + k) * m + i];
-    chol_solve<T, 6>(Ls, gs);
-    chol_solve<T, 3>(Lk, gk);
-    T* Lf = (T*)d.Lf;
+        for (int k = 0; k < 6; ++k) gs[k] = gbar[k * m + j];
+        chol_solve<T, 6>(Ls, gs);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) gbar[k * m + i] = gs[k];
+        for (int k = 0; k < 6; ++k) gbar[k * m + j] = gs[k];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) gbar[(6 + k) * m + i] = gk[k];
-#pragma unroll
-    for (int k = 0; k < 21; ++k) Lf[k * m + i] = Ls[k];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) Lf[(21 + k) * m + i] = Lk[k];
+        for (int k = 0; k < 21; ++k) Lf[k * m + j] = Ls[k];
+        ++nclamp;
+      }
+    }
+    // nfix and fix are reused by the next round
+    __syncthreads();
   }
   const int nclamp_sum = block_sum_int(nclamp, shc);
   if (threadIdx.x == 0) d.part_cnt[2 * bid] = nclamp_sum;
