@@ -819,7 +819,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter_F(DevMesh d) {
 // at each free vertex, plus (optionally) the constant pinned term -L_fp qbar_p
 // Four lanes per vertex take interleaved entries of its incidence list and are
 // added in a fixed order.
-constexpr int kRhsLanes = 4;
+constexpr int kRhsLanes = 8;
 // Workgroups are dispatched to the 8 XCDs in turn (workgroup b to XCD b % 8),
 // and each XCD has its own L2.  Passes whose neighbouring workgroups share
 // data (elements sharing vertices, vertices sharing elements) renumber the
@@ -849,10 +849,9 @@ DEV void b_rhs(const DevMesh& d, int bid, int add_pin, int check_done) {
     }
   }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    acc[c] += __shfl_xor(acc[c], 1);
-    acc[c] += __shfl_xor(acc[c], 2);
-  }
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int off = 1; off < kRhsLanes; off <<= 1) acc[c] += __shfl_xor(acc[c], off);
   if (f >= d.nf || sub != 0) return;
   if (add_pin)
 #pragma unroll
