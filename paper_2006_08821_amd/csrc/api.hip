@@ -232,12 +232,9 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
         if (fac.level[s] == L) {
           const bool wide = fac.parent[s] < 0 && fac.w[s] >= 256;
           const int step = wide ? 8 : 32;
-          if (wide) {
-            // rows further down need more of the frontal vector: heaviest first
-            for (int r = (fac.h[s] - 1) / step * step; r >= 0; r -= step) fwd.push_back(item(s, r | emu::kItemWideBit));
-          } else {
-            for (int r = 0; r < fac.h[s]; r += step) fwd.push_back(item(s, r));
-          }
+          // rows further down need more of the frontal vector: heaviest first
+          for (int r = (fac.h[s] - 1) / step * step; r >= 0; r -= step)
+            fwd.push_back(item(s, r | (wide ? emu::kItemWideBit : 0)));
         }
       pl.fwd_ptr[L + 1] = (int)fwd.size();
     }
