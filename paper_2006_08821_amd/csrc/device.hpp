@@ -16,7 +16,7 @@ constexpr int kLsTerms = 7;        // 6 polynomial coefficients + g.p
 // with fewer than kWideLevelItems 32-row items use the wide form for
 // supernodes whose rows are at least kWideRowMin long.
 constexpr int kItemWideBit = 1 << 30;
-constexpr int kWideLevelItems = 1024;
+constexpr int kWideLevelItems = 512;
 constexpr int kWideRowMin = 64;
 constexpr int kMaxFrontW = 2048;   // largest supernode width held in LDS
 
