@@ -869,7 +869,7 @@ __global__ void __launch_bounds__(kBlock) k_rhs(DevMesh d, int add_pin, int chec
 // workgroup) so that the few supernodes near the root still spread over many
 // compute units; the rest use LPR = 8 (32 rows).  The vector the rows multiply
 // lives in LDS, loaded in chunks of kVecChunk.
-constexpr int kVecChunk = 2048;
+constexpr int kVecChunk = 1536;  // 36 KB of LDS: four workgroups per CU, and the merged root (<= 1536 wide) in one chunk
 
 template <bool kFwd, int LPR>
 DEV void row_products(const double* __restrict__ V, int64_t base, int w, int h, int r0, int nrows,
