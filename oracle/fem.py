@@ -84,8 +84,12 @@ def prox(M, A, a_el, tol=1e-13, max_iters=100, nu=None):
         if np.all(gn <= tol * scale):
             break
         H = vol[:, None, None] * mat.hess(X, M.mu, M.lhat, a_el, M.kf, M.fiber) + beta[:, None, None] * np.eye(9)
-        H = mat.clamp_psd(H) + 1e-300
-        step = -np.linalg.solve(H, g.reshape(-1, 9, 1)).reshape(-1, 3, 3)
+        # damped Newton on a (possibly non-convex) element objective: the PSD
+        # part of the Hessian, floored at a tiny multiple of beta so that the
+        # step is always defined (the objective is beta-strongly convex far out)
+        w, V = np.linalg.eigh(H)
+        w = np.maximum(w, 1e-9 * beta[:, None])
+        step = -np.einsum("iab,ib,icb,ic->ia", V, 1.0 / w, V, g.reshape(-1, 9)).reshape(-1, 3, 3)
         f0 = obj(X)
         t = np.ones(M.m)
         for _ls in range(30):
@@ -136,9 +140,22 @@ def moreau_solve(M, a, q0=None, tol=1e-10, max_iters=200, history=False):
         Hinv = np.linalg.inv(H)
         b2 = M.beta[:, None, None]
         He = b2 * np.eye(9) - b2 ** 2 * Hinv
-        He = mat.clamp_psd(0.5 * (He + np.transpose(He, (0, 2, 1))))
-        K, _ = _assemble(M, He)
-        step = -spla.spsolve(K, grad)
+        He = 0.5 * (He + np.transpose(He, (0, 2, 1)))
+        # Newton step with the exact assembled Hessian of Ehat (each element's
+        # envelope Hessian is indefinite where Psi is, the sum is not near a
+        # minimizer); where that step is not a descent direction, the step of
+        # the per-element PSD parts instead
+        step = None
+        try:
+            K, _ = _assemble(M, He)
+            step = -spla.spsolve(K, grad)
+            if not (np.all(np.isfinite(step)) and float(grad @ step) < 0.0):
+                step = None
+        except RuntimeError:
+            step = None
+        if step is None:
+            K, _ = _assemble(M, mat.clamp_psd(He))
+            step = -spla.spsolve(K, grad)
         t = 1.0
         gs = float(grad @ step)
         for _ls in range(60):

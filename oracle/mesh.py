@@ -3,9 +3,13 @@
 * Deformation gradient of a linear tet (eq. defograd): F = D_s D_m^{-1}, so the
   compatible gradient is A_i(q) = sum_v q_v b_{i,v}^T with b_{i,1..3} the rows of
   D_m^{-1} and b_{i,4} = -(b_{i,1}+b_{i,2}+b_{i,3}).
-* ACAP energy (eq. ACAPEnergy), weighted per element (Sec. 3.3 recommends
-  stiffness-proportional weights):  1/2 sum_i w_i |A_i(q) - F_i|^2,
-  w_i = vol_i mu_i / mu_ref.  Its q-Hessian is L_w (x) I_3 with the scalar
+* ACAP energy (eq. ACAPEnergy), weighted per element:
+  1/2 sum_i w_i |A_i(q) - F_i|^2 with, by ``weight_mode``,
+  0: w_i = vol_i mu_i / mu_ref (stiffness-proportional for every tet),
+  1: w_i = vol_i (the printed unweighted energy as an integral),
+  2: stiffness-proportional for muscle and tendon but w_i = vol_i for bone
+     tets (the exception Sec. 3.3 states: a stiff spring on bones can lock).
+  Its q-Hessian is L_w (x) I_3 with the scalar
   weighted Laplacian L_w = sum_i w_i sum_{v,v'} (b_{i,v}.b_{i,v'}) e_v e_v'^T.
 * Nearest continuous mesh (eq. acap): q* solves L_ff q_f = r_f - L_fp qbar_p per
   coordinate, r_c[v] = sum_{i ∋ v} w_i b_{i,v} . F_i[c,:]; pins remove the
@@ -37,6 +41,7 @@ class Mesh:
     lhat: np.ndarray
     fiber: np.ndarray       # [m,3] unit
     group: np.ndarray       # [m]
+    bone: np.ndarray        # [m] bone id, -1 = not bone
     w: np.ndarray           # ACAP weights
     beta: np.ndarray        # alpha * w
     alpha: float
@@ -101,16 +106,20 @@ def build(problem, alpha_hat=None, n_modes=None, weight_mode=0, modes=True, fact
     mu_ref = float(mu[musc].min()) if musc.any() else float(mu.min())
     kf = mu_ref
     alpha = alpha_hat * mu_ref
+    m = tets.shape[0]
+    bone = (np.full(m, -1, np.int64) if getattr(problem, "bone", None) is None
+            else np.asarray(problem.bone, np.int64))
     if weight_mode == 0:
         w = vol * mu / mu_ref
     elif weight_mode == 1:
         w = vol.copy()
+    elif weight_mode == 2:
+        w = np.where(bone >= 0, vol, vol * mu / mu_ref)
     else:
         raise ValueError("weight_mode")
     beta = alpha * w
     fiber = problem.fiber / np.linalg.norm(problem.fiber, axis=1, keepdims=True)
     n = rest.shape[0]
-    m = tets.shape[0]
     # weighted Laplacian
     bb = np.einsum("ivd,iud->ivu", b, b) * w[:, None, None]
     rows = np.repeat(tets, 4, axis=1).reshape(-1)
@@ -126,7 +135,7 @@ def build(problem, alpha_hat=None, n_modes=None, weight_mode=0, modes=True, fact
     Lfp = L[free][:, pins].tocsr()
     lu = spla.splu(Lff, permc_spec="MMD_AT_PLUS_A") if factor else None
     M = Mesh(rest=rest, tets=tets, b=b, vol=vol, mu=mu, lhat=lhat, fiber=fiber,
-             group=group, w=w, beta=beta, alpha=alpha, mu_ref=mu_ref, kf=kf,
+             group=group, bone=bone, w=w, beta=beta, alpha=alpha, mu_ref=mu_ref, kf=kf,
              pins=pins, pin_xyz=np.asarray(problem.pin_xyz, np.float64),
              free=free, fpos=fpos, L=L, Lff=Lff, Lfp=Lfp, lu=lu)
     if n_modes < 0:                       # default: 48 modes, capped by the mesh

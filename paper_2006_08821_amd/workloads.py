@@ -52,6 +52,7 @@ class Problem:
     alpha_hat: float = 10.0
     n_modes: int = -1               # -1: library default (48, capped by the mesh)
     extra: dict = dataclasses.field(default_factory=dict)
+    bone: Optional[np.ndarray] = None  # [m] int32 bone id per tet, -1 = not bone (None: no bones)
 
     @property
     def n_vertices(self) -> int:
@@ -192,10 +193,11 @@ def limb(nx: int = 20, ny: int = 20, nz: int = 80, n_groups: int = 1, seed: int 
         raise ValueError("n_groups must be 1, 4 or 8")
     pins = _face_pins(xyz, 2, 0.0)
     act = np.zeros(n_groups) if activation is None else np.asarray(activation, np.float64)
+    bone = np.where(role == 2, 0, -1).astype(np.int32)
     return Problem(name=name, rest_xyz=xyz, tets=tets, youngs=youngs,
                    poisson=np.full(tets.shape[0], NU), fiber=fiber, group=group,
                    pins=pins, pin_xyz=xyz[pins].copy(), activation=act,
-                   dims=(nx, ny, nz), extra={"role": role})
+                   dims=(nx, ny, nz), extra={"role": role}, bone=bone)
 
 
 def heterogeneous_limb_ramp(steps: int = 20, nx=20, ny=20, nz=80) -> tuple:
@@ -235,8 +237,9 @@ def hinge_limb(nx: int = 40, ny: int = 40, nz: int = 160, frames: int = 60, seed
     pins = np.unique(np.concatenate([_face_pins(xyz2, 2, 0.0), hinge_ids])).astype(np.int32)
     rng = np.random.default_rng(seed)
     acts = [rng.uniform(0.0, 1.0, size=4) for _ in range(frames)]
+    bone = np.where(role == 2, np.where(upper_bone, 1, 0), -1).astype(np.int32)
     q = dataclasses.replace(p, rest_xyz=xyz2, tets=tets, pins=pins,
-                            pin_xyz=xyz2[pins].copy(), activation=acts[0].copy())
+                            pin_xyz=xyz2[pins].copy(), activation=acts[0].copy(), bone=bone)
     q.extra = dict(p.extra, hinge=hinge_ids, duplicated=dup_src)
     return q, acts
 
