@@ -54,7 +54,20 @@ typedef enum {
 } emu_status;
 
 enum { EMU_PRECISION_FP64 = 0, EMU_PRECISION_MIXED = 1 };
-enum { EMU_WEIGHT_STIFFNESS = 0, EMU_WEIGHT_VOLUME = 1 };
+/* ACAP weights w_i (eq. ACAPEnergy).  STIFFNESS: w_i = vol_i mu_i / mu_ref for
+   every tet.  VOLUME: w_i = vol_i (the printed unweighted energy read as an
+   integral).  PAPER: stiffness-proportional for muscle and tendon, volume for
+   bone tets (Sec. 3.3: a stiff spring on bones can lead to locking); bone tets
+   are those with bone[i] >= 0. */
+enum { EMU_WEIGHT_STIFFNESS = 0, EMU_WEIGHT_VOLUME = 1, EMU_WEIGHT_PAPER = 2 };
+
+/* Optional device allocator for the memory a mesh keeps resident (state,
+   factor, modes, work arrays).  alloc returns NULL on failure (-> EMU_E_OOM);
+   free receives exactly the pointers alloc returned, after the mesh's stream
+   has drained.  Used to draw mesh memory from a caller's pool (e.g. torch's
+   caching allocator). */
+typedef void* (*emu_dev_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*emu_dev_free_fn)(void* ptr, void* ctx);
 
 /* Mesh description (host arrays, copied by emu_create_mesh). */
 typedef struct {
@@ -78,13 +91,17 @@ typedef struct {
                                 tets with group >= 0 (all tets if none)          */
   double fiber_k;            /* fiber stress scale k_f in Psi_fib = a k_f |F u|^2;
                                 0 -> mu_ref                                      */
-  int32_t weight_mode;       /* EMU_WEIGHT_STIFFNESS: w_i = vol_i mu_i / mu_ref;
-                                EMU_WEIGHT_VOLUME: w_i = vol_i                   */
+  int32_t weight_mode;       /* EMU_WEIGHT_STIFFNESS, _VOLUME or _PAPER (above)   */
   int32_t n_modes;           /* k = 3 * (scalar modes), 0 <= k <= 48, k % 3 == 0,
                                 k/3 < free vertices; -1 -> min(48, 3 (free - 1))
                                 (eq. low-rank)                                    */
   int32_t precision;         /* EMU_PRECISION_FP64 or EMU_PRECISION_MIXED          */
   int32_t leaf_size;         /* nested-dissection leaf size; 0 -> 64              */
+  const int32_t *bone;       /* [m] bone id (>= 0) or -1; NULL = no bone tets.
+                                Read by weight_mode EMU_WEIGHT_PAPER             */
+  emu_dev_alloc_fn dev_alloc;  /* NULL -> hipMalloc / hipFree.  Both or neither;  */
+  emu_dev_free_fn dev_free;    /* the serving loop ignores them (it accounts its  */
+  void *alloc_ctx;             /* own HBM budget).  Passed back to both calls.    */
 } emu_mesh_desc;
 
 /* Solve options.  Defaults (emu_solve_opts_default): grad_tol 1e-8,
@@ -99,6 +116,10 @@ typedef struct {
   double stall_rel;          /* mixed precision only: also stop if no Armijo step
                                 exists and |g| <= stall_rel * |g_0|; 0 disables  */
   double grad_rtol;          /* also stop when |dE/dF|_2 <= grad_rtol |g_0|; 0 = off */
+  int32_t phase_timing;      /* 1: time the phases of every iteration with HIP
+                                events (fills the ms_* phase fields of the stats;
+                                the iterations are launched one by one instead
+                                of from a replayed graph); 0: phases report 0 */
 } emu_solve_opts;
 
 typedef struct {
@@ -113,6 +134,12 @@ typedef struct {
   double grad_norm;          /* |dE/dF|_2 at the end                              */
   double grad_norm0;         /* |dE/dF|_2 at the start                            */
   double ms_total;           /* device time of the call (hipEvent)                */
+  /* device time per phase, summed over the iterations (opts.phase_timing):
+     element pass (energy, gradient, blocks; Sec. 3.2.1), Woodbury correction
+     (eq. Hessian-woodbury: Gram, k x k solve, direction), ACAP solve of the
+     direction (eq. acap: right-hand side and triangular sweeps), line search
+     (Algorithm 1: polynomial coefficients, Armijo test, q update) */
+  double ms_elem, ms_woodbury, ms_solve, ms_linesearch;
 } emu_solve_stats;
 
 /* Static information about a mesh. */

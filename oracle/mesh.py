@@ -90,12 +90,14 @@ def hat_gradients(rest, tets):
     return b, vol
 
 
-def build(problem, alpha_hat=None, n_modes=None, weight_mode=0, modes=True, factor=True):
+def build(problem, alpha_hat=None, n_modes=None, weight_mode=None, modes=True, factor=True):
     """Set up the oracle mesh for a ``workloads.Problem``.  ``factor=False``
     skips the sparse factorization (and the modes): the element formulas,
     ``L``, ``scatter_GtWF`` and ``gather_A`` still work, which is what checks
     at sizes the factorization would take too long for need."""
     alpha_hat = problem.alpha_hat if alpha_hat is None else alpha_hat
+    if weight_mode is None:
+        weight_mode = getattr(problem, "weight_mode", 0)
     n_modes = problem.n_modes if n_modes is None else n_modes
     rest = np.asarray(problem.rest_xyz, np.float64)
     tets = orient(rest, problem.tets)

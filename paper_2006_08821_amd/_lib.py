@@ -20,6 +20,9 @@ STATUS_NAMES = {0: "EMU_OK", 1: "EMU_E_INVALID", 2: "EMU_E_SINGULAR", 3: "EMU_E_
 P = C.c_void_p
 I32P = C.POINTER(C.c_int32)
 DP = C.POINTER(C.c_double)
+# emu_dev_alloc_fn / emu_dev_free_fn
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 class MeshDesc(C.Structure):
@@ -28,20 +31,23 @@ class MeshDesc(C.Structure):
                 ("poisson", DP), ("fiber", DP), ("group", I32P), ("pins", I32P), ("pin_xyz", DP),
                 ("alpha_hat", C.c_double), ("mu_ref", C.c_double), ("fiber_k", C.c_double),
                 ("weight_mode", C.c_int32), ("n_modes", C.c_int32), ("precision", C.c_int32),
-                ("leaf_size", C.c_int32)]
+                ("leaf_size", C.c_int32), ("bone", I32P), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
+                ("alloc_ctx", P)]
 
 
 class SolveOpts(C.Structure):
     _fields_ = [("grad_tol", C.c_double), ("max_iters", C.c_int32), ("sigma0", C.c_double),
                 ("armijo_c", C.c_double), ("rho", C.c_double), ("warm_start", C.c_int32),
-                ("iters_per_sync", C.c_int32), ("stall_rel", C.c_double), ("grad_rtol", C.c_double)]
+                ("iters_per_sync", C.c_int32), ("stall_rel", C.c_double), ("grad_rtol", C.c_double),
+                ("phase_timing", C.c_int32)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("ls_trials", C.c_int32),
                 ("acap_solves", C.c_int32), ("inverted", C.c_int32), ("clamped", C.c_int32),
                 ("energy", C.c_double), ("grad_norm", C.c_double), ("grad_norm0", C.c_double),
-                ("ms_total", C.c_double)]
+                ("ms_total", C.c_double), ("ms_elem", C.c_double), ("ms_woodbury", C.c_double),
+                ("ms_solve", C.c_double), ("ms_linesearch", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -90,9 +90,6 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
   auto& d = im.d;
   const int32_t n = hm.n, m = hm.m, nf = hm.nf;
   const auto& fac = hm.fac;
-  for (int s = 0; s < fac.ns; ++s)
-    if (fac.w[s] > emu::kMaxFrontW)
-      throw emu::Error{EMU_E_INVALID, "separator wider than " + std::to_string(emu::kMaxFrontW) + " vertices"};
   d.n = n;
   d.nf = nf;
   d.m = m;
@@ -374,6 +371,7 @@ void release_user_stream(emu_mesh* M, void* stream) {
 
 void emu::fill_stats(const emu::Ctl& c, emu_solve_stats* s, float ms) {
   if (!s) return;
+  std::memset(s, 0, sizeof(*s));
   s->status = c.status;
   s->iters = c.iter;
   s->ls_trials = c.trials;
@@ -446,6 +444,7 @@ emu_solve_opts emu_solve_opts_default(void) {
   o.iters_per_sync = 16;
   o.stall_rel = 1e-6;
   o.grad_rtol = 0.0;
+  o.phase_timing = 0;
   return o;
 }
 
@@ -461,6 +460,9 @@ emu_status emu_create_mesh(const emu_mesh_desc* desc, emu_mesh** out) {
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
       throw emu::Error{EMU_E_HIP, "no HIP device available"};
     M = new emu_mesh(std::make_shared<emu::HostMesh>());
+    M->dev_alloc = desc->dev_alloc;
+    M->dev_free = desc->dev_free;
+    M->alloc_ctx = desc->alloc_ctx;
     auto t0 = std::chrono::steady_clock::now();
     emu::host_setup(*desc, M->hm, true);
     emu::upload_image(M, emu::prepare_image(M->hm), nullptr);
@@ -656,12 +658,33 @@ emu_status emu_solve(emu_mesh* M, const emu_solve_opts* opts, double* q_out, emu
     if (!o.warm_start) emu::launch_init_rest(M->d, M->st);
     init_ctl(M, o, 0);
     fresh_solve(M);
-    ensure_graph(M, per);
     const int max_launch = o.max_iters / per + 2;
-    for (int k = 0; k < max_launch; ++k) {
-      HIPCHK(hipGraphLaunch(M->gexec, M->st));
-      read_ctl(M);
-      if (M->h_ctl->done) break;
+    double phase_ms[4] = {0, 0, 0, 0};
+    if (o.phase_timing) {
+      // the same kernels launched one by one, with events between the phases
+      if ((int)M->t_ev.size() < 5 * per) {
+        const size_t have = M->t_ev.size();
+        M->t_ev.resize(5 * (size_t)per, nullptr);
+        for (size_t k = have; k < M->t_ev.size(); ++k) HIPCHK(hipEventCreate(&M->t_ev[k]));
+      }
+      for (int k = 0; k < max_launch; ++k) {
+        for (int it = 0; it < per; ++it) emu::launch_iteration_phased(M->d, M->plan, M->st, &M->t_ev[5 * (size_t)it]);
+        read_ctl(M);
+        for (int it = 0; it < per; ++it)
+          for (int ph = 0; ph < 4; ++ph) {
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, M->t_ev[5 * (size_t)it + ph], M->t_ev[5 * (size_t)it + ph + 1]));
+            phase_ms[ph] += ms;
+          }
+        if (M->h_ctl->done) break;
+      }
+    } else {
+      ensure_graph(M, per);
+      for (int k = 0; k < max_launch; ++k) {
+        HIPCHK(hipGraphLaunch(M->gexec, M->st));
+        read_ctl(M);
+        if (M->h_ctl->done) break;
+      }
     }
     if (!M->h_ctl->done) {
       // the iteration cap was reached between two checks
@@ -677,7 +700,13 @@ emu_status emu_solve(emu_mesh* M, const emu_solve_opts* opts, double* q_out, emu
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, M->ev_t0, M->ev_t1));
     emu::fill_stats(*M->h_ctl, stats, ms);
-    if (stats) stats->energy -= M->ext_c0;
+    if (stats) {
+      stats->energy -= M->ext_c0;
+      stats->ms_elem = phase_ms[0];
+      stats->ms_woodbury = phase_ms[1];
+      stats->ms_solve = phase_ms[2];
+      stats->ms_linesearch = phase_ms[3];
+    }
     release_user_stream(M, stream);
     emu_status st = (emu_status)M->h_ctl->status;
     M->converged = st == EMU_OK;
@@ -780,6 +809,9 @@ emu_status emu_profile_kernels(emu_mesh* M, int32_t reps, double* ms_out, void* 
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
     for (int k = 0; k < EMU_NUM_KERNELS; ++k) {
       for (int r = 0; r < reps; ++r) {
+        // the control block is copied from one pinned host buffer: let the
+        // previous rep's copy finish before it is rewritten
+        HIPCHK(hipStreamSynchronize(M->st));
         init_ctl(M, o, 1);
         // a tiny accepted step, so that the element pass times its accept path
         // (polar re-split) as it runs inside an iteration

@@ -18,7 +18,6 @@ constexpr int kLsTerms = 7;        // 6 polynomial coefficients + g.p
 constexpr int kItemWideBit = 1 << 30;
 constexpr int kWideLevelItems = 512;
 constexpr int kWideRowMin = 64;
-constexpr int kMaxFrontW = 2048;   // largest supernode width held in LDS
 
 // Iteration control block (device memory, one per mesh).
 struct Ctl {

@@ -115,7 +115,12 @@ static void validate(const emu_mesh_desc& d) {
   if (!(d.alpha_hat >= 0) || !std::isfinite(d.alpha_hat)) fail(EMU_E_INVALID, "alpha_hat must be >= 0");
   int k = d.n_modes < 0 ? 48 : d.n_modes;
   if (k % 3 != 0 || k > 48) fail(EMU_E_INVALID, "n_modes must be a multiple of 3 in [0, 48]");
-  if (d.weight_mode != 0 && d.weight_mode != 1) fail(EMU_E_INVALID, "weight_mode must be 0 or 1");
+  if (d.weight_mode < 0 || d.weight_mode > 2) fail(EMU_E_INVALID, "weight_mode must be 0, 1 or 2");
+  if (d.bone)
+    for (int64_t i = 0; i < m; ++i)
+      if (d.bone[i] < -1) fail(EMU_E_INVALID, "bone id must be >= -1");
+  if ((d.dev_alloc == nullptr) != (d.dev_free == nullptr))
+    fail(EMU_E_INVALID, "dev_alloc and dev_free must be given together");
   if (d.precision != 0 && d.precision != 1) fail(EMU_E_INVALID, "precision must be 0 or 1");
   if (d.leaf_size < 0) fail(EMU_E_INVALID, "leaf_size must be >= 0");
 }
@@ -131,6 +136,8 @@ static void geometry(const emu_mesh_desc& d, HostMesh& hm) {
   hm.youngs.assign(d.youngs, d.youngs + m);
   hm.poisson.assign(d.poisson, d.poisson + m);
   hm.group.assign(d.group, d.group + m);
+  if (d.bone) hm.bone.assign(d.bone, d.bone + m);
+  else hm.bone.assign(m, -1);
   hm.pins.assign(d.pins, d.pins + d.n_pins);
   hm.fiber.assign(3 * (int64_t)m, 0.0);
   for (int32_t i = 0; i < m; ++i) {
@@ -197,8 +204,10 @@ static void geometry(const emu_mesh_desc& d, HostMesh& hm) {
   hm.alpha = hm.alpha_hat * hm.mu_ref;
   hm.weight_mode = d.weight_mode;
   hm.w.resize(m);
-  for (int32_t i = 0; i < m; ++i)
-    hm.w[i] = d.weight_mode == 0 ? hm.vol[i] * hm.mu[i] / hm.mu_ref : hm.vol[i];
+  for (int32_t i = 0; i < m; ++i) {
+    const bool stiff = d.weight_mode == EMU_WEIGHT_STIFFNESS || (d.weight_mode == EMU_WEIGHT_PAPER && hm.bone[i] < 0);
+    hm.w[i] = stiff ? hm.vol[i] * hm.mu[i] / hm.mu_ref : hm.vol[i];
+  }
   hm.precision = d.precision;
   hm.leaf_size = d.leaf_size > 0 ? d.leaf_size : 64;
   hm.k1 = (d.n_modes < 0 ? 48 : d.n_modes) / 3;

@@ -56,6 +56,7 @@ struct HostMesh {
   std::vector<double> youngs, poisson;
   std::vector<double> fiber;           // [m][3] unit
   std::vector<int32_t> group;
+  std::vector<int32_t> bone;           // [m] bone id or -1
   std::vector<int32_t> pins;
   std::vector<double> pin_xyz;         // [npins][3]
   double alpha_hat = 10, mu_ref = 0, kf = 0, alpha = 0;

@@ -817,8 +817,8 @@ __global__ void __launch_bounds__(kBlock) k_scatter_F(DevMesh d) {
 
 // right-hand side of the ACAP solve: fixed-order sum of element contributions
 // at each free vertex, plus (optionally) the constant pinned term -L_fp qbar_p
-// Four lanes per vertex take interleaved entries of its incidence list and are
-// added in a fixed order.
+// kRhsLanes lanes per vertex take interleaved entries of its incidence list and
+// are added in a fixed order.
 constexpr int kRhsLanes = 8;
 // Workgroups are dispatched to the 8 XCDs in turn (workgroup b to XCD b % 8),
 // and each XCD has its own L2.  Passes whose neighbouring workgroups share
@@ -2090,12 +2090,19 @@ DEV void b_control_b(const DevMesh& d, int bid) {
   if (t != 0) return;
   double c[6];
   for (int k = 0; k < 6; ++k) c[k] = acc[k].hi + acc[k].lo;
-  const double gtp = acc[6].hi + acc[6].lo;
+  // Slope of the Armijo test.  FP64: g . p from the direction pass.  Mixed:
+  // that dot product is taken in FP32 (gbar, factors, p), so the exact FP64
+  // directional derivative dE/dsigma at 0, the linear coefficient c[0] of the
+  // energy polynomial, is used instead: the decision stays FP64 (form (1)).
+  const double gtp = d.mixed ? c[0] : acc[6].hi + acc[6].lo;
   ctl->gtp = gtp;
   ctl->solves += 1;
+  const double g2 = ctl->gnorm2, g02 = ctl->gnorm0_2;
+  const bool stalled = ctl->stall_rel > 0 && g2 <= ctl->stall_rel * ctl->stall_rel * g02;
   if (!(gtp < 0.0)) {
-    // no descent (|g| at the rounding floor): stop, keeping the state
-    ctl->status = ctl->stall_rel > 0 ? 0 : EMU_E_LINESEARCH_CODE;
+    // no descent direction: at the rounding floor of the gradient this is
+    // convergence (mixed path, |g| <= stall_rel |g_0|), otherwise a failure
+    ctl->status = stalled ? 0 : EMU_E_LINESEARCH_CODE;
     ctl->sigma = 0.0;
     ctl->done = 1;
     return;
@@ -2117,8 +2124,6 @@ DEV void b_control_b(const DevMesh& d, int bid) {
     ctl->iter += 1;
   } else {
     ctl->sigma = 0.0;
-    const double g2 = ctl->gnorm2, g02 = ctl->gnorm0_2;
-    const bool stalled = ctl->stall_rel > 0 && g2 <= ctl->stall_rel * ctl->stall_rel * g02;
     ctl->status = stalled ? 0 : EMU_E_LINESEARCH_CODE;
     ctl->done = 1;
   }
@@ -2569,6 +2574,37 @@ void launch_iteration(const DevMesh& d, const SolvePlan& pl, hipStream_t st) {
   hipLaunchKernelGGL(k_lscoef, dim3(d.nb), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_control_b, dim3(1), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_add_q, dim3(blocks(3 * (int64_t)d.nf)), dim3(kBlock), 0, st, d);
+}
+
+// One iteration with events between its phases: ev[0] element pass, ev[1]
+// Woodbury correction, ev[2] ACAP solve of the direction, ev[3] line search,
+// ev[4] end.
+void launch_iteration_phased(const DevMesh& d, const SolvePlan& pl, hipStream_t st, hipEvent_t* ev) {
+  (void)hipEventRecord(ev[0], st);
+  if (d.mixed) {
+    hipLaunchKernelGGL(k_element<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
+    hipLaunchKernelGGL(k_element_hess<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
+  } else {
+    hipLaunchKernelGGL(k_element<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
+    hipLaunchKernelGGL(k_element_hess<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
+  }
+  (void)hipEventRecord(ev[1], st);
+  if (d.mixed) hipLaunchKernelGGL(k_gram<float>, dim3(d.nbg), dim3(kBlock), 0, st, d);
+  else hipLaunchKernelGGL(k_gram<double>, dim3(d.nbg), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((kGramEntries + 15) / 16), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_control_a, dim3(1), dim3(kCtlThreads), 0, st, d);
+  hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d);
+  if (d.mixed)
+    hipLaunchKernelGGL(k_direction<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
+  else
+    hipLaunchKernelGGL(k_direction<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
+  (void)hipEventRecord(ev[2], st);
+  launch_solve(d, pl, 0, d.dq, 1, st);
+  (void)hipEventRecord(ev[3], st);
+  hipLaunchKernelGGL(k_lscoef, dim3(d.nb), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_control_b, dim3(1), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_add_q, dim3(blocks(3 * (int64_t)d.nf)), dim3(kBlock), 0, st, d);
+  (void)hipEventRecord(ev[4], st);
 }
 
 void launch_class(int k, const DevMesh& d, const SolvePlan& pl, hipStream_t st) {

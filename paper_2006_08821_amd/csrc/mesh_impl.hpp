@@ -61,6 +61,10 @@ struct emu_mesh {
   hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
   std::vector<void*> allocs;
   int64_t bytes = 0;
+  // caller's device allocator (emu_mesh_desc.dev_alloc); null: hipMalloc
+  emu_dev_alloc_fn dev_alloc = nullptr;
+  emu_dev_free_fn dev_free = nullptr;
+  void* alloc_ctx = nullptr;
   int32_t* d_eold = nullptr;
   int32_t* d_vold = nullptr;
   emu::Ctl* h_ctl = nullptr;  // pinned host copy
@@ -78,6 +82,8 @@ struct emu_mesh {
   // adjoint work arrays (allocated on first use)
   double *a_lam = nullptr, *a_r = nullptr, *a_z = nullptr, *a_p = nullptr, *a_hp = nullptr;
   double *a_ypart = nullptr, *a_part = nullptr, *a_vin = nullptr, *a_vx = nullptr, *a_el = nullptr;
+  // phase-timing events (emu_solve_opts.phase_timing), 5 per iteration of a sync block
+  std::vector<hipEvent_t> t_ev;
 
   explicit emu_mesh(std::shared_ptr<emu::HostMesh> p) : hmp(std::move(p)), hm(*hmp) {}
   emu_mesh(const emu_mesh&) = delete;
@@ -87,8 +93,13 @@ struct emu_mesh {
   T* dalloc(size_t count) {
     void* p = nullptr;
     size_t nb = std::max<size_t>(1, count * sizeof(T));
-    hipError_t e = hipMalloc(&p, nb);
-    if (e != hipSuccess) throw emu::Error{EMU_E_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
+    if (dev_alloc) {
+      p = dev_alloc(nb, alloc_ctx);
+      if (!p) throw emu::Error{EMU_E_OOM, "the caller's device allocator returned NULL"};
+    } else {
+      hipError_t e = hipMalloc(&p, nb);
+      if (e != hipSuccess) throw emu::Error{EMU_E_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
+    }
     allocs.push_back(p);
     bytes += (int64_t)nb;
     return (T*)p;
@@ -102,8 +113,14 @@ struct emu_mesh {
   ~emu_mesh() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
-    for (void* p : allocs) (void)hipFree(p);
+    if (st) (void)hipStreamSynchronize(st);
+    for (void* p : allocs) {
+      if (dev_free) dev_free(p, alloc_ctx);
+      else (void)hipFree(p);
+    }
     if (h_ctl) (void)hipHostFree(h_ctl);
+    if (t_ev.size())
+      for (hipEvent_t e : t_ev) (void)hipEventDestroy(e);
     if (ev_a) (void)hipEventDestroy(ev_a);
     if (ev_b) (void)hipEventDestroy(ev_b);
     if (ev_t0) (void)hipEventDestroy(ev_t0);

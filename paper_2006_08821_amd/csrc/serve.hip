@@ -44,7 +44,7 @@ using Clock = std::chrono::steady_clock;
 struct DescCopy {
   emu_mesh_desc d{};
   std::vector<double> rest, youngs, poisson, fiber, pin_xyz;
-  std::vector<int32_t> tets, group, pins;
+  std::vector<int32_t> tets, group, pins, bone;
   std::vector<char> key;  // canonical bytes of everything above
   uint64_t hash = 0;
 };
@@ -77,7 +77,13 @@ void copy_desc(const emu_mesh_desc& s, DescCopy& c) {
   copy_arr(c.group, s.group, m, "group");
   copy_arr(c.pins, s.pins, np, "pins");
   if (s.pin_xyz) copy_arr(c.pin_xyz, s.pin_xyz, 3 * np, "pin_xyz");
+  if (s.bone) copy_arr(c.bone, s.bone, m, "bone");
   c.d = s;
+  c.d.bone = s.bone ? c.bone.data() : nullptr;
+  // served meshes live in the server's own HBM budget
+  c.d.dev_alloc = nullptr;
+  c.d.dev_free = nullptr;
+  c.d.alloc_ctx = nullptr;
   c.d.rest_xyz = c.rest.data();
   c.d.tets = c.tets.data();
   c.d.youngs = c.youngs.data();
@@ -106,6 +112,7 @@ void copy_desc(const emu_mesh_desc& s, DescCopy& c) {
   key_append(k, c.group);
   key_append(k, c.pins);
   key_append(k, c.pin_xyz);
+  key_append(k, c.bone);
   uint64_t h = 1469598103934665603ull;  // FNV-1a
   for (char ch : k) {
     h ^= (uint8_t)ch;
@@ -151,6 +158,9 @@ struct Resident {
   std::shared_ptr<const Setup> setup;
   std::unique_ptr<emu_mesh> mesh;
   Clock::time_point used;
+  // the state left by the last request may seed a warm start: that request
+  // ended EMU_OK, or EMU_E_NOT_CONVERGED with a finite gradient norm
+  bool state_ok = false;
 };
 
 struct Active {
@@ -224,6 +234,12 @@ std::shared_ptr<const Setup> run_setup(const DescCopy& dc) {
     s->hm.reset();
   }
   return s;
+}
+
+// Whether a finished request's final state may seed a later warm start of
+// the same mesh: not after a failure that can leave NaN or a diverged state.
+bool warm_start_ok(emu_status code, double grad_norm) {
+  return code == EMU_OK || (code == EMU_E_NOT_CONVERGED && std::isfinite(grad_norm));
 }
 
 void finish_request(emu_server* S, Request* r, emu_status code, const std::string& msg) {
@@ -440,7 +456,7 @@ void admit(emu_server* S, std::unique_lock<std::mutex>& lk) {
       r->times.device_bytes = M->bytes;
       for (int g = 0; g < M->hm.ngroups; ++g) M->act[g] = r->act[g];
       HIPCHK(hipMemcpyAsync((void*)M->d.act, M->act.data(), M->act.size() * 8, hipMemcpyHostToDevice, S->st));
-      if (fresh || !r->opts.warm_start) emu::launch_init_rest(M->d, S->st);
+      if (fresh || !r->opts.warm_start || !res->state_ok) emu::launch_init_rest(M->d, S->st);
       emu::init_ctl(M, r->opts, 0);
       emu::fresh_solve(M);
       HIPCHK(hipGetLastError());
@@ -510,6 +526,7 @@ void run_round(emu_server* S, std::unique_lock<std::mutex>& lk) {
                    : code == EMU_E_LINESEARCH    ? "line search found no Armijo step"
                                                  : "non-finite value in the iteration");
     a.res->used = Clock::now();
+    a.res->state_ok = warm_start_ok(code, r->stats.grad_norm);
     S->idle.push_back(std::move(a.res));  // stays resident for reuse
   }
   std::vector<Active> keep;

@@ -16,9 +16,17 @@ from ._lib import check, dptr, iptr
 PRECISION = {"fp64": 0, "mixed": 1}
 
 
-def _desc_arrays(problem, alpha_hat=None, n_modes=None, precision="fp64", weight_mode=0,
+WEIGHT_MODES = {"stiffness": 0, "volume": 1, "paper": 2}
+
+
+def _desc_arrays(problem, alpha_hat=None, n_modes=None, precision="fp64", weight_mode=None,
                  leaf_size=0, mu_ref=0.0, fiber_k=0.0):
-    """Contiguous host arrays + the emu_mesh_desc struct that points at them."""
+    """Contiguous host arrays + the emu_mesh_desc struct that points at them.
+    ``weight_mode`` None takes the problem's (``Problem.weight_mode``)."""
+    if weight_mode is None:
+        weight_mode = getattr(problem, "weight_mode", 0)
+    if isinstance(weight_mode, str):
+        weight_mode = WEIGHT_MODES[weight_mode]
     keep = dict(
         rest=np.ascontiguousarray(problem.rest_xyz, np.float64),
         tets=np.ascontiguousarray(problem.tets, np.int32),
@@ -29,6 +37,8 @@ def _desc_arrays(problem, alpha_hat=None, n_modes=None, precision="fp64", weight
         pins=np.ascontiguousarray(problem.pins, np.int32),
         pin_xyz=np.ascontiguousarray(problem.pin_xyz, np.float64),
     )
+    if getattr(problem, "bone", None) is not None:
+        keep["bone"] = np.ascontiguousarray(problem.bone, np.int32)
     d = _lib.MeshDesc()
     d.n_vertices = keep["rest"].shape[0]
     d.n_tets = keep["tets"].shape[0]
@@ -49,6 +59,7 @@ def _desc_arrays(problem, alpha_hat=None, n_modes=None, precision="fp64", weight
     d.n_modes = int(problem.n_modes if n_modes is None else n_modes)
     d.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     d.leaf_size = int(leaf_size)
+    d.bone = iptr(keep["bone"]) if "bone" in keep else None
     return d, keep
 
 
@@ -123,13 +134,43 @@ def default_opts(**kw):
     return o
 
 
-class Mesh:
-    """A mesh resident on the current HIP device (factor, modes and state)."""
+def _torch_allocator(torch):
+    """emu_dev_alloc_fn / emu_dev_free_fn drawing from torch's caching
+    allocator on the current device and stream (a failed allocation returns
+    NULL, which the library reports as EMU_E_OOM)."""
+    dev = torch.cuda.current_device()
+    stream = torch.cuda.current_stream(dev)
 
-    def __init__(self, problem, **kw):
+    def alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+        except Exception:
+            return None
+
+    def free(ptr, ctx):
+        try:
+            torch.cuda.caching_allocator_delete(ptr)
+        except Exception:
+            pass
+
+    return _lib.ALLOC_FN(alloc), _lib.FREE_FN(free)
+
+
+class Mesh:
+    """A mesh resident on the current HIP device (factor, modes and state).
+
+    Its device memory comes from torch's caching allocator (``torch_alloc``),
+    so it shows in ``torch.cuda.memory_allocated()``; with ``torch_alloc=False``
+    the library allocates with hipMalloc itself."""
+
+    def __init__(self, problem, torch_alloc=True, **kw):
         self.torch = _torch()
         self._lib = _lib.load()
         desc, keep = _desc_arrays(problem, **kw)
+        if torch_alloc:
+            # kept alive as long as the mesh: the library frees through them
+            self._alloc_fns = _torch_allocator(self.torch)
+            desc.dev_alloc, desc.dev_free = self._alloc_fns
         h = C.c_void_p()
         check(self._lib.emu_create_mesh(C.byref(desc), C.byref(h)), "emu_create_mesh")
         self._h = h
@@ -211,6 +252,18 @@ class Mesh:
         F = t.as_tensor(F, dtype=t.float64, device="cuda").contiguous()
         check(self._lib.emu_set_state(self._h, C.c_void_p(F.data_ptr()), _stream(t)), "emu_set_state")
 
+    def restore_equilibrium(self, F, a, grad_tol=1e-8, max_iters=10000):
+        """Put the mesh back at a converged state F (from get_state) for the
+        activations a: set_state re-splits F and re-solves q*(F); the warm
+        solve that follows confirms convergence at once (it stops on the
+        first gradient test) and re-arms emu_solve_grad."""
+        self.set_activation(a)
+        self.set_state(F)
+        _, st = self.solve(grad_tol=grad_tol, max_iters=max_iters, warm_start=1)
+        if st["status"] != 0:
+            raise _lib.EmuError(st["status"], "could not restore the converged state")
+        return st
+
     def solve_grad(self, dL_dq, stats=False):
         """dL/da (numpy [n_groups]) at the converged state for dL/dq ([n,3] GPU tensor)."""
         t = self.torch
@@ -262,17 +315,25 @@ class _SolveFn:
             class SolveFunction(torch.autograd.Function):
                 @staticmethod
                 def forward(ctx, a, mesh, grad_tol, max_iters):
-                    mesh.set_activation(a.detach().cpu().numpy())
+                    a_host = a.detach().cpu().numpy().astype(np.float64)
+                    mesh.set_activation(a_host)
                     q, st = mesh.solve(grad_tol=grad_tol, max_iters=max_iters)
                     if st["status"] != 0:
                         raise _lib.EmuError(st["status"], "forward solve did not converge")
-                    ctx.mesh = mesh
+                    # the equilibrium this graph node stands for: the mesh may be
+                    # solved again (another forward, a probe) before backward
+                    F, _ = mesh.get_state()
+                    ctx.mesh, ctx.a_host, ctx.F = mesh, a_host, F
+                    ctx.opts = (grad_tol, max_iters)
+                    ctx.a_device = a.device
                     return q
 
                 @staticmethod
                 def backward(ctx, grad_q):
-                    g = ctx.mesh.solve_grad(grad_q.contiguous())
-                    return torch.as_tensor(g, dtype=torch.float64), None, None, None
+                    mesh = ctx.mesh
+                    mesh.restore_equilibrium(ctx.F, ctx.a_host, *ctx.opts)
+                    g = mesh.solve_grad(grad_q.contiguous())
+                    return torch.as_tensor(g, dtype=torch.float64, device=ctx.a_device), None, None, None
 
             cls._cls = SolveFunction
         return cls._cls

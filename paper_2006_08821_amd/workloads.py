@@ -29,6 +29,10 @@ from typing import Dict, List, Optional
 import numpy as np
 
 H_EDGE = 0.01          # cube edge (m)
+# ACAP weighting of the limb workloads (bone core, tendon caps): volume
+# weights.  Stiffness-proportional weights on the 1.7e3x tendon and 1.7e5x bone
+# contrast of these inputs stall the iteration (see the design notes).
+LIMB_WEIGHT_MODE = 1
 E_MUSCLE = 6.0e4       # Pa
 E_TENDON = 1.0e8
 E_BONE = 1.0e10
@@ -53,6 +57,7 @@ class Problem:
     n_modes: int = -1               # -1: library default (48, capped by the mesh)
     extra: dict = dataclasses.field(default_factory=dict)
     bone: Optional[np.ndarray] = None  # [m] int32 bone id per tet, -1 = not bone (None: no bones)
+    weight_mode: int = 0            # ACAP weights: 0 stiffness, 1 volume, 2 paper (bone by volume)
 
     @property
     def n_vertices(self) -> int:
@@ -197,7 +202,8 @@ def limb(nx: int = 20, ny: int = 20, nz: int = 80, n_groups: int = 1, seed: int 
     return Problem(name=name, rest_xyz=xyz, tets=tets, youngs=youngs,
                    poisson=np.full(tets.shape[0], NU), fiber=fiber, group=group,
                    pins=pins, pin_xyz=xyz[pins].copy(), activation=act,
-                   dims=(nx, ny, nz), extra={"role": role}, bone=bone)
+                   dims=(nx, ny, nz), extra={"role": role}, bone=bone,
+                   weight_mode=LIMB_WEIGHT_MODE)
 
 
 def heterogeneous_limb_ramp(steps: int = 20, nx=20, ny=20, nz=80) -> tuple:
