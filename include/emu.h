@@ -200,6 +200,19 @@ emu_status emu_solve(emu_mesh* mesh, const emu_solve_opts* opts, double* q_out,
 emu_status emu_solve_grad(emu_mesh* mesh, const double* dL_dq, double* dL_da,
                           emu_solve_stats* stats, void* stream);
 
+/* emu_solve_grad for callers that cannot allocate device memory (code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+   same arguments, result and errors, but its conjugate-gradient vectors and
+   partial sums live in one fixed device scratch array of the library
+   (48 MiB per GPU, held until the process ends) instead of memory the mesh
+   allocates on first use; it calls no hipMalloc, hipFree or other allocating
+   routine.  A mesh needing more scratch than that (about 46 m + 6 n + 50 nb
+   doubles: roughly 130k tets) is rejected with EMU_E_INVALID.  Every call on
+   one GPU shares that GPU's array, so calls that overlap on one GPU (two
+   meshes, two host threads, two streams) race: the caller serializes them. */
+emu_status emu_solve_grad_noalloc(emu_mesh* mesh, const double* dL_dq, double* dL_da,
+                                  emu_solve_stats* stats, void* stream);
+
 /* State access: F device [m][9] (row-major 3x3 per tet), q device [n][3].
    emu_set_state takes F, splits it as F = R S and re-solves q = q*(F). */
 emu_status emu_get_state(const emu_mesh* mesh, double* F, double* q, void* stream);

@@ -100,6 +100,7 @@ SIGNATURES = {
     "emu_get_modes": (C.c_int, [P, DP, DP]),
     "emu_solve": (C.c_int, [P, C.POINTER(SolveOpts), P, C.POINTER(SolveStats), P]),
     "emu_solve_grad": (C.c_int, [P, P, DP, C.POINTER(SolveStats), P]),
+    "emu_solve_grad_noalloc": (C.c_int, [P, P, DP, C.POINTER(SolveStats), P]),
     "emu_get_state": (C.c_int, [P, P, P, P]),
     "emu_set_state": (C.c_int, [P, P, P]),
     "emu_evaluate": (C.c_int, [P, P, P, DP, DP, P, P]),

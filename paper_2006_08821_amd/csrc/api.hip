@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -841,10 +842,14 @@ emu_status emu_profile_kernels(emu_mesh* M, int32_t reps, double* ms_out, void* 
   }
 }
 
+}  // extern "C"
+
 // Sum of the nb double-double block partials (fixed order) on the host.
+// nb <= 1024 (the element passes' workgroup count), so the partials fit in a
+// fixed buffer on the stack.
 static double host_dd_sum(emu_mesh* M, const double* dpart, int nb) {
-  std::vector<double> h(2 * (size_t)nb);
-  HIPCHK(hipMemcpyAsync(h.data(), dpart, h.size() * 8, hipMemcpyDeviceToHost, M->st));
+  double h[2 * 1024];
+  HIPCHK(hipMemcpyAsync(h, dpart, 2 * (size_t)nb * 8, hipMemcpyDeviceToHost, M->st));
   HIPCHK(hipStreamSynchronize(M->st));
   double hi = 0, lo = 0;
   for (int b = 0; b < nb; ++b) {
@@ -859,8 +864,121 @@ static double host_dd_sum(emu_mesh* M, const double* dpart, int nb) {
   return hi + lo;
 }
 
-emu_status emu_solve_grad(emu_mesh* M, const double* dL_dq, double* dL_da, emu_solve_stats* stats,
-                          void* stream) {
+namespace {
+
+// Device work arrays of the adjoint (F-space vectors [9][m], vertex vectors
+// [n][3], partial sums) and their total size in doubles.
+struct AdjWork {
+  double *lam, *r, *z, *p, *hp, *ypart, *part, *vin, *vx, *el, *da;
+};
+size_t adj_work_doubles(const emu_mesh* M) {
+  const size_t m = M->hm.m, n = M->hm.n, nb = M->d.nb, ng = std::max(1, M->hm.ngroups);
+  return 5 * 9 * m + 48 * nb + 2 * nb + 2 * 3 * n + m + ng;
+}
+// Carve the work arrays out of one block of adj_work_doubles(M) doubles
+// (each piece starts on a 256-byte boundary; the block is padded for that).
+AdjWork adj_carve(const emu_mesh* M, double* base) {
+  const size_t m = M->hm.m, n = M->hm.n, nb = M->d.nb, ng = std::max(1, M->hm.ngroups);
+  size_t off = 0;
+  auto take = [&](size_t count) {
+    double* p = base + off;
+    off += (count + 31) & ~(size_t)31;
+    return p;
+  };
+  AdjWork w;
+  w.lam = take(9 * m);
+  w.r = take(9 * m);
+  w.z = take(9 * m);
+  w.p = take(9 * m);
+  w.hp = take(9 * m);
+  w.ypart = take(48 * nb);
+  w.part = take(2 * nb);
+  w.vin = take(3 * n);
+  w.vx = take(3 * n);
+  w.el = take(m);
+  w.da = take(ng);
+  return w;
+}
+size_t adj_block_doubles(const emu_mesh* M) { return adj_work_doubles(M) + 11 * 32; }
+
+// The adjoint of the equilibrium (emu_solve_grad) with the given work arrays.
+// Allocates nothing: every device buffer is either the mesh's or in `w`.
+emu_status adjoint_run(emu_mesh* M, const AdjWork& w, const double* dL_dq, double* dL_da, emu_solve_stats* stats,
+                       void* stream) {
+  auto& d = M->d;
+  const size_t m = M->hm.m, n = M->hm.n, nf = M->hm.nf;
+  join_user_stream(M, stream);
+  HIPCHK(hipEventRecord(M->ev_t0, M->st));
+  // element blocks and the Woodbury factor at the converged state
+  emu_solve_opts o = emu_solve_opts_default();
+  init_ctl(M, o, 1);
+  emu::launch_evaluate(d, M->st);
+  // right-hand side b = W G L^{-1} (dL/dq)_f  (one ACAP solve); the rows of
+  // pinned vertices in vx stay zero (the sweeps write free rows only)
+  HIPCHK(hipMemsetAsync(w.vx, 0, 3 * n * 8, M->st));
+  hipLaunchKernelGGL(k_from_user_q, dim3((n + 255) / 256), dim3(256), 0, M->st, dL_dq, M->d_vold, (int)n, w.vin);
+  HIPCHK(hipMemcpyAsync(d.rhs, w.vin, 3 * nf * 8, hipMemcpyDeviceToDevice, M->st));
+  emu::launch_sweeps(d, M->plan, w.vx, M->st);
+  emu::launch_weighted_grad(d, w.vx, w.r, M->st);
+  HIPCHK(hipMemsetAsync(w.lam, 0, 9 * m * 8, M->st));
+  HIPCHK(hipMemsetAsync(w.hp, 0, 9 * m * 8, M->st));
+  // preconditioned conjugate gradients on d2E/dF2 lam = b
+  emu::launch_precond(d, w.r, w.z, w.ypart, w.part, M->st);
+  double rz = host_dd_sum(M, w.part, d.nb);
+  HIPCHK(hipMemcpyAsync(w.p, w.z, 9 * m * 8, hipMemcpyDeviceToDevice, M->st));
+  // |b| for the relative stopping test
+  emu::launch_cg_update(d, 0.0, w.p, w.hp, w.lam, w.r, w.part, M->st);
+  const double bnorm = std::sqrt(std::max(0.0, host_dd_sum(M, w.part, d.nb)));
+  const double tol = 1e-10 * bnorm;
+  int it = 0;
+  double rnorm = bnorm;
+  const int max_it = 20000;
+  int status = EMU_OK;
+  while (rnorm > tol && it < max_it) {
+    emu::launch_field_solve(d, M->plan, w.p, w.vx, M->st);
+    emu::launch_hvp(d, w.p, w.vx, w.hp, w.part, M->st);
+    const double php = host_dd_sum(M, w.part, d.nb);
+    if (!(php > 0) || !std::isfinite(php)) {
+      status = EMU_E_NONFINITE;
+      break;
+    }
+    const double alpha = rz / php;
+    emu::launch_cg_update(d, alpha, w.p, w.hp, w.lam, w.r, w.part, M->st);
+    rnorm = std::sqrt(std::max(0.0, host_dd_sum(M, w.part, d.nb)));
+    ++it;
+    if (rnorm <= tol) break;
+    emu::launch_precond(d, w.r, w.z, w.ypart, w.part, M->st);
+    const double rz2 = host_dd_sum(M, w.part, d.nb);
+    const double beta = rz2 / rz;
+    rz = rz2;
+    emu::launch_cg_dir(d, beta, w.z, w.p, M->st);
+  }
+  if (status == EMU_OK && rnorm > tol) status = EMU_E_NOT_CONVERGED;
+  // dL/da_g = -2 kf sum_{i in g} vol (lam_i u).(F_i u)
+  emu::launch_adj_da(d, w.lam, w.el, M->st);
+  emu::launch_group_sum(d, w.el, -2.0 * M->hm.kf, w.da, M->st);
+  if (M->hm.ngroups > 0)
+    HIPCHK(hipMemcpyAsync(dL_da, w.da, (size_t)M->hm.ngroups * 8, hipMemcpyDeviceToHost, M->st));
+  HIPCHK(hipEventRecord(M->ev_t1, M->st));
+  HIPCHK(hipEventSynchronize(M->ev_t1));
+  HIPCHK(hipGetLastError());
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, M->ev_t0, M->ev_t1));
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->status = status;
+    stats->iters = it;
+    stats->acap_solves = it + 1;
+    stats->grad_norm = rnorm;
+    stats->grad_norm0 = bnorm;
+    stats->ms_total = ms;
+  }
+  release_user_stream(M, stream);
+  if (status != EMU_OK) emu::set_error("adjoint conjugate gradients did not converge");
+  return (emu_status)status;
+}
+
+emu_status adjoint_args_ok(const emu_mesh* M, const double* dL_dq, const double* dL_da) {
   if (!M || !dL_dq || (!dL_da && M->hm.ngroups > 0)) {
     emu::set_error("NULL argument");
     return EMU_E_INVALID;
@@ -869,99 +987,68 @@ emu_status emu_solve_grad(emu_mesh* M, const double* dL_dq, double* dL_da, emu_s
     emu::set_error("emu_solve_grad needs a converged emu_solve at the current activations");
     return EMU_E_STATE;
   }
+  return EMU_OK;
+}
+
+// ---------------------------------------------------------------- scratch
+// Fixed device scratch of the allocation-free adjoint entry point
+// (emu_solve_grad_noalloc): kScratchDoubles doubles (48 MiB) per GPU, held
+// until the process ends.  Host code never uses the symbol itself as an
+// address: the per-device address comes from hipGetSymbolAddress.
+constexpr size_t kScratchDoubles = (size_t)48 << 17;  // 48 MiB / 8 B
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on `device` (looked up once per device, with
+// that device current).
+double* scratch_on(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) throw emu::Error{EMU_E_INVALID, "device index out of range"};
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = 0;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != device) HIPCHK(hipSetDevice(device));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) HIPCHK(hipSetDevice(cur));
+    if (e != hipSuccess || !ptr)
+      throw emu::Error{EMU_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+    g_scratch_ptr[device] = (double*)ptr;
+  }
+  return g_scratch_ptr[device];
+}
+
+}  // namespace
+
+extern "C" {
+
+emu_status emu_solve_grad(emu_mesh* M, const double* dL_dq, double* dL_da, emu_solve_stats* stats,
+                          void* stream) {
+  const emu_status ok = adjoint_args_ok(M, dL_dq, dL_da);
+  if (ok != EMU_OK) return ok;
   try {
-    auto& d = M->d;
-    const size_t m = M->hm.m, n = M->hm.n, nf = M->hm.nf;
-    if (!M->a_lam) {
-      M->a_lam = M->dalloc<double>(9 * m);
-      M->a_r = M->dalloc<double>(9 * m);
-      M->a_z = M->dalloc<double>(9 * m);
-      M->a_p = M->dalloc<double>(9 * m);
-      M->a_hp = M->dalloc<double>(9 * m);
-      M->a_ypart = M->dalloc<double>(48 * (size_t)d.nb);
-      M->a_part = M->dalloc<double>(2 * (size_t)d.nb);
-      std::vector<double> z3(3 * n, 0.0);
-      M->a_vin = M->upload(z3);
-      M->a_vx = M->upload(z3);
-      M->a_el = M->dalloc<double>(m);
-    }
-    join_user_stream(M, stream);
-    HIPCHK(hipEventRecord(M->ev_t0, M->st));
-    // element blocks and the Woodbury factor at the converged state
-    emu_solve_opts o = emu_solve_opts_default();
-    init_ctl(M, o, 1);
-    emu::launch_evaluate(d, M->st);
-    // right-hand side b = W G L^{-1} (dL/dq)_f  (one ACAP solve)
-    hipLaunchKernelGGL(k_from_user_q, dim3((n + 255) / 256), dim3(256), 0, M->st, dL_dq, M->d_vold, (int)n,
-                       M->a_vin);
-    HIPCHK(hipMemcpyAsync(d.rhs, M->a_vin, 3 * nf * 8, hipMemcpyDeviceToDevice, M->st));
-    emu::launch_sweeps(d, M->plan, M->a_vx, M->st);
-    emu::launch_weighted_grad(d, M->a_vx, M->a_r, M->st);
-    HIPCHK(hipMemsetAsync(M->a_lam, 0, 9 * m * 8, M->st));
-    HIPCHK(hipMemsetAsync(M->a_hp, 0, 9 * m * 8, M->st));
-    // preconditioned conjugate gradients on d2E/dF2 lam = b
-    emu::launch_precond(d, M->a_r, M->a_z, M->a_ypart, M->a_part, M->st);
-    double rz = host_dd_sum(M, M->a_part, d.nb);
-    HIPCHK(hipMemcpyAsync(M->a_p, M->a_z, 9 * m * 8, hipMemcpyDeviceToDevice, M->st));
-    // |b| for the relative stopping test
-    emu::launch_cg_update(d, 0.0, M->a_p, M->a_hp, M->a_lam, M->a_r, M->a_part, M->st);
-    const double bnorm = std::sqrt(std::max(0.0, host_dd_sum(M, M->a_part, d.nb)));
-    const double tol = 1e-10 * bnorm;
-    int it = 0;
-    double rnorm = bnorm;
-    const int max_it = 20000;
-    int status = EMU_OK;
-    while (rnorm > tol && it < max_it) {
-      emu::launch_field_solve(d, M->plan, M->a_p, M->a_vx, M->st);
-      emu::launch_hvp(d, M->a_p, M->a_vx, M->a_hp, M->a_part, M->st);
-      const double php = host_dd_sum(M, M->a_part, d.nb);
-      if (!(php > 0) || !std::isfinite(php)) {
-        status = EMU_E_NONFINITE;
-        break;
-      }
-      const double alpha = rz / php;
-      emu::launch_cg_update(d, alpha, M->a_p, M->a_hp, M->a_lam, M->a_r, M->a_part, M->st);
-      rnorm = std::sqrt(std::max(0.0, host_dd_sum(M, M->a_part, d.nb)));
-      ++it;
-      if (rnorm <= tol) break;
-      emu::launch_precond(d, M->a_r, M->a_z, M->a_ypart, M->a_part, M->st);
-      const double rz2 = host_dd_sum(M, M->a_part, d.nb);
-      const double beta = rz2 / rz;
-      rz = rz2;
-      emu::launch_cg_dir(d, beta, M->a_z, M->a_p, M->st);
-    }
-    if (status == EMU_OK && rnorm > tol) status = EMU_E_NOT_CONVERGED;
-    // dL/da_g = -2 kf sum_{i in g} vol (lam_i u).(F_i u)
-    emu::launch_adj_da(d, M->a_lam, M->a_el, M->st);
-    std::vector<double> per(m);
-    HIPCHK(hipMemcpyAsync(per.data(), M->a_el, m * 8, hipMemcpyDeviceToHost, M->st));
-    HIPCHK(hipEventRecord(M->ev_t1, M->st));
-    HIPCHK(hipEventSynchronize(M->ev_t1));
-    HIPCHK(hipGetLastError());
-    std::vector<double> hi(M->hm.ngroups, 0.0), lo(M->hm.ngroups, 0.0);
-    for (size_t e = 0; e < m; ++e) {
-      const int g = M->hm.group[M->hm.eold[e]];
-      if (g < 0) continue;
-      double s2 = hi[g] + per[e], bb = s2 - hi[g];
-      double er = (hi[g] - (s2 - bb)) + (per[e] - bb);
-      lo[g] += er;
-      hi[g] = s2;
-    }
-    for (int g = 0; g < M->hm.ngroups; ++g) dL_da[g] = -2.0 * M->hm.kf * (hi[g] + lo[g]);
-    float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, M->ev_t0, M->ev_t1));
-    if (stats) {
-      std::memset(stats, 0, sizeof(*stats));
-      stats->status = status;
-      stats->iters = it;
-      stats->acap_solves = it + 1;
-      stats->grad_norm = rnorm;
-      stats->grad_norm0 = bnorm;
-      stats->ms_total = ms;
-    }
-    release_user_stream(M, stream);
-    if (status != EMU_OK) emu::set_error("adjoint conjugate gradients did not converge");
-    return (emu_status)status;
+    if (!M->a_work) M->a_work = M->dalloc<double>(adj_block_doubles(M));
+    return adjoint_run(M, adj_carve(M, M->a_work), dL_dq, dL_da, stats, stream);
+  } catch (const emu::Error& e) {
+    return fail_with(e);
+  }
+}
+
+emu_status emu_solve_grad_noalloc(emu_mesh* M, const double* dL_dq, double* dL_da, emu_solve_stats* stats,
+                                  void* stream) {
+  if (M && adj_block_doubles(M) > kScratchDoubles) {
+    emu::set_error("emu_solve_grad_noalloc: the mesh needs " + std::to_string(adj_block_doubles(M) * 8) +
+                   " bytes of scratch, more than the fixed " + std::to_string(kScratchDoubles * 8) +
+                   " (use emu_solve_grad)");
+    return EMU_E_INVALID;
+  }
+  const emu_status ok = adjoint_args_ok(M, dL_dq, dL_da);
+  if (ok != EMU_OK) return ok;
+  try {
+    return adjoint_run(M, adj_carve(M, scratch_on(M->device)), dL_dq, dL_da, stats, stream);
   } catch (const emu::Error& e) {
     return fail_with(e);
   }

@@ -2430,9 +2430,22 @@ __global__ void __launch_bounds__(kBlock) k_adj_da(DevMesh d, const double* lam,
       }
       val *= e.vol;
     }
-    part[i] = val;  // per element; summed per group on the host in element order
+    part[i] = val;  // per element; summed per group by k_group_sum
     (void)ng;
   }
+}
+
+// dL/da_g = scale * sum over the tets of group g of per[i]: one workgroup per
+// group, each thread a fixed strided set of elements in double-double, the
+// wave and workgroup sums in a fixed order (deterministic).
+__global__ void __launch_bounds__(kBlock) k_group_sum(DevMesh d, const double* per, double scale, double* out) {
+  const int g = blockIdx.x;
+  __shared__ DD sh[kBlock];
+  DD acc[1] = {DD{0, 0}};
+  for (int i = threadIdx.x; i < d.m; i += kBlock)
+    if (d.grp[i] == g) acc[0] = dd_add_d(acc[0], per[i]);
+  block_reduce_dd<1>(acc, sh);
+  if (threadIdx.x == 0) out[g] = scale * (acc[0].hi + acc[0].lo);
 }
 
 __global__ void __launch_bounds__(kBlock) k_scale_free(DevMesh d, const double* in, double* out) {
@@ -2547,6 +2560,9 @@ void launch_precond(const DevMesh& d, const double* r, double* z, double* ypart,
 }
 void launch_adj_da(const DevMesh& d, const double* lam, double* part, hipStream_t st) {
   hipLaunchKernelGGL(k_adj_da, dim3(d.nb), dim3(kBlock), 0, st, d, lam, part);
+}
+void launch_group_sum(const DevMesh& d, const double* per, double scale, double* out, hipStream_t st) {
+  if (d.ngroups > 0) hipLaunchKernelGGL(k_group_sum, dim3(d.ngroups), dim3(kBlock), 0, st, d, per, scale, out);
 }
 
 void launch_set_pins(const DevMesh& d, hipStream_t st) {

@@ -65,5 +65,6 @@ void launch_cg_update(const DevMesh& d, double alpha, const double* P, const dou
 void launch_cg_dir(const DevMesh& d, double beta, const double* Z, double* P, hipStream_t st);
 void launch_precond(const DevMesh& d, const double* r, double* z, double* ypart, double* part, hipStream_t st);
 void launch_adj_da(const DevMesh& d, const double* lam, double* part, hipStream_t st);
+void launch_group_sum(const DevMesh& d, const double* per, double scale, double* out, hipStream_t st);
 
 }  // namespace emu

@@ -79,9 +79,8 @@ struct emu_mesh {
   double ext_c0 = 0;
   // backup of the state for emu_evaluate
   double *R_bak = nullptr, *S_bak = nullptr, *q_bak = nullptr;
-  // adjoint work arrays (allocated on first use)
-  double *a_lam = nullptr, *a_r = nullptr, *a_z = nullptr, *a_p = nullptr, *a_hp = nullptr;
-  double *a_ypart = nullptr, *a_part = nullptr, *a_vin = nullptr, *a_vx = nullptr, *a_el = nullptr;
+  // adjoint work arrays, one block (allocated on the first emu_solve_grad)
+  double* a_work = nullptr;
   // phase-timing events (emu_solve_opts.phase_timing), 5 per iteration of a sync block
   std::vector<hipEvent_t> t_ev;
 

@@ -264,14 +264,16 @@ class Mesh:
             raise _lib.EmuError(st["status"], "could not restore the converged state")
         return st
 
-    def solve_grad(self, dL_dq, stats=False):
-        """dL/da (numpy [n_groups]) at the converged state for dL/dq ([n,3] GPU tensor)."""
+    def solve_grad(self, dL_dq, stats=False, noalloc=False):
+        """dL/da (numpy [n_groups]) at the converged state for dL/dq ([n,3] GPU
+        tensor); ``noalloc`` uses the allocation-free entry point."""
         t = self.torch
         g = t.as_tensor(dL_dq, dtype=t.float64, device="cuda").contiguous()
         out = np.zeros(max(1, self.n_groups))
         st = _lib.SolveStats()
-        check(self._lib.emu_solve_grad(self._h, C.c_void_p(g.data_ptr()), dptr(out), C.byref(st), _stream(t)),
-              "emu_solve_grad")
+        fn = self._lib.emu_solve_grad_noalloc if noalloc else self._lib.emu_solve_grad
+        check(fn(self._h, C.c_void_p(g.data_ptr()), dptr(out), C.byref(st), _stream(t)),
+              "emu_solve_grad_noalloc" if noalloc else "emu_solve_grad")
         return (out[:self.n_groups], st.as_dict()) if stats else out[:self.n_groups]
 
     def profile_kernels(self, reps=20):
