@@ -3,15 +3,17 @@
 
 A step is one full iteration of the method (Sec. 3.2.1 / Algorithm 1): element
 pass, Woodbury Gram and solve, direction, ACAP triangular solve, exact
-line-search polynomial, Armijo test and accept.  The workload is the
-heterogeneous limb: a 20x20x80 Kuhn grid (192,000 tets), bone core / tendon
-caps / muscle, helical fibers, z=0 face pinned, one muscle group on a 20-step
-activation ramp (frame 1, a = 0.05, warm-started from rest).
+line-search polynomial, Armijo test and accept.  The headline workload is the
+largest single-GPU configuration: the hinge limb, a 40x40x160 Kuhn grid
+(1,536,000 tets), two bones joined by a pinned hinge line at mid-length, bone
+core / tendon caps / muscle, helical fibers, four quadrant muscle groups at
+the seeded activations of frame 0, FP64, warm state.
 
 Prints ONE JSON line: element-iterations/s (whole job, inputs resident in HBM),
 the roofline of the dominant kernel (HIP-event timing inside this process),
-frame solves/s with p50/p99 latency, the mixed-precision line and the CPU
-oracle baseline.
+converged frame solves/s with p50/p99 latency, the mixed-precision line, the
+192k-tet heterogeneous limb (its 20-frame activation ramp), the serving leg,
+the alpha search and the CPU oracle baseline.
 """
 from __future__ import annotations
 
@@ -77,50 +79,91 @@ def measured_traffic(kernel):
     return None
 
 
+def timed_line(p, prec, args, label):
+    """Host setup, warmup, then exactly ``steps`` iterations (a multiple of
+    the graph length, so every replayed iteration is a timed one) from the
+    warm state with the stop test off; per-kernel HIP-event times and
+    per-phase times of a short extra run."""
+    import torch
+    from paper_2006_08821_amd.emu import Mesh
+    t0 = time.time()
+    mesh = Mesh(p, precision=prec, leaf_size=args.leaf_size)
+    setup_s = time.time() - t0
+    info = mesh.info()
+    sync = args.iters_per_sync
+    steps = max(sync, (args.steps + sync - 1) // sync * sync)
+    mesh.solve(grad_tol=0.0, max_iters=args.warmup, iters_per_sync=sync, raise_on_error=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    q, st = mesh.solve(grad_tol=0.0, max_iters=steps, iters_per_sync=sync, raise_on_error=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = max(1, st["iters"])
+    prof = mesh.profile_kernels(reps=args.profile_reps)
+    _, sp = mesh.solve(grad_tol=0.0, max_iters=2 * sync, iters_per_sync=sync, phase_timing=1,
+                       raise_on_error=False)
+    ni = max(1, sp["iters"])
+    phases = {k: sp["ms_" + k] / ni for k in ("elem", "woodbury", "solve", "linesearch")}
+    print(f"[bench] {label} {prec}: {iters} iterations in {dt*1e3:.1f} ms ({dt/iters*1e3:.3f} ms/iter), "
+          f"setup {setup_s:.1f} s", file=sys.stderr, flush=True)
+    return dict(mesh=mesh, info=info, st=st, dt=dt, iters=iters, prof=prof, setup_s=setup_s,
+                q=q.cpu().numpy(), phases=phases)
+
+
+def roofline(prof, m, n, nnz, mixed=False):
+    """Roofline of the dominant kernel class by time (HIP events, on the
+    mesh's stream): algorithmic bytes (or Gram flops) per launch over the
+    average launch time."""
+    dom = max((k for k in prof if algorithmic_bytes(k, m, n, nnz, mixed) is not None or k == "gram"),
+              key=lambda k: prof[k])
+    if dom == "gram":
+        ach = GRAM_FLOPS_PER_ELEMENT * m / (prof[dom] * 1e-3) / 1e12
+        peak = FP64_PEAK_TFLOPS
+        return dict(bound="mfma", kernel=dom, achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak,
+                    traffic=measured_traffic(dom), ms=prof[dom])
+    ach = algorithmic_bytes(dom, m, n, nnz, mixed) / (prof[dom] * 1e-3) / 1e9
+    return dict(bound="hbm", kernel=dom, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                traffic=measured_traffic(dom), ms=prof[dom])
+
+
+def frame_solves(mesh, acts, tol, max_iters, keep_q=None):
+    """Warm-started frame solves (each from the previous frame's equilibrium)
+    to |g| <= tol; solves/s and latency over the frames, counting converged
+    ones.  ``keep_q`` (a list) receives the last frame's positions."""
+    import torch
+    lat, conv, its = [], 0, 0
+    q = None
+    t_all = time.perf_counter()
+    for a in acts:
+        mesh.set_activation(a)
+        t0 = time.perf_counter()
+        q, st = mesh.solve(grad_tol=tol, max_iters=max_iters, raise_on_error=False)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+        conv += st["status"] == 0
+        its += st["iters"]
+    t_all = time.perf_counter() - t_all
+    if keep_q is not None and q is not None:
+        keep_q.append(q.cpu().numpy())
+    ok = conv == len(acts)
+    return {"count": len(acts), "converged": conv, "grad_tol": tol, "iterations": its,
+            "solves_per_s": len(acts) / t_all if ok else None,
+            "latency_ms_p50": float(np.percentile(lat, 50)) if ok else None,
+            "latency_ms_p99": float(np.percentile(lat, 99)) if ok else None,
+            "wall_s": t_all}
+
+
 def run(args):
     import torch
     from paper_2006_08821_amd import workloads as wl
-    from paper_2006_08821_amd.emu import Mesh
 
-    p, ramp = wl.heterogeneous_limb_ramp()
-    p.activation = ramp[0].copy()
-    res = {}
+    p, acts = wl.hinge_limb(40, 40, 160, frames=max(1, args.frames + 1))
     lines = {}
     for prec in (["fp64", "mixed"] if args.precision == "both" else [args.precision]):
-        t0 = time.time()
-        mesh = Mesh(p, precision=prec, leaf_size=args.leaf_size)
-        setup_s = time.time() - t0
-        info = mesh.info()
-        # warmup
-        mesh.solve(grad_tol=0.0, max_iters=args.warmup, raise_on_error=False)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        q, st = mesh.solve(grad_tol=0.0, max_iters=args.steps, iters_per_sync=32, raise_on_error=False)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        iters = max(1, st["iters"])
-        prof = mesh.profile_kernels(reps=args.profile_reps)
-        lines[prec] = dict(mesh=mesh, info=info, st=st, dt=dt, iters=iters, prof=prof, setup_s=setup_s,
-                           q=q.cpu().numpy())
-        print(f"[bench] {prec}: {iters} iterations in {dt*1e3:.1f} ms ({dt/iters*1e3:.3f} ms/iter), "
-              f"|g| {st['grad_norm']:.3e}, setup {setup_s:.1f} s", file=sys.stderr, flush=True)
+        lines[prec] = timed_line(p, prec, args, "hinge_limb_40x40x160")
     main = lines.get("fp64") or lines[args.precision]
     m, n = p.n_tets, p.n_vertices
     nnz = main["info"]["factor_nnz"]
-    # roofline of the dominant kernel by time
-    prof = main["prof"]
-    dom = max((k for k in prof if algorithmic_bytes(k, m, n, nnz) is not None or k == "gram"),
-              key=lambda k: prof[k])
-    if dom == "gram":
-        flops = GRAM_FLOPS_PER_ELEMENT * m
-        ach = flops / (prof[dom] * 1e-3) / 1e12
-        roof = dict(bound="alu", kernel=dom, achieved=ach, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=ach / FP64_PEAK_TFLOPS, traffic=measured_traffic(dom), ms=prof[dom])
-    else:
-        b = algorithmic_bytes(dom, m, n, nnz)
-        ach = b / (prof[dom] * 1e-3) / 1e9
-        roof = dict(bound="hbm", kernel=dom, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=ach / HBM_PEAK_GBS, traffic=measured_traffic(dom), ms=prof[dom])
     value = m * main["iters"] / main["dt"]
     out = {
         "metric": "element-iterations/s",
@@ -135,79 +178,82 @@ def run(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "heterogeneous_limb_20x20x80", "tets": m, "vertices": n,
+        "config": {"workload": "hinge_limb_40x40x160", "tets": m, "vertices": n,
                    "free_vertices": main["info"]["n_free"], "modes": main["info"]["n_modes"],
-                   "alpha_hat": 10.0, "factor_nnz": nnz, "supernodes": main["info"]["n_supernodes"],
-                   "levels": main["info"]["n_levels"], "activation": float(p.activation[0])},
-        "roofline": roof,
-        "kernel_ms": prof,
+                   "alpha_hat": 10.0, "acap_weights": "volume", "factor_nnz": nnz,
+                   "supernodes": main["info"]["n_supernodes"], "levels": main["info"]["n_levels"],
+                   "groups": 4, "activation": [float(x) for x in p.activation],
+                   "iters_per_sync": args.iters_per_sync, "setup_s": main["setup_s"]},
+        "roofline": roofline(main["prof"], m, n, nnz),
+        "kernel_ms": main["prof"],
+        "phase_ms_per_iter": main["phases"],
     }
     if "mixed" in lines and "fp64" in lines:
         mx = lines["mixed"]
-        # position error of the mixed path against the FP64 path after the same
-        # number of iterations from the same start (relative to the displacement)
         q64, qmx = lines["fp64"]["q"], mx["q"]
         disp = np.abs(q64 - p.rest_xyz).max()
         out["mixed"] = {"value": m * mx["iters"] / mx["dt"], "ms_per_step": mx["dt"] / mx["iters"] * 1e3,
                         "dtype": "f32 element / f64 operator", "kernel_ms": mx["prof"],
-                        "position_err_vs_fp64": float(np.abs(qmx - q64).max() / disp) if disp > 0 else None}
-    # frame solves of the activation ramp (warm-started), latency percentiles
+                        "phase_ms_per_iter": mx["phases"],
+                        "roofline": roofline(mx["prof"], m, n, nnz, mixed=True),
+                        "position_diff_vs_fp64_after_same_iterations":
+                            float(np.abs(qmx - q64).max() / disp) if disp > 0 else None}
+    # converged frame solves of the hinge limb (seeded activations per frame,
+    # each warm-started from the previous frame's equilibrium)
+    last_q = {}
     if args.frames > 0:
-        mesh = main["mesh"]
-        lat = []
-        conv = 0
-        tot_it = 0
-        mesh.solve(grad_tol=0.0, max_iters=0, warm_start=0, raise_on_error=False)
-        t_all = time.perf_counter()
-        for f in range(args.frames):
-            mesh.set_activation(ramp[f])
-            t0 = time.perf_counter()
-            _, st = mesh.solve(grad_tol=args.frame_tol, max_iters=args.frame_max_iters, raise_on_error=False)
-            torch.cuda.synchronize()
-            lat.append((time.perf_counter() - t0) * 1e3)
-            conv += st["status"] == 0
-            tot_it += st["iters"]
-        t_all = time.perf_counter() - t_all
-        out["frames"] = {"count": args.frames, "converged": conv, "grad_tol": args.frame_tol,
-                         "max_iters_per_frame": args.frame_max_iters, "iterations": tot_it,
-                         "solves_per_s": args.frames / t_all,
-                         "latency_ms_p50": float(np.percentile(lat, 50)),
-                         "latency_ms_p99": float(np.percentile(lat, 99))}
+        for prec, ln in lines.items():
+            mesh = ln["mesh"]
+            mesh.set_activation(acts[0])
+            _, st0 = mesh.solve(grad_tol=args.frame_tol, max_iters=args.frame_max_iters, warm_start=0,
+                                raise_on_error=False)
+            kq = []
+            fr = frame_solves(mesh, acts[1:args.frames + 1], args.frame_tol, args.frame_max_iters, keep_q=kq)
+            if fr["converged"] == fr["count"] and kq:
+                last_q[prec] = kq[0]
+            fr["first_frame_from_rest"] = {"status": st0["status"], "iters": st0["iters"],
+                                           "ms": st0["ms_total"]}
+            key = "frames" if prec == "fp64" else "frames_mixed"
+            out[key] = fr
+            print(f"[bench] hinge frames {prec}: {fr['converged']}/{fr['count']} converged, "
+                  f"{fr['iterations']} iterations, {fr['wall_s']:.1f} s", file=sys.stderr, flush=True)
+    if "fp64" in last_q and "mixed" in last_q:
+        # form (1): position error of the converged mixed frames against the
+        # converged FP64 frames (same activations), relative to the displacement
+        d = np.abs(last_q["fp64"] - p.rest_xyz).max()
+        out["mixed"]["converged_position_err_vs_fp64"] = float(np.abs(last_q["mixed"] - last_q["fp64"]).max() / d)
+    for ln in lines.values():
+        ln["mesh"].close()
+    if args.limb:
+        out["heterogeneous_limb_20x20x80"] = limb_leg(args)
     if args.serve > 0:
         out["serving"] = serving(args)
     if args.alpha_search:
         out["alpha_search"] = alpha_search_leg()
-    if args.large:
-        out["largest_configuration"] = large_leg(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args)
     return out
 
 
-def large_leg(args):
-    """The largest configuration on one GPU: hinge limb 40x40x160 (1.536M
-    tets, four muscle groups at their first-frame activations); host setup
-    time, then the same timed iteration as the main line."""
-    import torch
+def limb_leg(args):
+    """The 192k-tet heterogeneous limb: timed iterations (FP64 and mixed) and
+    its 20-frame activation ramp a = t/20, each frame warm-started from the
+    previous equilibrium, to |g| <= frame_tol."""
     from paper_2006_08821_amd import workloads as wl
-    from paper_2006_08821_amd.emu import Mesh
-    p = wl.hinge_limb(40, 40, 160, frames=1)[0]
-    t0 = time.time()
-    mesh = Mesh(p)
-    setup_s = time.time() - t0
-    info = mesh.info()
-    mesh.solve(grad_tol=0.0, max_iters=10, raise_on_error=False)
-    torch.cuda.synchronize()
-    steps = 50
-    t0 = time.perf_counter()
-    _, st = mesh.solve(grad_tol=0.0, max_iters=steps, iters_per_sync=32, raise_on_error=False)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    it = max(1, st["iters"])
-    return {"workload": "hinge limb 40x40x160", "tets": p.n_tets, "vertices": p.n_vertices,
-            "factor_nnz": info["factor_nnz"], "levels": info["n_levels"], "setup_s": setup_s,
-            "device_mb": info["device_bytes"] / 1e6, "iterations": it, "ms_per_step": 1e3 * dt / it,
-            "element_iterations_per_s": p.n_tets * it / dt}
+    p, ramp = wl.heterogeneous_limb_ramp()
+    p.activation = ramp[0].copy()
+    out = {"workload": "heterogeneous limb 20x20x80 (192,000 tets), one group, 20-step ramp"}
+    for prec in ("fp64", "mixed"):
+        ln = timed_line(p, prec, args, "heterogeneous_limb_20x20x80")
+        ln["mesh"].solve(grad_tol=0.0, max_iters=0, warm_start=0, raise_on_error=False)
+        fr = frame_solves(ln["mesh"], ramp, args.frame_tol, args.frame_max_iters)
+        out[prec] = {"element_iterations_per_s": p.n_tets * ln["iters"] / ln["dt"],
+                     "ms_per_step": ln["dt"] / ln["iters"] * 1e3, "kernel_ms": ln["prof"],
+                     "phase_ms_per_iter": ln["phases"], "ramp": fr}
+        print(f"[bench] limb ramp {prec}: {fr['converged']}/{fr['count']} converged, {fr['iterations']} iterations, "
+              f"{fr['wall_s']:.1f} s", file=sys.stderr, flush=True)
+        ln["mesh"].close()
+    return out
 
 
 def alpha_search_leg():
@@ -240,8 +286,7 @@ def serving(args):
     Poisson trace (200 req/s, 2k-300k tets log-uniform, 4 groups, random pin
     pattern) submitted in real time to the continuous-batching server, then the
     same requests solved one mesh at a time (create, solve, destroy) in arrival
-    order.  Both at the same accuracy (|g| <= serve_rtol |g_0|, at most
-    serve_max_iters iterations, cold start)."""
+    order.  Both to the same accuracy: |g| <= serve_tol from rest."""
     import threading
     import torch
     from paper_2006_08821_amd import workloads as wl
@@ -249,7 +294,7 @@ def serving(args):
 
     trace = wl.serving_trace(n_requests=args.serve)
     probs = [wl.serving_problem(r["dims"], r["activation"], r["pin_mode"]) for r in trace]
-    opts = dict(grad_tol=0.0, grad_rtol=args.serve_rtol, max_iters=args.serve_max_iters, warm_start=0)
+    opts = dict(grad_tol=args.serve_tol, max_iters=args.serve_max_iters, warm_start=0)
 
     srv = Server(max_slots=args.serve_slots)
     tickets = [None] * len(probs)
@@ -273,7 +318,8 @@ def serving(args):
     queue = np.array([tm["t_admit"] - tm["t_setup_done"] for _, _, tm in res]) * 1e3
     span = max(tm["t_finish"] for _, _, tm in res) - min(tm["t_submit"] for _, _, tm in res)
     el_it = sum(p.n_tets * st["iters"] for p, (_, st, _) in zip(probs, res))
-    served = {"requests": len(res), "converged": int(sum(st["status"] == 0 for _, st, _ in res)),
+    n_conv = int(sum(st["status"] == 0 for _, st, _ in res))
+    served = {"requests": len(res), "converged": n_conv,
               "requests_per_s": len(res) / span, "element_iterations_per_s": el_it / span,
               "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
               "setup_ms_p50": float(np.percentile(setup, 50)), "setup_ms_p99": float(np.percentile(setup, 99)),
@@ -304,25 +350,45 @@ def serving(args):
              "latency_ms_p50": float(np.percentile(lat1, 50)), "latency_ms_p99": float(np.percentile(lat1, 99))}
     print(f"[bench] plain {len(trace)} requests in {span1:.2f} s", file=sys.stderr, flush=True)
     return {"workload": f"serving trace, first {len(trace)} requests (Poisson 200/s, 2k-300k tets)",
-            "grad_rtol": args.serve_rtol, "max_iters": args.serve_max_iters,
+            "grad_tol": args.serve_tol, "max_iters": args.serve_max_iters,
             "served": served, "plain_one_at_a_time": plain}
 
 
 def cpu_baseline(p, args):
-    """The FP64 oracle (NumPy/SciPy) timed on this host on a bounded sample: one
-    quasi-Newton iteration of the same workload (setup excluded)."""
+    """The FP64 oracle (NumPy/SciPy, as it stands) timed on this host on a
+    bounded sample of the headline workload: one quasi-Newton iteration (fresh
+    ACAP solve per Armijo trial, as Algorithm 1 does) on the bottom slab of the
+    hinge limb, its tets with centroid below z = 20 cube edges (a 40x40x20
+    sub-mesh of the same generator: 192,000 tets, bone core, tendon cap,
+    helical fibers, the z = 0 face pinned), oracle setup (factor, modes)
+    excluded.  Run once on one core and once with every BLAS thread the host
+    offers (NumPy's element-wise work is single-threaded either way)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import emu as oemu
     from oracle import mesh as omesh
-    M = omesh.build(p)
+    from paper_2006_08821_amd import workloads as wl
+    sub = wl.sub_problem(p, z_max=20 * wl.H_EDGE)
     t0 = time.perf_counter()
-    o = oemu.solve(M, p.activation, max_iters=args.cpu_iters, hessian="split")
-    dt = time.perf_counter() - t0
-    it = max(1, o["stats"]["iters"])
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": p.n_tets * it / dt, "unit": "element-iterations/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{it} oracle iteration(s) of the same 192k-tet workload from rest "
-                      f"(fresh ACAP solve per Armijo trial), mesh setup excluded; {dt:.1f} s"}
+    M = omesh.build(sub)
+    setup_s = time.perf_counter() - t0
+    blas = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    runs = {}
+    for label, limit in (("one_core", 1), ("all_cores", blas)):
+        with threadpool_limits(limits=limit):
+            t0 = time.perf_counter()
+            o = oemu.solve(M, sub.activation, max_iters=args.cpu_iters, hessian="split")
+            dt = time.perf_counter() - t0
+        it = max(1, o["stats"]["iters"])
+        runs[label] = dict(value=sub.n_tets * it / dt, seconds=dt, iterations=it, threads=limit)
+        print(f"[bench] oracle {label}: {it} iteration(s) in {dt:.1f} s", file=sys.stderr, flush=True)
+    r1 = runs["one_core"]
+    return {"value": r1["value"], "unit": "element-iterations/s", "cores": 1, "kind": "oracle",
+            "sample": f"{r1['iterations']} oracle iteration(s) on the 40x40x20 bottom slab of the hinge limb "
+                      f"({sub.n_tets} tets), setup ({setup_s:.0f} s) excluded, one core: {r1['seconds']:.1f} s",
+            "all_cores": {"value": runs["all_cores"]["value"], "cores": blas,
+                          "seconds": runs["all_cores"]["seconds"],
+                          "note": "BLAS threads; element-wise NumPy work and SuperLU stay single-threaded"},
+            "host_cpus": os.cpu_count()}
 
 
 def calibrate_copy(mib):
@@ -342,22 +408,23 @@ def calibrate_copy(mib):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=384)
+    ap.add_argument("--warmup", type=int, default=32)
+    ap.add_argument("--iters-per-sync", type=int, default=32)
     ap.add_argument("--precision", default="both", choices=["fp64", "mixed", "both"])
-    ap.add_argument("--frames", type=int, default=20)
-    ap.add_argument("--frame-tol", type=float, default=1e-6)
-    ap.add_argument("--frame-max-iters", type=int, default=400)
+    ap.add_argument("--frames", type=int, default=4, help="converged hinge-limb frames after frame 0")
+    ap.add_argument("--frame-tol", type=float, default=1e-8)
+    ap.add_argument("--frame-max-iters", type=int, default=20000)
+    ap.add_argument("--limb", type=int, default=1, help="run the 192k-tet limb leg (0: skip)")
     ap.add_argument("--profile-reps", type=int, default=20)
     ap.add_argument("--leaf-size", type=int, default=0, help="nested-dissection leaf size (0: library default)")
     ap.add_argument("--cpu-iters", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve", type=int, default=48, help="requests of the serving trace (0: skip)")
-    ap.add_argument("--serve-rtol", type=float, default=1e-4)
-    ap.add_argument("--serve-max-iters", type=int, default=300)
+    ap.add_argument("--serve", type=int, default=24, help="requests of the serving trace (0: skip)")
+    ap.add_argument("--serve-tol", type=float, default=1e-8)
+    ap.add_argument("--serve-max-iters", type=int, default=20000)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--alpha-search", type=int, default=1, help="run the alpha-search leg (0: skip)")
-    ap.add_argument("--large", type=int, default=0, help="run the largest configuration (1.5M tets) too")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (for scaling HBM counters)")
     args = ap.parse_args()

@@ -76,7 +76,10 @@ def prox(M, A, a_el, tol=1e-13, max_iters=100, nu=None):
         return (vol * mat.psi(X, M.mu, M.lhat, a_el, M.kf, M.fiber) + 0.5 * beta * np.einsum("icd,icd->i", D, D)
                 + np.einsum("icd,icd->i", nu, D))
 
-    scale = beta * (1.0 + np.sqrt(np.einsum("icd,icd->i", A, A)))
+    # force scale of each element's stationarity condition: the ACAP term's
+    # and the material's (a stiff element's gradient carries rounding of
+    # vol (mu + lhat) |X|, far above beta |X| when it is not stiffness-weighted)
+    scale = (beta + vol * (M.mu + M.lhat)) * (1.0 + np.sqrt(np.einsum("icd,icd->i", A, A)))
     for _ in range(max_iters):
         g = (vol[:, None, None] * mat.pk1(X, M.mu, M.lhat, a_el, M.kf, M.fiber) + beta[:, None, None] * (X - A)
              - nu)
@@ -84,11 +87,13 @@ def prox(M, A, a_el, tol=1e-13, max_iters=100, nu=None):
         if np.all(gn <= tol * scale):
             break
         H = vol[:, None, None] * mat.hess(X, M.mu, M.lhat, a_el, M.kf, M.fiber) + beta[:, None, None] * np.eye(9)
-        # damped Newton on a (possibly non-convex) element objective: the PSD
-        # part of the Hessian, floored at a tiny multiple of beta so that the
-        # step is always defined (the objective is beta-strongly convex far out)
+        # damped Newton on a (possibly non-convex) element objective: each
+        # eigenvalue of the Hessian replaced by its absolute value (a step
+        # along negative curvature keeps the length a curvature of that size
+        # gives), floored at 1e-12 of the largest so the step is defined
         w, V = np.linalg.eigh(H)
-        w = np.maximum(w, 1e-9 * beta[:, None])
+        w = np.abs(w)
+        w = np.maximum(w, 1e-12 * w.max(axis=1, keepdims=True))
         step = -np.einsum("iab,ib,icb,ic->ia", V, 1.0 / w, V, g.reshape(-1, 9)).reshape(-1, 3, 3)
         f0 = obj(X)
         t = np.ones(M.m)
@@ -110,8 +115,9 @@ def prox(M, A, a_el, tol=1e-13, max_iters=100, nu=None):
     return X, H
 
 
-def moreau_solve(M, a, q0=None, tol=1e-10, max_iters=200, history=False):
-    """O2: Newton on Ehat(q) with backtracking; returns q, the prox F = X* and stats."""
+def moreau_solve(M, a, q0=None, tol=1e-10, max_iters=200, history=False, callback=None):
+    """O2: Newton on Ehat(q), globalized by Levenberg-Marquardt; returns q, the
+    prox F = X* and stats."""
     a_el = msh.activation_per_element(M, a)
     q = M.rest.copy() if q0 is None else q0.copy()
     q[M.pins] = M.pin_xyz
@@ -129,42 +135,50 @@ def moreau_solve(M, a, q0=None, tol=1e-10, max_iters=200, history=False):
 
     E, A, X, H = Ehat(q)
     it = 0
+    lam = 0.0
     while True:
         GA = M.beta[:, None, None] * (A - X)
         grad = _scatter_grad(M, GA)[M.free].reshape(-1)
         gn = float(np.linalg.norm(grad))
         if history:
             hist.append((E, gn))
+        if callback is not None:
+            callback(it, E, gn, lam)
         if gn <= tol or it >= max_iters:
             break
         Hinv = np.linalg.inv(H)
         b2 = M.beta[:, None, None]
         He = b2 * np.eye(9) - b2 ** 2 * Hinv
         He = 0.5 * (He + np.transpose(He, (0, 2, 1)))
-        # Newton step with the exact assembled Hessian of Ehat (each element's
-        # envelope Hessian is indefinite where Psi is, the sum is not near a
-        # minimizer); where that step is not a descent direction, the step of
-        # the per-element PSD parts instead
-        step = None
-        try:
-            K, _ = _assemble(M, He)
-            step = -spla.spsolve(K, grad)
-            if not (np.all(np.isfinite(step)) and float(grad @ step) < 0.0):
+        # Newton step with the exact assembled Hessian K of Ehat, globalized by
+        # Levenberg-Marquardt: (K + lam D) s = -grad with D the diagonal of the
+        # assembly of the per-element PSD parts; lam shrinks after an accepted
+        # step and grows after a rejected or non-descent one, so near the
+        # minimizer the step is exact Newton (each element's envelope Hessian
+        # is indefinite wherever Psi is; the sum is positive definite there)
+        K, _ = _assemble(M, He)
+        Dg = _assemble(M, mat.clamp_psd(He))[0].diagonal()
+        Dg = sp.diags(np.maximum(Dg, 1e-12 * Dg.max()))
+        accepted = False
+        for _try in range(60):
+            try:
+                step = spla.spsolve((K + lam * Dg).tocsc(), -grad) if lam > 0 else spla.spsolve(K, -grad)
+            except RuntimeError:
                 step = None
-        except RuntimeError:
-            step = None
-        if step is None:
-            K, _ = _assemble(M, mat.clamp_psd(He))
-            step = -spla.spsolve(K, grad)
-        t = 1.0
-        gs = float(grad @ step)
-        for _ls in range(60):
+            if step is None or not np.all(np.isfinite(step)) or not float(grad @ step) < 0.0:
+                lam = max(4.0 * lam, 1e-6)
+                continue
+            gs = float(grad @ step)
             qt = q.copy()
-            qt[M.free] += t * step.reshape(-1, 3)
+            qt[M.free] += step.reshape(-1, 3)
             Et, At, Xt, Ht = Ehat(qt)
-            if Et <= E + 1e-4 * t * gs or abs(Et - E) <= 1e-15 * abs(E):
+            if Et <= E + 1e-4 * gs or abs(Et - E) <= 1e-15 * abs(E):
+                accepted = True
+                lam = lam / 8.0 if lam > 1e-9 else 0.0
                 break
-            t *= 0.5
+            lam = max(4.0 * lam, 1e-6)
+        if not accepted:
+            break
         q, E, A, X, H = qt, Et, At, Xt, Ht
         it += 1
     out = dict(q=q, F=X, iters=it, gnorm=gn, energy=E)

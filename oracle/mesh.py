@@ -154,7 +154,12 @@ def compute_modes(M, k):
         w, V = np.linalg.eigh(M.Lff.toarray())
         w, V = w[:k], V[:, :k]
     else:
-        w, V = spla.eigsh(M.Lff, k=k, sigma=0.0, which="LM")
+        # shift-invert about 0 with the factor already held (the same operator
+        # L_ff^{-1} that eigsh would factor again itself)
+        nf3 = M.free.size
+        OPinv = spla.LinearOperator((nf3, nf3), matvec=lambda x: M.lu.solve(np.asarray(x, np.float64)),
+                                    dtype=np.float64)
+        w, V = spla.eigsh(M.Lff, k=k, sigma=0.0, which="LM", OPinv=OPinv)
     order = np.argsort(w)
     M.nu = w[order]
     M.phi = V[:, order].T.copy()

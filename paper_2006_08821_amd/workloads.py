@@ -250,6 +250,25 @@ def hinge_limb(nx: int = 40, ny: int = 40, nz: int = 160, frames: int = 60, seed
     return q, acts
 
 
+def sub_problem(p: Problem, z_max: float) -> Problem:
+    """The tets of ``p`` whose centroid lies below ``z_max`` with their
+    materials, fibers, groups and bone labels, vertices renumbered in order;
+    pins are the kept pinned vertices (targets as in ``p``)."""
+    cz = p.rest_xyz[p.tets].mean(axis=1)[:, 2]
+    keep = np.nonzero(cz < z_max)[0]
+    used = np.unique(p.tets[keep])
+    new = np.full(p.n_vertices, -1, np.int64)
+    new[used] = np.arange(used.size)
+    pin_keep = np.nonzero(new[p.pins] >= 0)[0]
+    return dataclasses.replace(
+        p, name=f"{p.name}_z<{z_max:g}", rest_xyz=p.rest_xyz[used].copy(),
+        tets=new[p.tets[keep]].astype(np.int32), youngs=p.youngs[keep].copy(), poisson=p.poisson[keep].copy(),
+        fiber=p.fiber[keep].copy(), group=p.group[keep].copy(),
+        pins=new[p.pins[pin_keep]].astype(np.int32), pin_xyz=p.pin_xyz[pin_keep].copy(),
+        activation=p.activation.copy(), bone=None if p.bone is None else p.bone[keep].copy(),
+        extra={})
+
+
 def adjoint_case(nx: int = 16, ny: int = 16, nz: int = 64, n_markers: int = 64, seed: int = 0):
     """8-group limb with marker vertices drawn without replacement from the free
     surface vertices, and seeded target activations a* ~ U[0,1]^8."""

@@ -7,7 +7,9 @@ solve).  Converged positions are compared with the relative-to-displacement
 max-norm error e_q = max|q - q_ref| / max|q_ref - Q| at the same gradient
 tolerance: <= 1e-6 for FP64 and <= 1e-4 for the mixed path.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -307,3 +309,31 @@ def test_box_beam_solve_with_external_forces(torch):
     assert st["status"] == 0, st
     ref = ofem.moreau_solve(M, p.activation, tol=1e-11)["q"]
     assert _disp_err(q.cpu().numpy(), ref, M.rest) <= 1e-6
+
+
+def test_largest_configuration_matches_golden(torch):
+    # The hinge limb 40x40x160 (1.536M tets) at a seeded state F (not taken
+    # from the GPU): q*(F), E, |dE/dF| and the quasi-Newton direction against
+    # the oracle's values on sampled vertices and elements, written by
+    # tests/golden/make_hinge_golden.py (oracle and input generator only).
+    # The direction depends on the mode subspace only; the library computes
+    # its own 16 modes, checked against the oracle's eigenvalues.
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hinge40x40x160_state.json")))
+    p = wl.hinge_limb(40, 40, 160, frames=1)[0]
+    rng = np.random.default_rng(gold["state"]["seed"])
+    F = np.eye(3) + gold["state"]["amp"] * rng.normal(size=(p.n_tets, 3, 3))
+    print("hinge 40x40x160 seeded-state evaluate", flush=True)
+    mesh = _mesh(p)
+    nu, _ = mesh.get_modes()
+    assert np.allclose(nu, gold["nu"], rtol=1e-8)
+    ev = mesh.evaluate(F)
+    q = ev["q"].cpu().numpy()
+    d = ev["direction"].cpu().numpy()
+    del mesh
+    vx = np.array(gold["vertices"])
+    el = np.array(gold["elements"])
+    assert np.abs(q[vx] - np.array(gold["q"])).max() <= 1e-11 * gold["q_max"]
+    assert math.isclose(ev["energy"], gold["energy"], rel_tol=1e-11)
+    assert math.isclose(ev["grad_norm"], gold["grad_norm"], rel_tol=1e-10)
+    dd = d[el].reshape(-1, 9)
+    assert np.abs(dd - np.array(gold["direction"])).max() <= 1e-6 * gold["dir_max"]
