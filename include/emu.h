@@ -66,6 +66,16 @@ enum { EMU_WEIGHT_STIFFNESS = 0, EMU_WEIGHT_VOLUME = 1, EMU_WEIGHT_PAPER = 2 };
    free receives exactly the pointers alloc returned, after the mesh's stream
    has drained.  Used to draw mesh memory from a caller's pool (e.g. torch's
    caching allocator). */
+/* Element blocks of the approximate Hessian (Sec. 3.2.1: block diagonal in
+   the per-tet deformation gradients, made positive definite, plus alpha W).
+   SPLIT: in the frame of each tet's rotation (dF = R dX) the blocks of the
+   symmetric (6x6) and skew (3x3) parts of dX, each clamped to its positive
+   semi-definite part; the coupling of the two parts by the fiber term is
+   dropped.  COUPLED: the full 9x9 block: the isotropic term clamped per part
+   (it has no coupling) plus the whole fiber term, a convex quadratic, so the
+   block equals the exact element Hessian wherever no clamp is active. */
+enum { EMU_BLOCKS_SPLIT = 0, EMU_BLOCKS_COUPLED = 1 };
+
 typedef void* (*emu_dev_alloc_fn)(size_t bytes, void* ctx);
 typedef void (*emu_dev_free_fn)(void* ptr, void* ctx);
 
@@ -99,6 +109,10 @@ typedef struct {
   int32_t leaf_size;         /* nested-dissection leaf size; 0 -> 64              */
   const int32_t *bone;       /* [m] bone id (>= 0) or -1; NULL = no bone tets.
                                 Read by weight_mode EMU_WEIGHT_PAPER             */
+  int32_t hessian_blocks;    /* element blocks of the quasi-Newton Hessian
+                                (Sec. 3.2.1, eq. not-yet): EMU_BLOCKS_SPLIT, or
+                                EMU_BLOCKS_COUPLED for the full 9x9 block per
+                                tet (not supported by the serving loop)          */
   emu_dev_alloc_fn dev_alloc;  /* NULL -> hipMalloc / hipFree.  Both or neither;  */
   emu_dev_free_fn dev_free;    /* the serving loop ignores them (it accounts its  */
   void *alloc_ctx;             /* own HBM budget).  Passed back to both calls.    */

@@ -16,7 +16,10 @@ design notes list):
 2. Block Hessian H_i = clamp(vol_i d2Psi(F_i)) + beta_i I_9 (eq. not-yet with the
    definiteness fix), or -- with ``hessian="split"`` -- the block-diagonal part
    of it in the rotated frame dF = R_i dX (6x6 symmetric dX, 3x3 skew dX, each
-   clamped), which is the block structure the GPU library factors.
+   clamped), the GPU library's default block structure; or -- with
+   ``hessian="coupled"`` -- the full 9x9 block with the fix applied to the
+   isotropic term only (clamped per rotated-frame block) and the convex fiber
+   term kept whole, the library's 9x9 option.
 3. Low-rank correction (eq. low-rank, eq. Hessian-woodbury):
    B_i[(c,j),(c',e)] = w_i delta_cc' grad_i(phi_j)[e], y = sum B_i H_i^{-1} g_i,
    C = Lambda - alpha sum B_i H_i^{-1} B_i^T, z = C^{-1} y,
@@ -85,6 +88,19 @@ def block_hessian(M, F, a_el, hessian="full"):
         Hb[:, :6, :6] = mat.clamp_psd(HY[:, :6, :6])
         Hb[:, 6:, 6:] = mat.clamp_psd(HY[:, 6:, 6:])
         Hc = np.einsum("iab,ibc,idc->iad", T, Hb, T)
+    elif hessian == "coupled":
+        # the full 9x9 block with the definiteness fix on the term that needs
+        # it: the isotropic Hessian (block diagonal in the rotated frame, each
+        # block clamped) plus the fiber Hessian, a convex quadratic's (PSD)
+        zero = np.zeros(M.m)
+        Hiso = M.vol[:, None, None] * mat.hess(F, M.mu, M.lhat, zero, M.kf, M.fiber)
+        Hfib = M.vol[:, None, None] * mat.hess(F, zero, zero, a_el, M.kf, M.fiber)
+        T = frame_basis(mat.polar_rotation(F))
+        HY = np.einsum("iab,ibc,icd->iad", np.transpose(T, (0, 2, 1)), Hiso, T)
+        Hb = np.zeros_like(HY)
+        Hb[:, :6, :6] = mat.clamp_psd(HY[:, :6, :6])
+        Hb[:, 6:, 6:] = mat.clamp_psd(HY[:, 6:, 6:])
+        Hc = np.einsum("iab,ibc,idc->iad", T, Hb, T) + Hfib
     else:
         raise ValueError(hessian)
     return Hc + M.beta[:, None, None] * np.eye(9)

@@ -102,6 +102,7 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
   // partial sums for the reduction that follows)
   d.nbg = std::max(1, std::min((m + 63) / 64, 512));
   d.mixed = hm.precision == EMU_PRECISION_MIXED;
+  d.coupled = hm.hessian_blocks == EMU_BLOCKS_COUPLED;
   d.alpha = hm.alpha;
   d.kf = hm.kf;
 
@@ -134,7 +135,7 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
   B.reserve(SLOT(R), 72 * (size_t)m);
   B.reserve(SLOT(S), 48 * (size_t)m);
   B.reserve(SLOT(gbar), 9 * (size_t)m * tsz);
-  B.reserve(SLOT(Lf), 27 * (size_t)m * tsz);
+  B.reserve(SLOT(Lf), (d.coupled ? 33 : 27) * (size_t)m * tsz);
   B.put(SLOT(p), std::vector<double>(9 * (size_t)m, 0.0));
   B.reserve(SLOT(contrib), 96 * (size_t)m);
   {

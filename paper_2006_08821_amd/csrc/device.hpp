@@ -60,6 +60,8 @@ struct DevMesh {
   int32_t nbg;         // workgroups of the Woodbury Gram pass
   int32_t mixed;       // FP32 element Hessian / Gram / direction
   int32_t has_ext;     // external vertex forces set (vext nonzero)
+  int32_t coupled;     // 9x9 element blocks with the fiber coupling (else 6x6 + 3x3)
+  int32_t pad_c;
   double alpha, kf;
 
   // elements, internal order, structure of arrays
@@ -74,7 +76,8 @@ struct DevMesh {
   double* R;              // [9][m]
   double* S;              // [6][m]
   void* gbar;             // [9][m]  (double or float)
-  void* Lf;               // [27][m] Cholesky of the 6x6 and 3x3 blocks (packed)
+  void* Lf;               // [27][m] Cholesky of the 6x6 and 3x3 blocks (packed);
+                          // coupled: [33][m], + the factor of K (kernels.hip)
   double* p;              // [9][m]  step in the rotated (sym, skew) basis
   double* contrib;        // [m][12] ACAP right-hand-side contributions
 

@@ -122,6 +122,7 @@ static void validate(const emu_mesh_desc& d) {
   if ((d.dev_alloc == nullptr) != (d.dev_free == nullptr))
     fail(EMU_E_INVALID, "dev_alloc and dev_free must be given together");
   if (d.precision != 0 && d.precision != 1) fail(EMU_E_INVALID, "precision must be 0 or 1");
+  if (d.hessian_blocks != 0 && d.hessian_blocks != 1) fail(EMU_E_INVALID, "hessian_blocks must be 0 or 1");
   if (d.leaf_size < 0) fail(EMU_E_INVALID, "leaf_size must be >= 0");
 }
 
@@ -209,6 +210,7 @@ static void geometry(const emu_mesh_desc& d, HostMesh& hm) {
     hm.w[i] = stiff ? hm.vol[i] * hm.mu[i] / hm.mu_ref : hm.vol[i];
   }
   hm.precision = d.precision;
+  hm.hessian_blocks = d.hessian_blocks;
   hm.leaf_size = d.leaf_size > 0 ? d.leaf_size : 64;
   hm.k1 = (d.n_modes < 0 ? 48 : d.n_modes) / 3;
   hm.k1_default = d.n_modes < 0;

@@ -700,6 +700,135 @@ DEV int clamp_add_factor(T (&A)[N][N], T beta, T* L) {
   return clamped;
 }
 
+// Coupled 9x9 blocks (the mesh option hessian_blocks = 1).  In the rotated
+// frame dF = R dX the isotropic part of the element Hessian is block diagonal
+// (6x6 symmetric, 3x3 skew); it is clamped and factored per block exactly as in
+// the split form (D).  The fiber term a k_f |F u|^2 = a k_f |X u|^2 is a convex
+// quadratic whose Hessian 2 a k_f vol (I (x) u u^T) is positive semi-definite
+// of rank 3: V V^T, with column c of V the y-coordinates of sqrt(2 a k_f vol)
+// e_c u^T.  The block H = D + V V^T keeps the fiber's coupling of the
+// symmetric and skew parts, and
+//   H^{-1} = D^{-1} - D^{-1} V K^{-1} V^T D^{-1},  K = I + V^T D^{-1} V (3x3),
+// so only the Cholesky factor of K (6 values) is stored after D's 27.
+constexpr int kLfSplit = 27;
+constexpr int kLfCoupled = 33;
+
+template <typename T>
+DEV void fiber_cols(const T* u, T s, T (&V)[9][3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    T M[9], y[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) M[k] = T(0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) M[3 * c + j] = s * u[j];
+    to_y<T, T>(M, y);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) V[k][c] = y[k];
+  }
+}
+// sqrt(2 a k_f vol) of element i (0 for passive tets or zero activation).
+DEV double fiber_scale(const DevMesh& d, int i) {
+  const int g = d.grp[i];
+  const double a = g >= 0 ? d.act[g] : 0.0;
+  return a > 0.0 ? sqrt(2.0 * a * d.kf * d.vol[i]) : 0.0;
+}
+template <typename T>
+DEV void fiber_V(const DevMesh& d, int i, T (&V)[9][3]) {
+  const int m = d.m;
+  const T u[3] = {(T)d.fib[i], (T)d.fib[m + i], (T)d.fib[2 * m + i]};
+  fiber_cols<T>(u, (T)fiber_scale(d, i), V);
+}
+// x <- D^{-1} x with the split factors
+template <typename T>
+DEV void split_solve(const T* Ls, const T* Lk, T* x) {
+  chol_solve<T, 6>(Ls, x);
+  chol_solve<T, 3>(Lk, x + 6);
+}
+// x <- H^{-1} x: the split solve, then (coupled form) the rank-3 correction
+template <typename T, bool kC>
+DEV void hinv_apply(const DevMesh& d, int i, const T* Ls, const T* Lk, T* x) {
+  split_solve<T>(Ls, Lk, x);
+  if constexpr (kC) {
+    const T* Lf = (const T*)d.Lf;
+    const int m = d.m;
+    T V[9][3], Kf[6];
+    fiber_V<T>(d, i, V);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Kf[k] = Lf[(kLfSplit + k) * m + i];
+    T t[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T v = 0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) v += V[k][c] * x[k];
+      t[c] = v;
+    }
+    chol_solve<T, 3>(Kf, t);
+    T w[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w[k] = V[k][0] * t[0] + V[k][1] * t[1] + V[k][2] * t[2];
+    split_solve<T>(Ls, Lk, w);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) x[k] -= w[k];
+  }
+}
+// Coupled form, after the split factors of element i are stored and gbar
+// holds D^{-1} g: form and store the factor of K, and finish gbar = H^{-1} g.
+template <typename T>
+DEV void coupled_finish(const DevMesh& d, int i) {
+  const int m = d.m;
+  T* Lf = (T*)d.Lf;
+  T* gbar = (T*)d.gbar;
+  T Kf[6] = {T(1), T(0), T(1), T(0), T(0), T(1)};
+  if (fiber_scale(d, i) > 0.0) {
+    T Ls[21], Lk[6], V[9][3], W[9][3];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) Ls[k] = Lf[k * m + i];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Lk[k] = Lf[(21 + k) * m + i];
+    fiber_V<T>(d, i, V);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T col[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) col[k] = V[k][c];
+      split_solve<T>(Ls, Lk, col);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) W[k][c] = col[k];
+    }
+    T K[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        T v = a == b ? T(1) : T(0);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) v += V[k][a] * W[k][b];
+        K[a][b] = v;
+      }
+    K[0][1] = K[1][0] = T(0.5) * (K[0][1] + K[1][0]);
+    K[0][2] = K[2][0] = T(0.5) * (K[0][2] + K[2][0]);
+    K[1][2] = K[2][1] = T(0.5) * (K[1][2] + K[2][1]);
+    chol_packed<T, 3>(K, Kf);  // K >= I: positive definite
+    T g[9], t[3];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) g[k] = gbar[k * m + i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T v = 0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) v += V[k][c] * g[k];
+      t[c] = v;
+    }
+    chol_solve<T, 3>(Kf, t);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) gbar[k * m + i] = g[k] - (W[k][0] * t[0] + W[k][1] * t[1] + W[k][2] * t[2]);
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) Lf[(kLfSplit + k) * m + i] = Kf[k];
+}
+
 // ------------------------------------------------------------------ element data access
 struct Elem {
   int32_t v[4];
@@ -1234,7 +1363,7 @@ DEV void b_element(const DevMesh& d, int bid) {
 // clamped blocks + beta I in the rotated basis (precision T), their Cholesky
 // factors, and gbar = H^{-1} g (g read from gbar, overwritten in place).
 template <typename T>
-DEV void hess_blocks(const DevMesh& d, int i, T (&Hs)[6][6], T (&Hk)[3][3]) {
+DEV void hess_blocks(const DevMesh& d, int i, T (&Hs)[6][6], T (&Hk)[3][3], bool fiber = true) {
   const int m = d.m;
   double S[9];
   load_S(d, i, S);
@@ -1243,7 +1372,7 @@ DEV void hess_blocks(const DevMesh& d, int i, T (&Hs)[6][6], T (&Hk)[3][3]) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) u[c] = d.fib[c * m + i];
   const int g = d.grp[i];
-  const double afk = (g >= 0 ? d.act[g] : 0.0) * d.kf;
+  const double afk = fiber ? (g >= 0 ? d.act[g] : 0.0) * d.kf : 0.0;
   const double J = det3(S);
   double C[9];
   cof3<double>(S, C);
@@ -1274,7 +1403,7 @@ DEV void hess_blocks(const DevMesh& d, int i, T (&Hs)[6][6], T (&Hk)[3][3]) {
 // definite (rare) is parked, lower triangle, in its factor's place and
 // finished by thread 0 after the round with an LDS-resident Jacobi, so that
 // the eigen-decomposition holds no registers in the main loop.
-template <typename T>
+template <typename T, bool kC = false>
 DEV void b_element_hess(const DevMesh& d, int bid) {
   const int lb = xcd_block(bid, d.nb);
   {
@@ -1295,7 +1424,7 @@ DEV void b_element_hess(const DevMesh& d, int bid) {
     const int i = base + threadIdx.x;
     if (i < m) {
       T Hs[6][6], Hk[3][3];
-      hess_blocks<T>(d, i, Hs, Hk);
+      hess_blocks<T>(d, i, Hs, Hk, !kC);
       const T beta = (T)(d.alpha * d.w[i]);
       {
         T Ls[21];
@@ -1350,6 +1479,10 @@ DEV void b_element_hess(const DevMesh& d, int bid) {
         ++nclamp;
       }
     }
+    if constexpr (kC) {
+      __syncthreads();
+      if (i < m) coupled_finish<T>(d, i);
+    }
     // nfix and fix are reused by the next round
     __syncthreads();
   }
@@ -1358,8 +1491,8 @@ DEV void b_element_hess(const DevMesh& d, int bid) {
 }
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_element(DevMesh d) { b_element<T>(d, blockIdx.x); }
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_element_hess(DevMesh d) { b_element_hess<T>(d, blockIdx.x); }
+template <typename T, bool kC = false>
+__global__ void __launch_bounds__(kBlock) k_element_hess(DevMesh d) { b_element_hess<T, kC>(d, blockIdx.x); }
 
 // --------------------------------------------------------------- Woodbury Gram
 // Per element: Z = T H^{-1} T^T (9x9, F coordinates; T = (R (x) I) Y) and the
@@ -1400,7 +1533,7 @@ struct MfmaAcc<float> {
 // for the pairs p = (0,0) (0,1) (0,2) (1,1) (1,2) (2,2).  The lane computes
 // the entries whose first F coordinate is c (c = 0, 1, 2: three lanes per
 // element share the work; c = 3 computes and stores nothing useful).
-template <typename T>
+template <typename T, bool kC = false>
 DEV void gram_zblocks(const DevMesh& d, int i, int c, T* zr) {
   const int m = d.m;
   T R[9];
@@ -1453,6 +1586,52 @@ DEV void gram_zblocks(const DevMesh& d, int i, int c, T* zr) {
         Hk[r * (r + 1) / 2 + c] = v;
       }
   }
+  // coupled form: the full inverse blockdiag(D^{-1}) - W K^{-1} W^T in the
+  // rotated (y) coordinates, packed lower, W = D^{-1} V
+  [[maybe_unused]] T Hf[kC ? 45 : 1];
+  if constexpr (kC) {
+    T V[9][3], W[9][3];
+    fiber_V<T>(d, i, V);
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        T v = 0;
+#pragma unroll
+        for (int b = 0; b < 9; ++b) {
+          if ((a < 6) != (b < 6)) continue;
+          T h;
+          if (a < 6) h = Hs[(a > b ? a : b) * ((a > b ? a : b) + 1) / 2 + (a > b ? b : a)];
+          else h = Hk[(a > b ? a - 6 : b - 6) * ((a > b ? a - 6 : b - 6) + 1) / 2 + (a > b ? b - 6 : a - 6)];
+          v += h * V[b][cc];
+        }
+        W[a][cc] = v;
+      }
+    // K^{-1} from its stored factor
+    T Kf[6], Ki[3][3];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Kf[k] = Lf[(kLfSplit + k) * m + i];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      T e[3] = {T(cc == 0), T(cc == 1), T(cc == 2)};
+      chol_solve<T, 3>(Kf, e);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) Ki[r][cc] = e[r];
+    }
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      T u0 = W[a][0] * Ki[0][0] + W[a][1] * Ki[1][0] + W[a][2] * Ki[2][0];
+      T u1 = W[a][0] * Ki[0][1] + W[a][1] * Ki[1][1] + W[a][2] * Ki[2][1];
+      T u2 = W[a][0] * Ki[0][2] + W[a][1] * Ki[1][2] + W[a][2] * Ki[2][2];
+#pragma unroll
+      for (int b = 0; b <= a; ++b) {
+        T h = T(0);
+        if (a < 6 && b < 6) h = Hs[a * (a + 1) / 2 + b];
+        else if (a >= 6 && b >= 6) h = Hk[(a - 6) * (a - 5) / 2 + (b - 6)];
+        Hf[a * (a + 1) / 2 + b] = h - (u0 * W[b][0] + u1 * W[b][1] + u2 * W[b][2]);
+      }
+    }
+  }
   // per gradient-direction pair (dd <= dp): M[e][e'] = (Y H^{-1} Y^T)[(e,dd),(e',dp)],
   // then Z[(c,dd),(c',dp)] = (R M R^T)[c][c'], stored in the block of (min, max)(c, c')
   const int cr = c < 2 ? c : 2;
@@ -1474,6 +1653,13 @@ DEV void gram_zblocks(const DevMesh& d, int i, int c, T* zr) {
 #pragma unroll
             for (int pb = 0; pb < 2; ++pb) {
               const int ya = kYof[A][pa], yb = kYof[B][pb];
+              if constexpr (kC) {
+                if (ya >= 0 && yb >= 0) {
+                  const int lo = ya < yb ? ya : yb, hi = ya < yb ? yb : ya;
+                  v += T(kYvf[A][pa] * kYvf[B][pb]) * Hf[hi * (hi + 1) / 2 + lo];
+                }
+                continue;
+              }
               if (ya >= 0 && yb >= 0 && (ya < 6) == (yb < 6)) {
                 const T cv = T(kYvf[A][pa] * kYvf[B][pb]);
                 if (ya < 6) {
@@ -1508,7 +1694,7 @@ DEV void gram_zblocks(const DevMesh& d, int i, int c, T* zr) {
     }
 }
 
-template <typename T>
+template <typename T, bool kC = false>
 DEV void b_gram(const DevMesh& d, int bid) {
   if (d.ctl->done) return;
   typedef typename MfmaAcc<T>::v4 v4;
@@ -1543,7 +1729,7 @@ DEV void b_gram(const DevMesh& d, int bid) {
       const int el = lane >> 2, sl = lane & 3, q4 = 4 * sl;
       if (el < ne) {
         const int i = base + el;
-        gram_zblocks<T>(d, i, sl, zw[el]);
+        gram_zblocks<T, kC>(d, i, sl, zw[el]);
         if (sl < 3) {
           const T* gbar = (const T*)d.gbar;
           double gbd[9], D[9];
@@ -1658,8 +1844,8 @@ DEV void b_gram(const DevMesh& d, int bid) {
     }
   }
 }
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_gram(DevMesh d) { b_gram<T>(d, blockIdx.x); }
+template <typename T, bool kC = false>
+__global__ void __launch_bounds__(kBlock) k_gram(DevMesh d) { b_gram<T, kC>(d, blockIdx.x); }
 
 // Partial Gram sums: 16 threads per entry sum interleaved workgroup partials,
 // then add their results in a fixed order.
@@ -1942,7 +2128,7 @@ __global__ void __launch_bounds__(kBlock) k_uz(DevMesh d) { b_uz(d, blockIdx.x);
 
 // Direction: d = gbar + alpha H^{-1} B^T z with B^T z = w Y^T vec(R^T G uz);
 // p = -d; g.p = (L^T gbar).(L^T p) per block; contributions of dF = R D(p).
-template <typename T>
+template <typename T, bool kC = false>
 DEV void b_direction(const DevMesh& d, int bid) {
   {
     const int i0 = xcd_block(bid, d.nb) * kBlock + threadIdx.x;
@@ -1972,8 +2158,7 @@ DEV void b_direction(const DevMesh& d, int bid) {
       gb[k] = gbar[k * m + i];
       ty[k] *= (T)e.w;
     }
-    chol_solve<T, 6>(Ls, ty);
-    chol_solve<T, 3>(Lk, ty + 6);
+    hinv_apply<T, kC>(d, i, Ls, Lk, ty);
     double p[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -1991,6 +2176,21 @@ DEV void b_direction(const DevMesh& d, int bid) {
     double gp = 0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) gp += (double)a1[k] * (double)a2[k];
+    if constexpr (kC) {
+      // g = (L L^T + V V^T) gbar: add (V^T gbar) . (V^T p)
+      T V[9][3];
+      fiber_V<T>(d, i, V);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T vg = 0, vp = 0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          vg += V[k][c] * gb[k];
+          vp += V[k][c] * pt[k];
+        }
+        gp += (double)vg * (double)vp;
+      }
+    }
     acc[0] = dd_add_d(acc[0], gp);
     double D[9], dF[9];
     from_y<double>(p, D);
@@ -2003,8 +2203,8 @@ DEV void b_direction(const DevMesh& d, int bid) {
     d.part_ls[2 * kLsTerms * bid + 13] = acc[0].lo;
   }
 }
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_direction(DevMesh d) { b_direction<T>(d, blockIdx.x); }
+template <typename T, bool kC = false>
+__global__ void __launch_bounds__(kBlock) k_direction(DevMesh d) { b_direction<T, kC>(d, blockIdx.x); }
 
 // Line-search polynomial: E(sigma) - E(0) = sum_k c_k sigma^k (k = 1..6), exact
 // per element along F(sigma) = R (S + sigma D), A(sigma) = A + sigma dA.
@@ -2269,7 +2469,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_dir(DevMesh d, double beta, const
 
 // Preconditioner, part 1: rbar = H^{-1} Y^T vec(R^T r) (blocks), stored in d.p,
 // and block partials of y[(c,j)] = sum_i w_i (R D(rbar) gphi_j)[c].
-template <typename T>
+template <typename T, bool kC = false>
 __global__ void __launch_bounds__(kBlock) k_pc1(DevMesh d, const double* r, double* ypart) {
   __shared__ double red[kBlock / 64][48];
   const int m = d.m;
@@ -2292,8 +2492,7 @@ __global__ void __launch_bounds__(kBlock) k_pc1(DevMesh d, const double* r, doub
     for (int k = 0; k < 21; ++k) Ls[k] = Lf[k * m + i];
 #pragma unroll
     for (int k = 0; k < 6; ++k) Lk[k] = Lf[(21 + k) * m + i];
-    chol_solve<T, 6>(Ls, ry);
-    chol_solve<T, 3>(Lk, ry + 6);
+    hinv_apply<T, kC>(d, i, Ls, Lk, ry);
     double rb[9], D[9], RD[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -2383,7 +2582,7 @@ __global__ void __launch_bounds__(64) k_pc_solve(DevMesh d, const double* ypart)
 
 // Preconditioner, part 3: z_i = R D(rbar_i + alpha H^{-1} w Y^T vec(R^T A_i(uz)))
 // (F coordinates); block partials of r . z.
-template <typename T>
+template <typename T, bool kC = false>
 __global__ void __launch_bounds__(kBlock) k_pc2(DevMesh d, const double* r, double* zout, double* part) {
   __shared__ DD sh[kBlock];
   DD acc[1] = {DD{0, 0}};
@@ -2405,8 +2604,7 @@ __global__ void __launch_bounds__(kBlock) k_pc2(DevMesh d, const double* r, doub
     for (int k = 0; k < 6; ++k) Lk[k] = Lf[(21 + k) * m + i];
 #pragma unroll
     for (int k = 0; k < 9; ++k) ty[k] *= (T)e.w;
-    chol_solve<T, 6>(Ls, ty);
-    chol_solve<T, 3>(Lk, ty + 6);
+    hinv_apply<T, kC>(d, i, Ls, Lk, ty);
     double zy[9], D[9], Z[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) zy[k] = d.p[k * m + i] + d.alpha * (double)ty[k];
@@ -2513,6 +2711,32 @@ __global__ void __launch_bounds__(64) kb_gather_ctl(const DevMesh* __restrict__ 
 static inline int blocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 static inline int rhs_blocks(int64_t nf) { return blocks(nf * kRhsLanes); }
 
+// Kernel instance for the mesh's precision and block structure.
+typedef void (*MeshKernel)(DevMesh);
+static MeshKernel pick_hess(const DevMesh& d) {
+  return d.mixed ? (d.coupled ? k_element_hess<float, true> : k_element_hess<float, false>)
+                 : (d.coupled ? k_element_hess<double, true> : k_element_hess<double, false>);
+}
+static MeshKernel pick_gram(const DevMesh& d) {
+  return d.mixed ? (d.coupled ? k_gram<float, true> : k_gram<float, false>)
+                 : (d.coupled ? k_gram<double, true> : k_gram<double, false>);
+}
+static MeshKernel pick_direction(const DevMesh& d) {
+  return d.mixed ? (d.coupled ? k_direction<float, true> : k_direction<float, false>)
+                 : (d.coupled ? k_direction<double, true> : k_direction<double, false>);
+}
+static MeshKernel pick_element(const DevMesh& d) { return d.mixed ? k_element<float> : k_element<double>; }
+typedef void (*Pc1Kernel)(DevMesh, const double*, double*);
+typedef void (*Pc2Kernel)(DevMesh, const double*, double*, double*);
+static Pc1Kernel pick_pc1(const DevMesh& d) {
+  return d.mixed ? (d.coupled ? k_pc1<float, true> : k_pc1<float, false>)
+                 : (d.coupled ? k_pc1<double, true> : k_pc1<double, false>);
+}
+static Pc2Kernel pick_pc2(const DevMesh& d) {
+  return d.mixed ? (d.coupled ? k_pc2<float, true> : k_pc2<float, false>)
+                 : (d.coupled ? k_pc2<double, true> : k_pc2<double, false>);
+}
+
 void launch_init_rest(const DevMesh& d, hipStream_t st) {
   hipLaunchKernelGGL(k_init_rest, dim3(blocks(d.m)), dim3(kBlock), 0, st, d);
 }
@@ -2568,12 +2792,10 @@ void launch_cg_dir(const DevMesh& d, double beta, const double* Z, double* P, hi
   hipLaunchKernelGGL(k_cg_dir, dim3(d.nb), dim3(kBlock), 0, st, d, beta, Z, P);
 }
 void launch_precond(const DevMesh& d, const double* r, double* z, double* ypart, double* part, hipStream_t st) {
-  if (d.mixed) hipLaunchKernelGGL(k_pc1<float>, dim3(d.nb), dim3(kBlock), 0, st, d, r, ypart);
-  else hipLaunchKernelGGL(k_pc1<double>, dim3(d.nb), dim3(kBlock), 0, st, d, r, ypart);
+  hipLaunchKernelGGL(pick_pc1(d), dim3(d.nb), dim3(kBlock), 0, st, d, r, ypart);
   hipLaunchKernelGGL(k_pc_solve, dim3(1), dim3(64), 0, st, d, ypart);
   hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d);
-  if (d.mixed) hipLaunchKernelGGL(k_pc2<float>, dim3(d.nb), dim3(kBlock), 0, st, d, r, z, part);
-  else hipLaunchKernelGGL(k_pc2<double>, dim3(d.nb), dim3(kBlock), 0, st, d, r, z, part);
+  hipLaunchKernelGGL(pick_pc2(d), dim3(d.nb), dim3(kBlock), 0, st, d, r, z, part);
 }
 void launch_adj_da(const DevMesh& d, const double* lam, double* part, hipStream_t st) {
   hipLaunchKernelGGL(k_adj_da, dim3(d.nb), dim3(kBlock), 0, st, d, lam, part);
@@ -2587,22 +2809,13 @@ void launch_set_pins(const DevMesh& d, hipStream_t st) {
 }
 
 void launch_iteration(const DevMesh& d, const SolvePlan& pl, hipStream_t st) {
-  if (d.mixed) {
-    hipLaunchKernelGGL(k_element<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
-    hipLaunchKernelGGL(k_element_hess<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
-    hipLaunchKernelGGL(k_gram<float>, dim3(d.nbg), dim3(kBlock), 0, st, d);
-  } else {
-    hipLaunchKernelGGL(k_element<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
-    hipLaunchKernelGGL(k_element_hess<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
-    hipLaunchKernelGGL(k_gram<double>, dim3(d.nbg), dim3(kBlock), 0, st, d);
-  }
+  hipLaunchKernelGGL(pick_element(d), dim3(d.nb), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(pick_hess(d), dim3(d.nb), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(pick_gram(d), dim3(d.nbg), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_gram_reduce, dim3((kGramEntries + 15) / 16), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_control_a, dim3(1), dim3(kCtlThreads), 0, st, d);
   hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d);
-  if (d.mixed)
-    hipLaunchKernelGGL(k_direction<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
-  else
-    hipLaunchKernelGGL(k_direction<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(pick_direction(d), dim3(d.nb), dim3(kBlock), 0, st, d);
   launch_solve(d, pl, 0, d.dq, 1, st);
   hipLaunchKernelGGL(k_lscoef, dim3(d.nb), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_control_b, dim3(1), dim3(kBlock), 0, st, d);
@@ -2614,23 +2827,14 @@ void launch_iteration(const DevMesh& d, const SolvePlan& pl, hipStream_t st) {
 // ev[4] end.
 void launch_iteration_phased(const DevMesh& d, const SolvePlan& pl, hipStream_t st, hipEvent_t* ev) {
   (void)hipEventRecord(ev[0], st);
-  if (d.mixed) {
-    hipLaunchKernelGGL(k_element<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
-    hipLaunchKernelGGL(k_element_hess<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
-  } else {
-    hipLaunchKernelGGL(k_element<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
-    hipLaunchKernelGGL(k_element_hess<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
-  }
+  hipLaunchKernelGGL(pick_element(d), dim3(d.nb), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(pick_hess(d), dim3(d.nb), dim3(kBlock), 0, st, d);
   (void)hipEventRecord(ev[1], st);
-  if (d.mixed) hipLaunchKernelGGL(k_gram<float>, dim3(d.nbg), dim3(kBlock), 0, st, d);
-  else hipLaunchKernelGGL(k_gram<double>, dim3(d.nbg), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(pick_gram(d), dim3(d.nbg), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_gram_reduce, dim3((kGramEntries + 15) / 16), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_control_a, dim3(1), dim3(kCtlThreads), 0, st, d);
   hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d);
-  if (d.mixed)
-    hipLaunchKernelGGL(k_direction<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
-  else
-    hipLaunchKernelGGL(k_direction<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(pick_direction(d), dim3(d.nb), dim3(kBlock), 0, st, d);
   (void)hipEventRecord(ev[2], st);
   launch_solve(d, pl, 0, d.dq, 1, st);
   (void)hipEventRecord(ev[3], st);
@@ -2643,25 +2847,14 @@ void launch_iteration_phased(const DevMesh& d, const SolvePlan& pl, hipStream_t 
 void launch_class(int k, const DevMesh& d, const SolvePlan& pl, hipStream_t st) {
   switch (k) {
     case 0:
-      if (d.mixed) {
-        hipLaunchKernelGGL(k_element<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
-        hipLaunchKernelGGL(k_element_hess<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
-      } else {
-        hipLaunchKernelGGL(k_element<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
-        hipLaunchKernelGGL(k_element_hess<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
-      }
+      hipLaunchKernelGGL(pick_element(d), dim3(d.nb), dim3(kBlock), 0, st, d);
+      hipLaunchKernelGGL(pick_hess(d), dim3(d.nb), dim3(kBlock), 0, st, d);
       break;
-    case 1:
-      if (d.mixed) hipLaunchKernelGGL(k_gram<float>, dim3(d.nbg), dim3(kBlock), 0, st, d);
-      else hipLaunchKernelGGL(k_gram<double>, dim3(d.nbg), dim3(kBlock), 0, st, d);
-      break;
+    case 1: hipLaunchKernelGGL(pick_gram(d), dim3(d.nbg), dim3(kBlock), 0, st, d); break;
     case 2: hipLaunchKernelGGL(k_gram_reduce, dim3((kGramEntries + 15) / 16), dim3(kBlock), 0, st, d); break;
     case 3: hipLaunchKernelGGL(k_control_a, dim3(1), dim3(kCtlThreads), 0, st, d); break;
     case 4: hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d); break;
-    case 5:
-      if (d.mixed) hipLaunchKernelGGL(k_direction<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
-      else hipLaunchKernelGGL(k_direction<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
-      break;
+    case 5: hipLaunchKernelGGL(pick_direction(d), dim3(d.nb), dim3(kBlock), 0, st, d); break;
     case 6: hipLaunchKernelGGL(k_rhs, dim3(rhs_blocks(d.nf)), dim3(kBlock), 0, st, d, 0, 1); break;
     case 7:
       for (int L = 0; L < pl.nlevels; ++L) {
@@ -2684,22 +2877,13 @@ void launch_class(int k, const DevMesh& d, const SolvePlan& pl, hipStream_t st) 
 
 // evaluation at the current state: element pass, Woodbury system, direction
 void launch_evaluate(const DevMesh& d, hipStream_t st) {
-  if (d.mixed) {
-    hipLaunchKernelGGL(k_element<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
-    hipLaunchKernelGGL(k_element_hess<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
-    hipLaunchKernelGGL(k_gram<float>, dim3(d.nbg), dim3(kBlock), 0, st, d);
-  } else {
-    hipLaunchKernelGGL(k_element<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
-    hipLaunchKernelGGL(k_element_hess<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
-    hipLaunchKernelGGL(k_gram<double>, dim3(d.nbg), dim3(kBlock), 0, st, d);
-  }
+  hipLaunchKernelGGL(pick_element(d), dim3(d.nb), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(pick_hess(d), dim3(d.nb), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(pick_gram(d), dim3(d.nbg), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_gram_reduce, dim3((kGramEntries + 15) / 16), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_control_a, dim3(1), dim3(kCtlThreads), 0, st, d);
   hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d);
-  if (d.mixed)
-    hipLaunchKernelGGL(k_direction<float>, dim3(d.nb), dim3(kBlock), 0, st, d);
-  else
-    hipLaunchKernelGGL(k_direction<double>, dim3(d.nb), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(pick_direction(d), dim3(d.nb), dim3(kBlock), 0, st, d);
 }
 
 static inline void launch_map(void (*k)(const DevMesh*, const int2*), const BatchPlan& b, const BatchClass& c,

@@ -104,6 +104,7 @@ void copy_desc(const emu_mesh_desc& s, DescCopy& c) {
   key_scalar(k, s.n_modes);
   key_scalar(k, s.precision);
   key_scalar(k, s.leaf_size);
+  key_scalar(k, s.hessian_blocks);
   key_append(k, c.rest);
   key_append(k, c.tets);
   key_append(k, c.youngs);
@@ -618,6 +619,8 @@ emu_status emu_server_submit(emu_server* S, const emu_mesh_desc* desc, const dou
   try {
     std::unique_ptr<Request> r(new Request());
     r->times.t_submit = S->now();
+    if (desc->hessian_blocks != EMU_BLOCKS_SPLIT)
+      throw emu::Error{EMU_E_INVALID, "the serving loop runs the split element blocks only"};
     copy_desc(*desc, r->desc);
     if (desc->n_groups < 0) throw emu::Error{EMU_E_INVALID, "negative n_groups"};
     if (desc->n_groups > 0 && !activation) throw emu::Error{EMU_E_INVALID, "NULL activation"};

@@ -19,8 +19,11 @@ PRECISION = {"fp64": 0, "mixed": 1}
 WEIGHT_MODES = {"stiffness": 0, "volume": 1, "paper": 2}
 
 
+BLOCKS = {"split": 0, "coupled": 1}
+
+
 def _desc_arrays(problem, alpha_hat=None, n_modes=None, precision="fp64", weight_mode=None,
-                 leaf_size=0, mu_ref=0.0, fiber_k=0.0):
+                 leaf_size=0, mu_ref=0.0, fiber_k=0.0, hessian_blocks="split"):
     """Contiguous host arrays + the emu_mesh_desc struct that points at them.
     ``weight_mode`` None takes the problem's (``Problem.weight_mode``)."""
     if weight_mode is None:
@@ -60,6 +63,7 @@ def _desc_arrays(problem, alpha_hat=None, n_modes=None, precision="fp64", weight
     d.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     d.leaf_size = int(leaf_size)
     d.bone = iptr(keep["bone"]) if "bone" in keep else None
+    d.hessian_blocks = BLOCKS[hessian_blocks] if isinstance(hessian_blocks, str) else int(hessian_blocks)
     return d, keep
 
 

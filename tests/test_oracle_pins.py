@@ -122,13 +122,14 @@ def _clamp_inactive_state(M, a_el, scale=0.01, tries=50):
     raise AssertionError("no clamp-inactive state found")
 
 
-@pytest.mark.parametrize("hessian,act", [("full", 0.5), ("split", 0.0)])
+@pytest.mark.parametrize("hessian,act", [("full", 0.5), ("split", 0.0), ("coupled", 0.5)])
 def test_all_modes_woodbury_is_exact_newton(hessian, act):
     # With every mode kept (k = 3 n_f) the low-rank term reproduces
     # alpha W G L_w^{-1} G^T W exactly (eq. low-rank with nothing dropped), so
     # where the clamp is inactive the quasi-Newton direction is the exact
     # Newton direction of the separated energy (eq. full-Hessian).  The split
-    # block structure is exact for the isotropic energy (no fiber term, a = 0).
+    # block structure is exact for the isotropic energy (no fiber term, a = 0);
+    # the coupled 9x9 structure keeps the fiber coupling and is exact with it.
     p = _hetero("cube2", seed=1)
     p.activation = np.array([act, act])
     M = msh.build(p, modes=False)
@@ -198,3 +199,20 @@ def test_heterogeneous_emu_equals_dense_newton(weight_mode):
     assert o1["stats"]["converged"], o1["stats"]
     assert _disp_err(o1["q"], o4["q"], M.rest) < 1e-8
     assert np.abs(o1["F"] - o4["F"]).max() < 1e-8
+
+
+def test_coupled_blocks_are_psd_and_equal_split_without_fibers():
+    # the coupled 9x9 blocks are positive semi-definite (+ beta I) at indefinite
+    # states; with no activation they reduce to the split blocks, and with
+    # activation they differ from them only by the fiber's sym/skew coupling
+    p = _hetero("cube2", seed=6)
+    M = msh.build(p, modes=False)
+    F = np.eye(3) + 0.5 * RNG.normal(size=(M.m, 3, 3))
+    a0 = np.zeros(M.m)
+    assert np.abs(emu.block_hessian(M, F, a0, "coupled") - emu.block_hessian(M, F, a0, "split")).max() \
+        <= 1e-12 * np.abs(emu.block_hessian(M, F, a0, "split")).max()
+    a_el = msh.activation_per_element(M, p.activation)
+    Hc = emu.block_hessian(M, F, a_el, "coupled") - M.beta[:, None, None] * np.eye(9)
+    assert np.linalg.eigvalsh(Hc).min() >= -1e-10 * np.abs(Hc).max()
+    Hs = emu.block_hessian(M, F, a_el, "split")
+    assert np.abs(Hc + M.beta[:, None, None] * np.eye(9) - Hs).max() > 1e-6 * np.abs(Hs).max()
