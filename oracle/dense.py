@@ -51,12 +51,21 @@ def solve(M, a, tol=1e-11, max_iters=200):
         e = M.vol * mat.psi(F, M.mu, M.lhat, a_el, M.kf, M.fiber)
         return math.fsum(e) + 0.5 * math.fsum(Bw * D * D), Av, qf
 
-    Fv = np.tile(np.eye(3), (M.m, 1, 1)).reshape(-1)
+    # variables: one 3x3 per tet, or (affine bones, Sec. 3.3) one per non-bone
+    # tet and one per bone: F = Pm F_red with Pm the 0/1 map of tets to variables
+    nvar = M.m if M.red_of is None else M.m_red
+    red = np.arange(M.m) if M.red_of is None else M.red_of
+    Pm = np.zeros((9 * M.m, 9 * nvar))
+    for i in range(M.m):
+        Pm[9 * i:9 * i + 9, 9 * red[i]:9 * red[i] + 9] = np.eye(9)
+    Fr = np.tile(np.eye(3), (nvar, 1, 1)).reshape(-1)
+    Fv = Pm @ Fr
     E, Av, qf = energy(Fv)
     it = 0
     while True:
         F = Fv.reshape(M.m, 3, 3)
-        g = (M.vol[:, None, None] * mat.pk1(F, M.mu, M.lhat, a_el, M.kf, M.fiber)).reshape(-1) + Bw * (Fv - Av)
+        g = Pm.T @ ((M.vol[:, None, None] * mat.pk1(F, M.mu, M.lhat, a_el, M.kf, M.fiber)).reshape(-1)
+                    + Bw * (Fv - Av))
         gn = float(np.linalg.norm(g))
         if gn <= tol or it >= max_iters:
             break
@@ -65,16 +74,18 @@ def solve(M, a, tol=1e-11, max_iters=200):
         for i in range(M.m):
             H[9 * i:9 * i + 9, 9 * i:9 * i + 9] = Hb[i]
         H += np.diag(Bw) - (Bw[:, None] * G) @ Kinv @ (G.T * Bw[None, :])
+        H = Pm.T @ H @ Pm
         H = mat.clamp_psd(0.5 * (H + H.T)) + 1e-12 * np.abs(H).max() * np.eye(H.shape[0])
         step = -np.linalg.solve(H, g)
         gs = float(g @ step)
         t = 1.0
         for _ls in range(60):
-            Et, Avt, qft = energy(Fv + t * step)
+            Et, Avt, qft = energy(Pm @ (Fr + t * step))
             if Et <= E + 1e-4 * t * gs or abs(Et - E) <= 1e-15 * abs(E):
                 break
             t *= 0.5
-        Fv, E, Av, qf = Fv + t * step, Et, Avt, qft
+        Fr = Fr + t * step
+        Fv, E, Av, qf = Pm @ Fr, Et, Avt, qft
         it += 1
     q = qp.copy()
     q[M.free] = qf.reshape(-1, 3)

@@ -106,6 +106,30 @@ def block_hessian(M, F, a_el, hessian="full"):
     return Hc + M.beta[:, None, None] * np.eye(9)
 
 
+def reduced_block_hessian(M, F, a_el, hessian="full"):
+    """Blocks of the reduced variables: per-tet blocks for non-bone tets; for
+    a bone, the definiteness fix of the summed element Hessians of its tets
+    (they share F_b) plus the summed beta."""
+    if M.red_of is None:
+        return block_hessian(M, F, a_el, hessian)
+    Hel = M.vol[:, None, None] * mat.hess(F, M.mu, M.lhat, a_el, M.kf, M.fiber)
+    Hsum = reduce_sum(M, Hel)
+    Fr = np.zeros((M.m_red, 3, 3))
+    Fr[M.red_of] = F
+    if hessian == "full":
+        Hc = mat.clamp_psd(Hsum)
+    elif hessian == "split":
+        T = frame_basis(mat.polar_rotation(Fr))
+        HY = np.einsum("iab,ibc,icd->iad", np.transpose(T, (0, 2, 1)), Hsum, T)
+        Hb = np.zeros_like(HY)
+        Hb[:, :6, :6] = mat.clamp_psd(HY[:, :6, :6])
+        Hb[:, 6:, 6:] = mat.clamp_psd(HY[:, 6:, 6:])
+        Hc = np.einsum("iab,ibc,idc->iad", T, Hb, T)
+    else:
+        raise ValueError(hessian)
+    return Hc + reduce_sum(M, M.beta)[:, None, None] * np.eye(9)
+
+
 def mode_gradients(M, idx=None):
     """grad_i phi_j = sum_v phi_j(v) b_{i,v} (pinned vertices carry zero), [m,k,3]."""
     k = M.phi.shape[0]
@@ -124,8 +148,25 @@ def woodbury_blocks(M, idx):
     return B.reshape(len(idx), 3 * k, 9)
 
 
-def direction(M, H, g, chunk=4096, return_parts=False):
-    """Woodbury direction d = Htilde^{-1} g for blocks H [m,9,9], gradient g [m,9]."""
+def reduce_sum(M, x):
+    """Affine bones (Sec. 3.3): per-tet quantities summed onto the reduced
+    variables (a bone's tets share its F_b); identity without bones."""
+    if M.red_of is None:
+        return x
+    out = np.zeros((M.m_red,) + x.shape[1:])
+    np.add.at(out, M.red_of, x)
+    return out
+
+
+def expand(M, x):
+    """Reduced quantities back to the tets (a bone's value on each of its tets)."""
+    return x if M.red_of is None else x[M.red_of]
+
+
+def direction(M, H, g, chunk=4096, return_parts=False, B_all=None):
+    """Woodbury direction d = Htilde^{-1} g for blocks H [m,9,9], gradient g [m,9]
+    (one block per variable; ``B_all`` [m,k,9] gives the low-rank rows of the
+    variables when they are not the tets', e.g. the summed rows of a bone)."""
     gbar = np.linalg.solve(H, g[..., None])[..., 0]
     if M.phi is None or M.phi.shape[0] == 0:
         return (gbar, None, None, None) if return_parts else gbar
@@ -134,9 +175,10 @@ def direction(M, H, g, chunk=4096, return_parts=False):
     y = np.zeros(k3)
     Gm = np.zeros((k3, k3))
     HiBt_all = []
-    for lo in range(0, M.m, chunk):
-        idx = np.arange(lo, min(M.m, lo + chunk))
-        B = woodbury_blocks(M, idx)
+    nvar = H.shape[0]
+    for lo in range(0, nvar, chunk):
+        idx = np.arange(lo, min(nvar, lo + chunk))
+        B = woodbury_blocks(M, idx) if B_all is None else B_all[idx]
         HiBt = np.linalg.solve(H[idx], np.transpose(B, (0, 2, 1)))
         y += np.einsum("ikl,il->k", B, gbar[idx])
         Gm += np.tensordot(B, HiBt, axes=([0, 2], [0, 1]))
@@ -177,7 +219,7 @@ def delta_energy(M, F, P, sigma, A, A_t, a_el, dwork=0.0):
 def gradient_norm(M, F, a_el):
     q = msh.acap_solve(M, F)
     A = msh.gather_A(M, q)
-    g = grad_F(M, F, A, a_el)
+    g = reduce_sum(M, grad_F(M, F, A, a_el))
     return math.sqrt(math.fsum((g * g).reshape(-1))), q
 
 
@@ -199,7 +241,8 @@ def solve(M, a, F0=None, tol=1e-8, max_iters=5000, sigma0=10.0, armijo_c=1e-4, r
     while True:
         A = msh.gather_A(M, q)
         G = grad_F(M, F, A, a_el)
-        gnorm = math.sqrt(math.fsum((G * G).reshape(-1)))
+        Gr = reduce_sum(M, G)
+        gnorm = math.sqrt(math.fsum((Gr * Gr).reshape(-1)))
         E0 = math.fsum(element_energy(M, F, A, a_el)) - msh.work(M, q)
         if history:
             hist.append(dict(E=E0, gnorm=gnorm))
@@ -211,10 +254,17 @@ def solve(M, a, F0=None, tol=1e-8, max_iters=5000, sigma0=10.0, armijo_c=1e-4, r
         if stats["iters"] >= max_iters:
             stats["status"] = "not_converged"
             break
-        H = block_hessian(M, F, a_el, hessian)
-        g = G.reshape(M.m, 9)
-        d = direction(M, H, g)
-        P = -d.reshape(M.m, 3, 3)
+        if M.red_of is None:
+            H = block_hessian(M, F, a_el, hessian)
+            g = G.reshape(M.m, 9)
+            d = direction(M, H, g)
+            P = -d.reshape(M.m, 3, 3)
+        else:
+            H = reduced_block_hessian(M, F, a_el, hessian)
+            g = reduce_sum(M, G.reshape(M.m, 9))
+            Bred = reduce_sum(M, woodbury_blocks(M, np.arange(M.m)))
+            d = direction(M, H, g, B_all=Bred)
+            P = -expand(M, d).reshape(M.m, 3, 3)
         gp = -math.fsum((g * d).reshape(-1))
         if not gp < 0.0:
             stats["status"] = "not_descent"

@@ -59,6 +59,8 @@ class Mesh:
     phi: np.ndarray = None  # modes [k/3, n_f]
     fext: np.ndarray = None  # external vertex forces [n,3] (None: W = 0)
     vext: np.ndarray = None  # L_ff^{-1} f at free vertices, 0 at pins [n,3]
+    red_of: np.ndarray = None  # affine bones: reduced variable of each tet (None: one per tet)
+    m_red: int = 0
 
     @property
     def n(self):
@@ -90,7 +92,8 @@ def hat_gradients(rest, tets):
     return b, vol
 
 
-def build(problem, alpha_hat=None, n_modes=None, weight_mode=None, modes=True, factor=True):
+def build(problem, alpha_hat=None, n_modes=None, weight_mode=None, modes=True, factor=True,
+          affine_bones=False, bone_slack=1e-3):
     """Set up the oracle mesh for a ``workloads.Problem``.  ``factor=False``
     skips the sparse factorization (and the modes): the element formulas,
     ``L``, ``scatter_GtWF`` and ``gather_A`` still work, which is what checks
@@ -119,6 +122,13 @@ def build(problem, alpha_hat=None, n_modes=None, weight_mode=None, modes=True, f
         w = np.where(bone >= 0, vol, vol * mu / mu_ref)
     else:
         raise ValueError("weight_mode")
+    if affine_bones:
+        # Sec. 3.3: the tets of each bone share one deformation gradient F_b,
+        # tied to the continuous mesh by B_q q = B_F F with the slack eps_2 of
+        # eq. kkt-matrix; eliminating the slack's multiplier adds the penalty
+        # |G_i q - F_b|^2 / (2 |eps_2|) per bone tet (read relative to the
+        # tet's volume-weighted ACAP term), and bones are not stiffness-weighted
+        w = np.where(bone >= 0, vol * (1.0 + 1.0 / bone_slack), w)
     beta = alpha * w
     fiber = problem.fiber / np.linalg.norm(problem.fiber, axis=1, keepdims=True)
     n = rest.shape[0]
@@ -140,6 +150,17 @@ def build(problem, alpha_hat=None, n_modes=None, weight_mode=None, modes=True, f
              group=group, bone=bone, w=w, beta=beta, alpha=alpha, mu_ref=mu_ref, kf=kf,
              pins=pins, pin_xyz=np.asarray(problem.pin_xyz, np.float64),
              free=free, fpos=fpos, L=L, Lff=Lff, Lfp=Lfp, lu=lu)
+    # reduced variables: one per non-bone tet, one per bone (affine bones)
+    if affine_bones and (bone >= 0).any():
+        ids = np.unique(bone[bone >= 0])
+        nonb = np.nonzero(bone < 0)[0]
+        red_of = np.empty(m, np.int64)
+        red_of[nonb] = np.arange(nonb.size)
+        for k, b in enumerate(ids):
+            red_of[bone == b] = nonb.size + k
+        M.red_of, M.m_red = red_of, nonb.size + ids.size
+    else:
+        M.red_of, M.m_red = None, m
     if n_modes < 0:                       # default: 48 modes, capped by the mesh
         n_modes = min(48, 3 * (free.size - 1))
     if modes and factor and n_modes > 0:

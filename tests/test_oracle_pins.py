@@ -216,3 +216,72 @@ def test_coupled_blocks_are_psd_and_equal_split_without_fibers():
     assert np.linalg.eigvalsh(Hc).min() >= -1e-10 * np.abs(Hc).max()
     Hs = emu.block_hessian(M, F, a_el, "split")
     assert np.abs(Hc + M.beta[:, None, None] * np.eye(9) - Hs).max() > 1e-6 * np.abs(Hs).max()
+
+
+# ------------------------------------------------------------ affine bones
+def _two_bones(kind="grid224", seed=2):
+    """Two rigid-ish layers (bone 0 and bone 1, 100x stiffer) in a muscle column:
+    the cube layers 1 and 3 along z; layer 0 rests on the pinned face."""
+    p = wl.tiny(kind, activation=0.6, seed=seed)
+    cz = p.rest_xyz[p.tets].mean(axis=1)[:, 2] / wl.H_EDGE
+    layer = np.floor(cz).astype(int)
+    p.bone = np.where(layer == 1, 0, np.where(layer == 3, 1, -1)).astype(np.int32)
+    p.youngs = np.where(p.bone >= 0, 100 * wl.E_MUSCLE, p.youngs)
+    p.group = np.where(p.bone >= 0, -1, 0).astype(np.int32)
+    p.weight_mode = 1
+    return p
+
+
+def test_affine_bones_emu_equals_dense_newton():
+    # Sec. 3.3 with a soft constraint: each bone's tets share one F_b.  The EMU
+    # iteration on the reduced variables (summed gradients and element blocks,
+    # the clamp after the sum) against brute-force Newton with the exact
+    # Hessian of E over the same reduced variables
+    p = _two_bones()
+    M = msh.build(p, affine_bones=True, bone_slack=1e-1)
+    assert M.m_red == M.m - int((p.bone >= 0).sum()) + 2
+    o1 = emu.solve(M, p.activation, tol=1e-11, max_iters=4000, trials="affine")
+    o4 = dense.solve(M, p.activation, tol=1e-12)
+    assert o1["stats"]["converged"], o1["stats"]
+    assert _disp_err(o1["q"], o4["q"], M.rest) < 1e-8
+    assert np.abs(o1["F"] - o4["F"]).max() < 1e-8
+    for b in (0, 1):
+        Fb = o1["F"][p.bone == b]
+        assert np.abs(Fb - Fb[0]).max() == 0.0
+
+
+def test_affine_bone_gradient_is_the_derivative_of_the_energy():
+    # the reduced gradient of a bone is dE/dF_b: central differences of E over
+    # a common perturbation of every tet of the bone (E from a fresh ACAP solve)
+    p = _two_bones()
+    M = msh.build(p, affine_bones=True, bone_slack=1e-2)
+    a_el = msh.activation_per_element(M, p.activation)
+    rng = np.random.default_rng(5)
+    Fr = np.eye(3) + 0.2 * rng.normal(size=(M.m_red, 3, 3))
+    F = emu.expand(M, Fr)
+    _, q, A = _total_energy(M, F, a_el)
+    g = emu.reduce_sum(M, emu.grad_F(M, F, A, a_el))
+    for b in (0, 1):
+        r = M.red_of[np.nonzero(p.bone == b)[0][0]]
+        for c in range(9):
+            h = 1e-6
+            D = np.zeros((M.m_red, 9))
+            D[r, c] = h
+            Ep = _total_energy(M, emu.expand(M, Fr + D.reshape(-1, 3, 3)), a_el)[0]
+            Em = _total_energy(M, emu.expand(M, Fr - D.reshape(-1, 3, 3)), a_el)[0]
+            fd = (Ep - Em) / (2 * h)
+            assert abs(fd - g[r].reshape(9)[c]) <= 1e-6 * max(1.0, np.abs(g[r]).max())
+
+
+def test_affine_bone_constraint_residual_scales_with_the_slack():
+    # the soft constraint G_i q = F_b: its residual on the bone tets at the
+    # minimizer shrinks in proportion to |eps_2|
+    p = _two_bones()
+    res = []
+    for slack in (1e-1, 1e-3):
+        M = msh.build(p, affine_bones=True, bone_slack=slack)
+        o = dense.solve(M, p.activation, tol=1e-12)
+        A = msh.gather_A(M, o["q"])
+        sel = p.bone >= 0
+        res.append(np.abs(A[sel] - o["F"][sel]).max())
+    assert 50 < res[0] / res[1] < 200, res
