@@ -109,6 +109,18 @@ typedef struct {
   int32_t leaf_size;         /* nested-dissection leaf size; 0 -> 64              */
   const int32_t *bone;       /* [m] bone id (>= 0) or -1; NULL = no bone tets.
                                 Read by weight_mode EMU_WEIGHT_PAPER             */
+  int32_t affine_bones;      /* 1: the tets of each bone (bone[i] >= 0) share one
+                                deformation gradient F_b (Sec. 3.3), tied to the
+                                continuous mesh by B_q q = B_F F with the slack
+                                eps_2 of eq. kkt-matrix: a bone tet's ACAP weight
+                                is vol (1 + 1/bone_slack) (bones are not
+                                stiffness-weighted).  Joints are vertices shared
+                                by two bones (J q = 0 holds by construction).
+                                Bone tets must be passive (group -1).
+                                Requires split element blocks; not supported
+                                by emu_solve_grad or the serving loop.
+                                0: every tet has its own F.                   */
+  double bone_slack;         /* |eps_2| of the bone constraint; 0 -> 1e-3       */
   int32_t hessian_blocks;    /* element blocks of the quasi-Newton Hessian
                                 (Sec. 3.2.1, eq. not-yet): EMU_BLOCKS_SPLIT, or
                                 EMU_BLOCKS_COUPLED for the full 9x9 block per
@@ -228,7 +240,9 @@ emu_status emu_solve_grad_noalloc(emu_mesh* mesh, const double* dL_dq, double* d
                                   emu_solve_stats* stats, void* stream);
 
 /* State access: F device [m][9] (row-major 3x3 per tet), q device [n][3].
-   emu_set_state takes F, splits it as F = R S and re-solves q = q*(F). */
+   emu_set_state takes F, splits it as F = R S and re-solves q = q*(F); with
+   affine bones each bone takes the F of its first tet in element order (the
+   lowest vertex id). */
 emu_status emu_get_state(const emu_mesh* mesh, double* F, double* q, void* stream);
 emu_status emu_set_state(emu_mesh* mesh, const double* F, void* stream);
 

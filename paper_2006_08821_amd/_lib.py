@@ -31,7 +31,8 @@ class MeshDesc(C.Structure):
                 ("poisson", DP), ("fiber", DP), ("group", I32P), ("pins", I32P), ("pin_xyz", DP),
                 ("alpha_hat", C.c_double), ("mu_ref", C.c_double), ("fiber_k", C.c_double),
                 ("weight_mode", C.c_int32), ("n_modes", C.c_int32), ("precision", C.c_int32),
-                ("leaf_size", C.c_int32), ("bone", I32P), ("hessian_blocks", C.c_int32),
+                ("leaf_size", C.c_int32), ("bone", I32P), ("affine_bones", C.c_int32),
+                ("bone_slack", C.c_double), ("hessian_blocks", C.c_int32),
                 ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_ctx", P)]
 
 

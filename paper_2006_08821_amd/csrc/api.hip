@@ -274,13 +274,40 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
     B.reserve(SLOT(xbuf), 24 * (size_t)nf);
     B.put(SLOT(slots), std::vector<double>(3 * (size_t)std::max<int32_t>(1, slotbase[fac.ns]), 0.0));
   }
-  B.reserve(SLOT(part_e), 16 * (size_t)d.nb);
-  B.reserve(SLOT(part_g), 16 * (size_t)d.nb);
-  B.reserve(SLOT(part_cnt), 8 * (size_t)d.nb);
-  B.reserve(SLOT(part_gram), 8 * (size_t)emu::kGramEntries * d.nbg);
+  // affine bones (Sec. 3.3): the tets of each bone in internal element order
+  {
+    std::vector<int32_t> ids;
+    if (hm.affine_bones)
+      for (int32_t o = 0; o < m; ++o)
+        if (hm.bone[o] >= 0) ids.push_back(hm.bone[o]);
+    std::sort(ids.begin(), ids.end());
+    ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+    d.nbones = (int32_t)ids.size();
+    std::vector<int32_t> ptr(d.nbones + 1, 0), el, pos(m, -1);
+    for (int b = 0; b < d.nbones; ++b) {
+      for (int32_t e = 0; e < m; ++e)
+        if (hm.bone[hm.eold[e]] == ids[b]) {
+          pos[e] = (int32_t)el.size();
+          el.push_back(e);
+        }
+      ptr[b + 1] = (int32_t)el.size();
+    }
+    d.nbt = (int32_t)el.size();
+    if (el.empty()) el.push_back(0);
+    B.put(SLOT(bone_ptr), ptr);
+    B.put(SLOT(bone_el), el);
+    B.put(SLOT(bone_pos), pos);
+    B.reserve(SLOT(bone_gbuf), 72 * (size_t)std::max(1, d.nbt));
+    B.reserve(SLOT(bone_g), 72 * (size_t)std::max(1, d.nbones));
+  }
+  const size_t nparts = (size_t)d.nb + d.nbones;
+  B.reserve(SLOT(part_e), 16 * nparts);
+  B.reserve(SLOT(part_g), 16 * nparts);
+  B.reserve(SLOT(part_cnt), 8 * nparts);
+  B.reserve(SLOT(part_gram), 8 * (size_t)emu::kGramEntries * ((size_t)d.nbg + d.nbones));
   B.reserve(SLOT(gram), 8 * (size_t)emu::kGramEntries);
   B.put(SLOT(zbuf), std::vector<double>(48, 0.0));
-  B.reserve(SLOT(part_ls), 16 * (size_t)emu::kLsTerms * d.nb);
+  B.reserve(SLOT(part_ls), 16 * (size_t)emu::kLsTerms * nparts);
   B.reserve(SLOT(cfac), 8 * 48 * 48);
   B.reserve(SLOT(cfac_ok), 4);
   B.reserve(SLOT(ctl), sizeof(emu::Ctl));
@@ -750,6 +777,7 @@ emu_status emu_set_state(emu_mesh* M, const double* F, void* stream) {
   try {
     join_user_stream(M, stream);
     emu::launch_set_F(M->d, F, M->d_eold, M->st);
+    emu::launch_bone_sync(M->d, M->st);
     fresh_solve(M);
     HIPCHK(hipGetLastError());
     release_user_stream(M, stream);
@@ -770,6 +798,7 @@ emu_status emu_evaluate(emu_mesh* M, const double* F, double* q, double* energy,
     join_user_stream(M, stream);
     backup_state(M);
     emu::launch_set_F(M->d, F, M->d_eold, M->st);
+    emu::launch_bone_sync(M->d, M->st);
     emu_solve_opts o = emu_solve_opts_default();
     init_ctl(M, o, 1);
     fresh_solve(M);
@@ -982,6 +1011,10 @@ emu_status adjoint_run(emu_mesh* M, const AdjWork& w, const double* dL_dq, doubl
 emu_status adjoint_args_ok(const emu_mesh* M, const double* dL_dq, const double* dL_da) {
   if (!M || !dL_dq || (!dL_da && M->hm.ngroups > 0)) {
     emu::set_error("NULL argument");
+    return EMU_E_INVALID;
+  }
+  if (M->d.nbones > 0) {
+    emu::set_error("the adjoint does not support affine bones");
     return EMU_E_INVALID;
   }
   if (!M->converged) {

@@ -61,7 +61,9 @@ struct DevMesh {
   int32_t mixed;       // FP32 element Hessian / Gram / direction
   int32_t has_ext;     // external vertex forces set (vext nonzero)
   int32_t coupled;     // 9x9 element blocks with the fiber coupling (else 6x6 + 3x3)
-  int32_t pad_c;
+  int32_t nbones;      // affine bones (one shared F per bone; 0: none)
+  int32_t nbt;         // tets in all affine bones
+  int32_t pad_b;
   double alpha, kf;
 
   // elements, internal order, structure of arrays
@@ -118,6 +120,13 @@ struct DevMesh {
   double* cfac;              // [48][48] Cholesky factor of the last Woodbury system
   int32_t* cfac_ok;          // [1] 1 if that factorization succeeded
   double* part_ls;           // [nb][2*kLsTerms]
+  // affine bones: partial-sum slots nb .. nb + nbones - 1 (part_e, part_g,
+  // part_cnt, part_ls) and Gram rows nbg .. nbg + nbones - 1 belong to the bones
+  const int32_t* bone_ptr;   // [nbones + 1] into bone_el
+  const int32_t* bone_el;    // bone tets (internal ids, ascending per bone)
+  const int32_t* bone_pos;   // [m] position of the tet in bone_el, -1 if not a bone tet
+  double* bone_gbuf;         // [9][nbt] gradient of each bone tet (rotated frame, y coordinates)
+  double* bone_g;            // [nbones][9] summed gradient of each bone
   Ctl* ctl;
 };
 

@@ -123,6 +123,13 @@ static void validate(const emu_mesh_desc& d) {
     fail(EMU_E_INVALID, "dev_alloc and dev_free must be given together");
   if (d.precision != 0 && d.precision != 1) fail(EMU_E_INVALID, "precision must be 0 or 1");
   if (d.hessian_blocks != 0 && d.hessian_blocks != 1) fail(EMU_E_INVALID, "hessian_blocks must be 0 or 1");
+  if (d.affine_bones != 0 && d.affine_bones != 1) fail(EMU_E_INVALID, "affine_bones must be 0 or 1");
+  if (!(d.bone_slack >= 0) || !std::isfinite(d.bone_slack)) fail(EMU_E_INVALID, "bone_slack must be >= 0");
+  if (d.affine_bones && d.hessian_blocks != 0)
+    fail(EMU_E_INVALID, "affine bones take the split element blocks");
+  if (d.affine_bones && d.bone)
+    for (int64_t i = 0; i < m; ++i)
+      if (d.bone[i] >= 0 && d.group[i] >= 0) fail(EMU_E_INVALID, "affine bone tets must be passive (group -1)");
   if (d.leaf_size < 0) fail(EMU_E_INVALID, "leaf_size must be >= 0");
 }
 
@@ -205,9 +212,15 @@ static void geometry(const emu_mesh_desc& d, HostMesh& hm) {
   hm.alpha = hm.alpha_hat * hm.mu_ref;
   hm.weight_mode = d.weight_mode;
   hm.w.resize(m);
+  hm.affine_bones = d.affine_bones;
+  hm.bone_slack = d.bone_slack > 0 ? d.bone_slack : 1e-3;
   for (int32_t i = 0; i < m; ++i) {
     const bool stiff = d.weight_mode == EMU_WEIGHT_STIFFNESS || (d.weight_mode == EMU_WEIGHT_PAPER && hm.bone[i] < 0);
     hm.w[i] = stiff ? hm.vol[i] * hm.mu[i] / hm.mu_ref : hm.vol[i];
+    // affine bones (Sec. 3.3): the bone constraint with slack eps_2 adds
+    // |G_i q - F_b|^2 / (2 |eps_2|) per bone tet, relative to its
+    // volume-weighted ACAP term; bones are not stiffness-weighted
+    if (hm.affine_bones && hm.bone[i] >= 0) hm.w[i] = hm.vol[i] * (1.0 + 1.0 / hm.bone_slack);
   }
   hm.precision = d.precision;
   hm.hessian_blocks = d.hessian_blocks;

@@ -60,7 +60,8 @@ struct HostMesh {
   std::vector<int32_t> pins;
   std::vector<double> pin_xyz;         // [npins][3]
   double alpha_hat = 10, mu_ref = 0, kf = 0, alpha = 0;
-  int32_t weight_mode = 0, k1 = 16, precision = 0, leaf_size = 64, hessian_blocks = 0;
+  int32_t weight_mode = 0, k1 = 16, precision = 0, leaf_size = 64, hessian_blocks = 0, affine_bones = 0;
+  double bone_slack = 1e-3;
   bool k1_default = true;            // n_modes not given: capped at n_free - 1
 
   // derived per element (user order)

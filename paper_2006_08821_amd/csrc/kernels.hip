@@ -1341,12 +1341,19 @@ DEV void b_element(const DevMesh& d, int bid) {
     double gn = 0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) gn += G[k] * G[k];
-    acc[1] = dd_add_d(acc[1], gn);
     double gy[9];
     to_y<double, double>(G, gy);
-    T* gyo = (T*)d.gbar;
+    const int bpos = d.nbones ? d.bone_pos[i] : -1;
+    if (bpos < 0) {
+      acc[1] = dd_add_d(acc[1], gn);
+      T* gyo = (T*)d.gbar;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) gyo[k * m + i] = (T)gy[k];
+      for (int k = 0; k < 9; ++k) gyo[k * m + i] = (T)gy[k];
+    } else {
+      // affine bone tet: its gradient is a term of the bone's (k_bone_blocks)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) d.bone_gbuf[(int64_t)k * d.nbt + bpos] = gy[k];
+    }
   }
   block_reduce_dd<2>(acc, sh);
   const int ninv_sum = block_sum_int(ninv, shc);
@@ -1362,39 +1369,46 @@ DEV void b_element(const DevMesh& d, int bid) {
 // Hessian blocks of the element pass: at the state left by b_element, the two
 // clamped blocks + beta I in the rotated basis (precision T), their Cholesky
 // factors, and gbar = H^{-1} g (g read from gbar, overwritten in place).
+// The two blocks at a stretch S with material scalars (vol mu, vol lhat,
+// a k_f): the element's own, or a bone's sums over its tets (the Hessian is
+// linear in vol mu and vol lhat at a fixed S).
 template <typename T>
-DEV void hess_blocks(const DevMesh& d, int i, T (&Hs)[6][6], T (&Hk)[3][3], bool fiber = true) {
-  const int m = d.m;
-  double S[9];
-  load_S(d, i, S);
-  const double vol = d.vol[i], mu = d.mu[i], lhat = d.lhat[i];
-  double u[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) u[c] = d.fib[c * m + i];
-  const int g = d.grp[i];
-  const double afk = fiber ? (g >= 0 ? d.act[g] : 0.0) * d.kf : 0.0;
+DEV void hess_blocks_s(const double* S, double vmu, double vlhat, double vafk, const double* u, T (&Hs)[6][6],
+                       T (&Hk)[3][3]) {
   const double J = det3(S);
   double C[9];
   cof3<double>(S, C);
-  const double kap = lhat * (J - 1.0) - mu;
-  // Hessian blocks in the rotated basis (precision T)
+  const double vkap = vlhat * (J - 1.0) - vmu;
   T St[9], ut[3];
 #pragma unroll
   for (int k = 0; k < 9; ++k) St[k] = (T)S[k];
 #pragma unroll
   for (int k = 0; k < 3; ++k) ut[k] = (T)u[k];
-  const T muT = (T)mu, kapT = (T)kap, phiT = (T)(2.0 * afk), volT = (T)vol, lhT = (T)lhat;
+  const T muT = (T)vmu, kapT = (T)vkap, phiT = (T)(2.0 * vafk), lhT = (T)vlhat;
   T cy[9];
   to_y<T, double>(C, cy);
 #pragma unroll
   for (int y = 0; y < 6; ++y)
 #pragma unroll
-    for (int z = 0; z < 6; ++z)
-      Hs[y][z] = volT * (hproj<T>(y, z, St, muT, kapT, phiT, ut) + lhT * cy[y] * cy[z]);
+    for (int z = 0; z < 6; ++z) Hs[y][z] = hproj<T>(y, z, St, muT, kapT, phiT, ut) + lhT * cy[y] * cy[z];
 #pragma unroll
   for (int y = 0; y < 3; ++y)
 #pragma unroll
-    for (int z = 0; z < 3; ++z) Hk[y][z] = volT * hproj<T>(6 + y, 6 + z, St, muT, kapT, phiT, ut);
+    for (int z = 0; z < 3; ++z) Hk[y][z] = hproj<T>(6 + y, 6 + z, St, muT, kapT, phiT, ut);
+}
+
+template <typename T>
+DEV void hess_blocks(const DevMesh& d, int i, T (&Hs)[6][6], T (&Hk)[3][3], bool fiber = true) {
+  const int m = d.m;
+  double S[9];
+  load_S(d, i, S);
+  const double vol = d.vol[i];
+  double u[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) u[c] = d.fib[c * m + i];
+  const int g = d.grp[i];
+  const double afk = fiber ? (g >= 0 ? d.act[g] : 0.0) * d.kf : 0.0;
+  hess_blocks_s<T>(S, vol * d.mu[i], vol * d.lhat[i], vol * afk, u, Hs, Hk);
 }
 
 // Both blocks are clamped to their positive semi-definite part, beta I is
@@ -1422,7 +1436,8 @@ DEV void b_element_hess(const DevMesh& d, int bid) {
     if (threadIdx.x == 0) nfix = 0;
     __syncthreads();
     const int i = base + threadIdx.x;
-    if (i < m) {
+    const bool own = i < m && !(d.nbones && d.bone_pos[i] >= 0);  // bone tets: k_bone_blocks
+    if (own) {
       T Hs[6][6], Hk[3][3];
       hess_blocks<T>(d, i, Hs, Hk, !kC);
       const T beta = (T)(d.alpha * d.w[i]);
@@ -1456,6 +1471,15 @@ DEV void b_element_hess(const DevMesh& d, int bid) {
       for (int k = 0; k < 3; ++k) gbar[(6 + k) * m + i] = gk[k];
 #pragma unroll
       for (int k = 0; k < 6; ++k) Lf[(21 + k) * m + i] = Lk[k];
+    } else if (i < m) {
+      // an affine bone tet: identity factors and gbar = 0, so that the Gram
+      // pass (which gives it weight 0) reads finite values; k_bone_blocks
+      // then stores the bone's own block at its first tet
+#pragma unroll
+      for (int k = 0; k < 27; ++k) Lf[k * m + i] = (k < 21 ? (k == 0 || k == 2 || k == 5 || k == 9 || k == 14 || k == 20)
+                                                            : (k == 21 || k == 23 || k == 26)) ? T(1) : T(0);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) gbar[k * m + i] = T(0);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1481,7 +1505,7 @@ DEV void b_element_hess(const DevMesh& d, int bid) {
     }
     if constexpr (kC) {
       __syncthreads();
-      if (i < m) coupled_finish<T>(d, i);
+      if (own) coupled_finish<T>(d, i);
     }
     // nfix and fix are reused by the next round
     __syncthreads();
@@ -1741,7 +1765,8 @@ DEV void b_gram(const DevMesh& d, int bid) {
 #pragma unroll
           for (int q = 0; q < 3; ++q) zw[el][54 + 3 * sl + q] = (T)(r0 * D[q] + r1 * D[3 + q] + r2 * D[6 + q]);
         } else {
-          zw[el][63] = (T)d.w[i];
+          // affine bone tets enter through their bone's row (k_bone_blocks)
+          zw[el][63] = (d.nbones && d.bone_pos[i] >= 0) ? T(0) : (T)d.w[i];
         }
         double b[4][3];
 #pragma unroll
@@ -1875,6 +1900,7 @@ DEV void b_gram_reduce(const DevMesh& d, int bid) {
     double s = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) s += sh[k][el];
+    for (int b = 0; b < d.nbones; ++b) s += d.part_gram[(int64_t)(d.nbg + b) * kGramEntries + e];
     d.gram[e] = s;
   }
 }
@@ -1902,10 +1928,11 @@ DEV void b_control_a(const DevMesh& d, int bid) {
   constexpr int kPU = 4;  // partials per thread in the first round (nb <= 1024)
   double pe[kPU][2], pg[kPU][2];
   int pc[kPU][2];
+  const int nparts = d.nb + d.nbones;  // element workgroups, then bones
 #pragma unroll
   for (int u = 0; u < kPU; ++u) {
     const int b = t + u * kCtlThreads;
-    const bool ok = b < d.nb;
+    const bool ok = b < nparts;
     pe[u][0] = ok ? d.part_e[2 * b] : 0.0;
     pe[u][1] = ok ? d.part_e[2 * b + 1] : 0.0;
     pg[u][0] = ok ? d.part_g[2 * b] : 0.0;
@@ -1935,13 +1962,13 @@ DEV void b_control_a(const DevMesh& d, int bid) {
   int cl = 0, inv = 0;
 #pragma unroll
   for (int u = 0; u < kPU; ++u)
-    if (t + u * kCtlThreads < d.nb) {
+    if (t + u * kCtlThreads < nparts) {
       acc[0] = dd_add(acc[0], DD{pe[u][0], pe[u][1]});
       acc[1] = dd_add(acc[1], DD{pg[u][0], pg[u][1]});
       cl += pc[u][0];
       inv += pc[u][1];
     }
-  for (int b = t + kPU * kCtlThreads; b < d.nb; b += kCtlThreads) {
+  for (int b = t + kPU * kCtlThreads; b < nparts; b += kCtlThreads) {
     acc[0] = dd_add(acc[0], DD{d.part_e[2 * b], d.part_e[2 * b + 1]});
     acc[1] = dd_add(acc[1], DD{d.part_g[2 * b], d.part_g[2 * b + 1]});
     cl += d.part_cnt[2 * b];
@@ -2140,6 +2167,7 @@ DEV void b_direction(const DevMesh& d, int bid) {
   const T* Lf = (const T*)d.Lf;
   const T* gbar = (const T*)d.gbar;
   for (int i = xcd_block(bid, d.nb) * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
+    if (d.nbones && d.bone_pos[i] >= 0) continue;  // affine bone tets: k_bone_dir
     Elem e;
     load_elem(d, i, e);
     double R[9], Az[9], RA[9];
@@ -2205,6 +2233,218 @@ DEV void b_direction(const DevMesh& d, int bid) {
 }
 template <typename T, bool kC = false>
 __global__ void __launch_bounds__(kBlock) k_direction(DevMesh d) { b_direction<T, kC>(d, blockIdx.x); }
+
+// ------------------------------------------------------------------ affine bones
+// Sec. 3.3: the tets of a bone share one deformation gradient F_b.  Each bone
+// tet keeps a copy of F_b = R_b S_b (the accept step applies the same p_b to
+// every copy, so the copies stay identical), and the reduced variable's
+// quantities are sums over its tets, all in the shared rotated frame:
+//   gradient  g_b = sum_i g_i
+//   block     H_b = definiteness fix of the blocks of sum_i vol_i d2Psi_i(S_b)
+//                   + alpha sum_i w_i I  (d2Psi is linear in vol mu and vol lhat
+//                   at a fixed S; bone tets are passive)
+//   low rank  B_b = sum_i B_i, i.e. Gamma_b[j] = sum_i w_i gphi_j(i)
+// The bone's factor and gbar_b sit at its representative tet (its first in
+// element order).  The per-element passes leave bone tets out (the element
+// pass keeps their gradients aside and out of the norm, the Hessian pass skips
+// them, the Gram pass weights them 0, the direction pass leaves them to
+// k_bone_dir).  One workgroup per bone, a fixed assignment of its tets to
+// threads and fixed-order sums; its partial sums take the slots after the
+// element workgroups'.
+constexpr int kBoneSums = 9 + 3 * kMaxK1 + 3;  // g, Gamma, vol mu, vol lhat, w
+
+template <int N>
+DEV void block_sum_fixed(double (&v)[N], double (*red)[N]) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) red[wave][k] = v[k];
+  __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bone_blocks(DevMesh d) {
+  if (d.ctl->done) return;
+  const int b = blockIdx.x, t = threadIdx.x, m = d.m;
+  const int p0 = d.bone_ptr[b], p1 = d.bone_ptr[b + 1];
+  __shared__ double red[kBlock / 64][kBoneSums];
+  __shared__ double tot[kBoneSums];
+  __shared__ T zr[kGramRow];
+  double acc[kBoneSums];
+#pragma unroll
+  for (int k = 0; k < kBoneSums; ++k) acc[k] = 0.0;
+  for (int q = p0 + t; q < p1; q += kBlock) {
+    const int i = d.bone_el[q];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] += d.bone_gbuf[(int64_t)k * d.nbt + q];
+    Elem e;
+    load_elem(d, i, e);
+    for (int j = 0; j < d.k1; ++j) {
+      double g0 = 0, g1 = 0, g2 = 0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double ph = d.phi[(int64_t)kMaxK1 * e.v[v] + j];
+        g0 += ph * e.b[v][0];
+        g1 += ph * e.b[v][1];
+        g2 += ph * e.b[v][2];
+      }
+#pragma unroll
+      for (int jj = 0; jj < kMaxK1; ++jj)
+        if (jj == j) {
+          acc[9 + 3 * jj] += e.w * g0;
+          acc[9 + 3 * jj + 1] += e.w * g1;
+          acc[9 + 3 * jj + 2] += e.w * g2;
+        }
+    }
+    acc[kBoneSums - 3] += e.vol * e.mu;
+    acc[kBoneSums - 2] += e.vol * e.lhat;
+    acc[kBoneSums - 1] += e.w;
+  }
+  block_sum_fixed<kBoneSums>(acc, red);
+  if (t < kBoneSums) {
+    double v = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) v += red[w][t];
+    tot[t] = v;
+  }
+  __syncthreads();
+  const int rep = d.bone_el[p0];
+  T* Lf = (T*)d.Lf;
+  T* gbar = (T*)d.gbar;
+  if (t == 0) {
+    double S[9];
+    load_S(d, rep, S);
+    const double u[3] = {0, 0, 1};
+    T Hs[6][6], Hk[3][3];
+    hess_blocks_s<T>(S, tot[kBoneSums - 3], tot[kBoneSums - 2], 0.0, u, Hs, Hk);
+    const T beta = (T)(d.alpha * tot[kBoneSums - 1]);
+    T Ls[21], Lk[6];
+    const int ncl = clamp_add_factor<T, 6>(Hs, beta, Ls) + clamp_add_factor<T, 3>(Hk, beta, Lk);
+    T gy[9];
+    double g2 = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      gy[k] = (T)tot[k];
+      g2 += tot[k] * tot[k];
+      d.bone_g[9 * b + k] = tot[k];
+    }
+    split_solve<T>(Ls, Lk, gy);
+#pragma unroll
+    for (int k = 0; k < 21; ++k) Lf[k * m + rep] = Ls[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Lf[(21 + k) * m + rep] = Lk[k];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) gbar[k * m + rep] = gy[k];
+    const int slot = d.nb + b;
+    d.part_e[2 * slot] = 0.0;
+    d.part_e[2 * slot + 1] = 0.0;
+    d.part_g[2 * slot] = g2;
+    d.part_g[2 * slot + 1] = 0.0;
+    d.part_cnt[2 * slot] = ncl;
+    d.part_cnt[2 * slot + 1] = 0;
+  }
+  __syncthreads();
+  // the bone's Z blocks (three lanes, as in the Gram pass) and R D(gbar_b)
+  if (t < 3) {
+    gram_zblocks<T, false>(d, rep, t, zr);
+    double gbd[9], D[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) gbd[q] = (double)gbar[q * m + rep];
+    from_y<double>(gbd, D);
+    const double r0 = d.R[(3 * t) * m + rep], r1 = d.R[(3 * t + 1) * m + rep], r2 = d.R[(3 * t + 2) * m + rep];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) zr[54 + 3 * t + q] = (T)(r0 * D[q] + r1 * D[3 + q] + r2 * D[6 + q]);
+  }
+  __syncthreads();
+  // its Gram row: [p][x][y] = Gamma_x^T Z_p Gamma_y, and y[(c, j)] = Gamma_j . (R D(gbar))_c
+  double* out = d.part_gram + (int64_t)(d.nbg + b) * kGramEntries;
+  for (int e = t; e < kGramEntries; e += kBlock) {
+    double v = 0;
+    if (e < 1536) {
+      const int pp = e >> 8, x = (e >> 4) & 15, y = e & 15;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v += tot[9 + 3 * x + a] * (double)zr[pp * 9 + a * 3 + c] * tot[9 + 3 * y + c];
+    } else {
+      const int c = (e - 1536) >> 4, j = (e - 1536) & 15;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) v += tot[9 + 3 * j + a] * (double)zr[54 + 3 * c + a];
+    }
+    out[e] = v;
+  }
+}
+
+// The bone's step p_b = -(gbar_b + alpha H_b^{-1} R_b^T sum_i w_i A_z(i)) (A_z:
+// the compatible gradient of Phi^T z at tet i), copied to every bone tet with
+// its ACAP right-hand-side contribution; the bone's g . p into its line-search
+// slot (whose polynomial coefficients are zero).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bone_dir(DevMesh d) {
+  if (d.ctl->done) return;
+  const int b = blockIdx.x, t = threadIdx.x, m = d.m;
+  const int p0 = d.bone_ptr[b], p1 = d.bone_ptr[b + 1];
+  __shared__ double red[kBlock / 64][9];
+  __shared__ double pb[9];
+  double acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+  for (int q = p0 + t; q < p1; q += kBlock) {
+    const int i = d.bone_el[q];
+    Elem e;
+    load_elem(d, i, e);
+    double Az[9];
+    gather_grad(d.uz, e, Az);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] += e.w * Az[k];
+  }
+  block_sum_fixed<9>(acc, red);
+  const int rep = d.bone_el[p0];
+  if (t == 0) {
+    double u[9], R[9], RA[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) u[k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
+    load_R(d, rep, R);
+    matTmul3(R, u, RA);
+    const T* Lf = (const T*)d.Lf;
+    const T* gbar = (const T*)d.gbar;
+    T Ls[21], Lk[6], ty[9];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) Ls[k] = Lf[k * m + rep];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Lk[k] = Lf[(21 + k) * m + rep];
+    to_y<T, double>(RA, ty);
+    split_solve<T>(Ls, Lk, ty);
+    double gp = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      pb[k] = -((double)gbar[k * m + rep] + d.alpha * (double)ty[k]);
+      gp += d.bone_g[9 * b + k] * pb[k];
+    }
+    double* ls = d.part_ls + 2 * kLsTerms * (d.nb + b);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) ls[k] = 0.0;
+    ls[12] = gp;
+    ls[13] = 0.0;
+  }
+  __syncthreads();
+  double D[9], R[9], dF[9];
+  from_y<double>(pb, D);
+  load_R(d, rep, R);
+  matmul3(R, D, dF);
+  for (int q = p0 + t; q < p1; q += kBlock) {
+    const int i = d.bone_el[q];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) d.p[k * m + i] = pb[k];
+    Elem e;
+    load_elem(d, i, e);
+    write_contrib(d, i, e, dF);
+  }
+}
 
 // Line-search polynomial: E(sigma) - E(0) = sum_k c_k sigma^k (k = 1..6), exact
 // per element along F(sigma) = R (S + sigma D), A(sigma) = A + sigma dA.
@@ -2299,7 +2539,7 @@ DEV void b_control_b(const DevMesh& d, int bid) {
   DD acc[kLsTerms];
 #pragma unroll
   for (int k = 0; k < kLsTerms; ++k) acc[k] = DD{0, 0};
-  for (int b = t; b < d.nb; b += kBlock)
+  for (int b = t; b < d.nb + d.nbones; b += kBlock)
 #pragma unroll
     for (int k = 0; k < kLsTerms; ++k)
       acc[k] = dd_add(acc[k], DD{d.part_ls[2 * kLsTerms * b + 2 * k], d.part_ls[2 * kLsTerms * b + 2 * k + 1]});
@@ -2726,6 +2966,14 @@ static MeshKernel pick_direction(const DevMesh& d) {
                  : (d.coupled ? k_direction<double, true> : k_direction<double, false>);
 }
 static MeshKernel pick_element(const DevMesh& d) { return d.mixed ? k_element<float> : k_element<double>; }
+static void launch_bone_blocks(const DevMesh& d, hipStream_t st) {
+  if (d.nbones > 0)
+    hipLaunchKernelGGL(d.mixed ? k_bone_blocks<float> : k_bone_blocks<double>, dim3(d.nbones), dim3(kBlock), 0, st, d);
+}
+static void launch_bone_dir(const DevMesh& d, hipStream_t st) {
+  if (d.nbones > 0)
+    hipLaunchKernelGGL(d.mixed ? k_bone_dir<float> : k_bone_dir<double>, dim3(d.nbones), dim3(kBlock), 0, st, d);
+}
 typedef void (*Pc1Kernel)(DevMesh, const double*, double*);
 typedef void (*Pc2Kernel)(DevMesh, const double*, double*, double*);
 static Pc1Kernel pick_pc1(const DevMesh& d) {
@@ -2735,6 +2983,24 @@ static Pc1Kernel pick_pc1(const DevMesh& d) {
 static Pc2Kernel pick_pc2(const DevMesh& d) {
   return d.mixed ? (d.coupled ? k_pc2<float, true> : k_pc2<float, false>)
                  : (d.coupled ? k_pc2<double, true> : k_pc2<double, false>);
+}
+
+// Every bone tet takes its bone's representative (R, S): after a state is
+// set from outside, each bone has one F.
+__global__ void __launch_bounds__(kBlock) k_bone_sync(DevMesh d) {
+  const int b = blockIdx.x, m = d.m;
+  const int p0 = d.bone_ptr[b], p1 = d.bone_ptr[b + 1];
+  const int rep = d.bone_el[p0];
+  for (int q = p0 + 1 + threadIdx.x; q < p1; q += kBlock) {
+    const int i = d.bone_el[q];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) d.R[k * m + i] = d.R[k * m + rep];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) d.S[k * m + i] = d.S[k * m + rep];
+  }
+}
+void launch_bone_sync(const DevMesh& d, hipStream_t st) {
+  if (d.nbones > 0) hipLaunchKernelGGL(k_bone_sync, dim3(d.nbones), dim3(kBlock), 0, st, d);
 }
 
 void launch_init_rest(const DevMesh& d, hipStream_t st) {
@@ -2811,10 +3077,12 @@ void launch_set_pins(const DevMesh& d, hipStream_t st) {
 void launch_iteration(const DevMesh& d, const SolvePlan& pl, hipStream_t st) {
   hipLaunchKernelGGL(pick_element(d), dim3(d.nb), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(pick_hess(d), dim3(d.nb), dim3(kBlock), 0, st, d);
+  launch_bone_blocks(d, st);
   hipLaunchKernelGGL(pick_gram(d), dim3(d.nbg), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_gram_reduce, dim3((kGramEntries + 15) / 16), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_control_a, dim3(1), dim3(kCtlThreads), 0, st, d);
   hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d);
+  launch_bone_dir(d, st);
   hipLaunchKernelGGL(pick_direction(d), dim3(d.nb), dim3(kBlock), 0, st, d);
   launch_solve(d, pl, 0, d.dq, 1, st);
   hipLaunchKernelGGL(k_lscoef, dim3(d.nb), dim3(kBlock), 0, st, d);
@@ -2830,10 +3098,12 @@ void launch_iteration_phased(const DevMesh& d, const SolvePlan& pl, hipStream_t 
   hipLaunchKernelGGL(pick_element(d), dim3(d.nb), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(pick_hess(d), dim3(d.nb), dim3(kBlock), 0, st, d);
   (void)hipEventRecord(ev[1], st);
+  launch_bone_blocks(d, st);
   hipLaunchKernelGGL(pick_gram(d), dim3(d.nbg), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_gram_reduce, dim3((kGramEntries + 15) / 16), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_control_a, dim3(1), dim3(kCtlThreads), 0, st, d);
   hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d);
+  launch_bone_dir(d, st);
   hipLaunchKernelGGL(pick_direction(d), dim3(d.nb), dim3(kBlock), 0, st, d);
   (void)hipEventRecord(ev[2], st);
   launch_solve(d, pl, 0, d.dq, 1, st);
@@ -2849,12 +3119,16 @@ void launch_class(int k, const DevMesh& d, const SolvePlan& pl, hipStream_t st) 
     case 0:
       hipLaunchKernelGGL(pick_element(d), dim3(d.nb), dim3(kBlock), 0, st, d);
       hipLaunchKernelGGL(pick_hess(d), dim3(d.nb), dim3(kBlock), 0, st, d);
+      launch_bone_blocks(d, st);
       break;
     case 1: hipLaunchKernelGGL(pick_gram(d), dim3(d.nbg), dim3(kBlock), 0, st, d); break;
     case 2: hipLaunchKernelGGL(k_gram_reduce, dim3((kGramEntries + 15) / 16), dim3(kBlock), 0, st, d); break;
     case 3: hipLaunchKernelGGL(k_control_a, dim3(1), dim3(kCtlThreads), 0, st, d); break;
     case 4: hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d); break;
-    case 5: hipLaunchKernelGGL(pick_direction(d), dim3(d.nb), dim3(kBlock), 0, st, d); break;
+    case 5:
+      launch_bone_dir(d, st);
+      hipLaunchKernelGGL(pick_direction(d), dim3(d.nb), dim3(kBlock), 0, st, d);
+      break;
     case 6: hipLaunchKernelGGL(k_rhs, dim3(rhs_blocks(d.nf)), dim3(kBlock), 0, st, d, 0, 1); break;
     case 7:
       for (int L = 0; L < pl.nlevels; ++L) {
@@ -2879,10 +3153,12 @@ void launch_class(int k, const DevMesh& d, const SolvePlan& pl, hipStream_t st) 
 void launch_evaluate(const DevMesh& d, hipStream_t st) {
   hipLaunchKernelGGL(pick_element(d), dim3(d.nb), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(pick_hess(d), dim3(d.nb), dim3(kBlock), 0, st, d);
+  launch_bone_blocks(d, st);
   hipLaunchKernelGGL(pick_gram(d), dim3(d.nbg), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_gram_reduce, dim3((kGramEntries + 15) / 16), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_control_a, dim3(1), dim3(kCtlThreads), 0, st, d);
   hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d);
+  launch_bone_dir(d, st);
   hipLaunchKernelGGL(pick_direction(d), dim3(d.nb), dim3(kBlock), 0, st, d);
 }
 

@@ -51,6 +51,7 @@ void launch_get_dir(const DevMesh& d, double* out, const int32_t* eold, hipStrea
 void launch_scatter_F(const DevMesh& d, hipStream_t st);
 void launch_solve(const DevMesh& d, const SolvePlan& pl, int add_pin, double* x, int check_done, hipStream_t st);
 void launch_set_pins(const DevMesh& d, hipStream_t st);
+void launch_bone_sync(const DevMesh& d, hipStream_t st);
 void launch_iteration(const DevMesh& d, const SolvePlan& pl, hipStream_t st);
 void launch_iteration_phased(const DevMesh& d, const SolvePlan& pl, hipStream_t st, hipEvent_t* ev);
 void launch_evaluate(const DevMesh& d, hipStream_t st);

@@ -621,6 +621,7 @@ emu_status emu_server_submit(emu_server* S, const emu_mesh_desc* desc, const dou
     r->times.t_submit = S->now();
     if (desc->hessian_blocks != EMU_BLOCKS_SPLIT)
       throw emu::Error{EMU_E_INVALID, "the serving loop runs the split element blocks only"};
+    if (desc->affine_bones) throw emu::Error{EMU_E_INVALID, "the serving loop does not run affine bones"};
     copy_desc(*desc, r->desc);
     if (desc->n_groups < 0) throw emu::Error{EMU_E_INVALID, "negative n_groups"};
     if (desc->n_groups > 0 && !activation) throw emu::Error{EMU_E_INVALID, "NULL activation"};

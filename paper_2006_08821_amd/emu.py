@@ -23,7 +23,8 @@ BLOCKS = {"split": 0, "coupled": 1}
 
 
 def _desc_arrays(problem, alpha_hat=None, n_modes=None, precision="fp64", weight_mode=None,
-                 leaf_size=0, mu_ref=0.0, fiber_k=0.0, hessian_blocks="split"):
+                 leaf_size=0, mu_ref=0.0, fiber_k=0.0, hessian_blocks="split", affine_bones=False,
+                 bone_slack=0.0):
     """Contiguous host arrays + the emu_mesh_desc struct that points at them.
     ``weight_mode`` None takes the problem's (``Problem.weight_mode``)."""
     if weight_mode is None:
@@ -64,6 +65,8 @@ def _desc_arrays(problem, alpha_hat=None, n_modes=None, precision="fp64", weight
     d.leaf_size = int(leaf_size)
     d.bone = iptr(keep["bone"]) if "bone" in keep else None
     d.hessian_blocks = BLOCKS[hessian_blocks] if isinstance(hessian_blocks, str) else int(hessian_blocks)
+    d.affine_bones = int(bool(affine_bones))
+    d.bone_slack = float(bone_slack)
     return d, keep
 
 
