@@ -226,10 +226,19 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
         if (fac.level[s] == L) items += ((fwd_dir ? fac.h[s] : fac.w[s]) + 31) / 32;
       return items < emu::kWideLevelItems;
     };
+    // A level runs the narrow sweep variant when it has no wide items and its
+    // vectors are short: forward, frontal vectors of at most kNarrowFwdW
+    // entries; backward, at most kNarrowBwdH entries from an item's first
+    // column.  Measured on the 1.5M-tet hinge limb, these levels gain from
+    // the doubled occupancy; levels with longer rows lose to the variant's
+    // smaller load window.
+    pl.fwd_narrow.assign(fac.nlevels, 1);
+    pl.bwd_narrow.assign(fac.nlevels, 1);
     for (int L = 0; L < fac.nlevels; ++L) {
       for (int s = 0; s < fac.ns; ++s)
         if (fac.level[s] == L) {
           const bool wide = fac.parent[s] < 0 && fac.w[s] >= 256;
+          if (wide || fac.w[s] > emu::kNarrowFwdW) pl.fwd_narrow[L] = 0;
           const int step = wide ? 8 : 32;
           // rows further down need more of the frontal vector: heaviest first
           for (int r = (fac.h[s] - 1) / step * step; r >= 0; r -= step)
@@ -242,6 +251,7 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
       for (int s = 0; s < fac.ns; ++s)
         if (fac.level[s] == L) {
           const bool wide = sparse && fac.h[s] >= emu::kWideRowMin;
+          if (wide || fac.h[s] > emu::kNarrowBwdH) pl.bwd_narrow[k] = 0;
           const int step = wide ? 8 : 32;
           for (int c = 0; c < fac.w[s]; c += step) bwd.push_back(item(s, c | (wide ? emu::kItemWideBit : 0)));
         }
@@ -298,7 +308,6 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
     B.put(SLOT(bone_el), el);
     B.put(SLOT(bone_pos), pos);
     B.reserve(SLOT(bone_gbuf), 72 * (size_t)std::max(1, d.nbt));
-    B.reserve(SLOT(bone_g), 72 * (size_t)std::max(1, d.nbones));
   }
   const size_t nparts = (size_t)d.nb + d.nbones;
   B.reserve(SLOT(part_e), 16 * nparts);
@@ -307,7 +316,7 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
   B.reserve(SLOT(part_gram), 8 * (size_t)emu::kGramEntries * ((size_t)d.nbg + d.nbones));
   B.reserve(SLOT(gram), 8 * (size_t)emu::kGramEntries);
   B.put(SLOT(zbuf), std::vector<double>(48, 0.0));
-  B.reserve(SLOT(part_ls), 16 * (size_t)emu::kLsTerms * nparts);
+  B.reserve(SLOT(part_ls), 16 * (size_t)emu::kLsTerms * d.nb);
   B.reserve(SLOT(cfac), 8 * 48 * 48);
   B.reserve(SLOT(cfac_ok), 4);
   B.reserve(SLOT(ctl), sizeof(emu::Ctl));

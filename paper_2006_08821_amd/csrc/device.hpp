@@ -10,7 +10,7 @@ namespace emu {
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kMaxK1 = 16;         // scalar low-rank modes (k = 3 * k1 <= 48)
 constexpr int kGramEntries = 6 * 256 + 48;   // 6 coordinate-pair 16x16 blocks + y
-constexpr int kLsTerms = 7;        // 6 polynomial coefficients + g.p
+constexpr int kLsTerms = 6;        // coefficients of the line-search polynomial
 // Triangular-sweep work items: 32 rows (8 lanes per row) or, flagged by
 // kItemWideBit in the first row, 8 rows (32 lanes per row).  Items of a level
 // with fewer than kWideLevelItems 32-row items use the wide form for
@@ -18,6 +18,9 @@ constexpr int kLsTerms = 7;        // 6 polynomial coefficients + g.p
 constexpr int kItemWideBit = 1 << 30;
 constexpr int kWideLevelItems = 512;
 constexpr int kWideRowMin = 64;
+constexpr int kNarrowChunk = 512;     // vector chunk of the narrow sweep variant (12 KB of LDS)
+constexpr int kNarrowFwdW = 64;       // widest supernode of a forward level run narrow
+constexpr int kNarrowBwdH = 256;      // tallest supernode of a backward level run narrow
 
 // Iteration control block (device memory, one per mesh).
 struct Ctl {
@@ -78,8 +81,8 @@ struct DevMesh {
   double* R;              // [9][m]
   double* S;              // [6][m]
   void* gbar;             // [9][m]  (double or float)
-  void* Lf;               // [27][m] Cholesky of the 6x6 and 3x3 blocks (packed);
-                          // coupled: [33][m], + the factor of K (kernels.hip)
+  void* Lf;               // [27][m] inverses of the 6x6 and 3x3 blocks (packed
+                          // symmetric); coupled: [33][m], + K^{-1} (kernels.hip)
   double* p;              // [9][m]  step in the rotated (sym, skew) basis
   double* contrib;        // [m][12] ACAP right-hand-side contributions
 
@@ -121,12 +124,11 @@ struct DevMesh {
   int32_t* cfac_ok;          // [1] 1 if that factorization succeeded
   double* part_ls;           // [nb][2*kLsTerms]
   // affine bones: partial-sum slots nb .. nb + nbones - 1 (part_e, part_g,
-  // part_cnt, part_ls) and Gram rows nbg .. nbg + nbones - 1 belong to the bones
+  // part_cnt) and Gram rows nbg .. nbg + nbones - 1 belong to the bones
   const int32_t* bone_ptr;   // [nbones + 1] into bone_el
   const int32_t* bone_el;    // bone tets (internal ids, ascending per bone)
   const int32_t* bone_pos;   // [m] position of the tet in bone_el, -1 if not a bone tet
   double* bone_gbuf;         // [9][nbt] gradient of each bone tet (rotated frame, y coordinates)
-  double* bone_g;            // [nbones][9] summed gradient of each bone
   Ctl* ctl;
 };
 

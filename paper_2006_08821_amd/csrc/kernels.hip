@@ -481,15 +481,45 @@ DEV void chol_solve(const T* L, T* x) {  // in place: L L^T x = b
     x[i] = t * rd[i];
   }
 }
+// P = (L L^T)^{-1} = L^{-T} L^{-1}, packed lower, from the packed lower factor L.
 template <typename T, int N>
-DEV void chol_lt_mul(const T* L, const T* x, T* y) {  // y = L^T x
+DEV void chol_inverse(const T* L, T* P) {
+  T Li[N * (N + 1) / 2];
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    T t = 0;
+  for (int c = 0; c < N; ++c) Li[c * (c + 1) / 2 + c] = T(1) / L[c * (c + 1) / 2 + c];
 #pragma unroll
-    for (int k = i; k < N; ++k) t += L[k * (k + 1) / 2 + i] * x[k];
-    y[i] = t;
+  for (int c = 0; c < N; ++c) {
+#pragma unroll
+    for (int r = c + 1; r < N; ++r) {
+      T v = 0;
+#pragma unroll
+      for (int k = c; k < r; ++k) v += L[r * (r + 1) / 2 + k] * Li[k * (k + 1) / 2 + c];
+      Li[r * (r + 1) / 2 + c] = -v * Li[r * (r + 1) / 2 + r];
+    }
   }
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int c = 0; c <= r; ++c) {
+      T v = 0;
+#pragma unroll
+      for (int k = r; k < N; ++k) v += Li[k * (k + 1) / 2 + r] * Li[k * (k + 1) / 2 + c];
+      P[r * (r + 1) / 2 + c] = v;
+    }
+}
+// x <- P x for a packed (lower) symmetric P.
+template <typename T, int N>
+DEV void sym_apply(const T* P, T* x) {
+  T y[N];
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    T v = 0;
+#pragma unroll
+    for (int c = 0; c < N; ++c) v += P[r >= c ? r * (r + 1) / 2 + c : c * (c + 1) / 2 + r] * x[c];
+    y[r] = v;
+  }
+#pragma unroll
+  for (int r = 0; r < N; ++r) x[r] = y[r];
 }
 
 // A <- its positive semi-definite part (eigenvalues < 0 -> 0), by Jacobi.
@@ -709,7 +739,7 @@ DEV int clamp_add_factor(T (&A)[N][N], T beta, T* L) {
 // e_c u^T.  The block H = D + V V^T keeps the fiber's coupling of the
 // symmetric and skew parts, and
 //   H^{-1} = D^{-1} - D^{-1} V K^{-1} V^T D^{-1},  K = I + V^T D^{-1} V (3x3),
-// so only the Cholesky factor of K (6 values) is stored after D's 27.
+// so only K^{-1} (6 values) is stored after D^{-1}'s 27.
 constexpr int kLfSplit = 27;
 constexpr int kLfCoupled = 33;
 
@@ -739,23 +769,23 @@ DEV void fiber_V(const DevMesh& d, int i, T (&V)[9][3]) {
   const T u[3] = {(T)d.fib[i], (T)d.fib[m + i], (T)d.fib[2 * m + i]};
   fiber_cols<T>(u, (T)fiber_scale(d, i), V);
 }
-// x <- D^{-1} x with the split factors
+// x <- D^{-1} x with the stored split inverses (6x6 and 3x3, packed)
 template <typename T>
-DEV void split_solve(const T* Ls, const T* Lk, T* x) {
-  chol_solve<T, 6>(Ls, x);
-  chol_solve<T, 3>(Lk, x + 6);
+DEV void split_apply(const T* Ds, const T* Dk, T* x) {
+  sym_apply<T, 6>(Ds, x);
+  sym_apply<T, 3>(Dk, x + 6);
 }
-// x <- H^{-1} x: the split solve, then (coupled form) the rank-3 correction
+// x <- H^{-1} x: the split inverses, then (coupled form) the rank-3 correction
 template <typename T, bool kC>
-DEV void hinv_apply(const DevMesh& d, int i, const T* Ls, const T* Lk, T* x) {
-  split_solve<T>(Ls, Lk, x);
+DEV void hinv_apply(const DevMesh& d, int i, const T* Ds, const T* Dk, T* x) {
   if constexpr (kC) {
     const T* Lf = (const T*)d.Lf;
     const int m = d.m;
-    T V[9][3], Kf[6];
+    T V[9][3], Ki[6];
     fiber_V<T>(d, i, V);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) Kf[k] = Lf[(kLfSplit + k) * m + i];
+    for (int k = 0; k < 6; ++k) Ki[k] = Lf[(kLfSplit + k) * m + i];
+    split_apply<T>(Ds, Dk, x);
     T t[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -764,36 +794,38 @@ DEV void hinv_apply(const DevMesh& d, int i, const T* Ls, const T* Lk, T* x) {
       for (int k = 0; k < 9; ++k) v += V[k][c] * x[k];
       t[c] = v;
     }
-    chol_solve<T, 3>(Kf, t);
+    sym_apply<T, 3>(Ki, t);
     T w[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) w[k] = V[k][0] * t[0] + V[k][1] * t[1] + V[k][2] * t[2];
-    split_solve<T>(Ls, Lk, w);
+    split_apply<T>(Ds, Dk, w);
 #pragma unroll
     for (int k = 0; k < 9; ++k) x[k] -= w[k];
+  } else {
+    split_apply<T>(Ds, Dk, x);
   }
 }
-// Coupled form, after the split factors of element i are stored and gbar
-// holds D^{-1} g: form and store the factor of K, and finish gbar = H^{-1} g.
+// Coupled form, after the split inverses of element i are stored and gbar
+// holds D^{-1} g: form and store K^{-1}, and finish gbar = H^{-1} g.
 template <typename T>
 DEV void coupled_finish(const DevMesh& d, int i) {
   const int m = d.m;
   T* Lf = (T*)d.Lf;
   T* gbar = (T*)d.gbar;
-  T Kf[6] = {T(1), T(0), T(1), T(0), T(0), T(1)};
+  T Ki[6] = {T(1), T(0), T(1), T(0), T(0), T(1)};
   if (fiber_scale(d, i) > 0.0) {
-    T Ls[21], Lk[6], V[9][3], W[9][3];
+    T Ds[21], Dk[6], V[9][3], W[9][3];
 #pragma unroll
-    for (int k = 0; k < 21; ++k) Ls[k] = Lf[k * m + i];
+    for (int k = 0; k < 21; ++k) Ds[k] = Lf[k * m + i];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) Lk[k] = Lf[(21 + k) * m + i];
+    for (int k = 0; k < 6; ++k) Dk[k] = Lf[(21 + k) * m + i];
     fiber_V<T>(d, i, V);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       T col[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) col[k] = V[k][c];
-      split_solve<T>(Ls, Lk, col);
+      split_apply<T>(Ds, Dk, col);
 #pragma unroll
       for (int k = 0; k < 9; ++k) W[k][c] = col[k];
     }
@@ -810,7 +842,9 @@ DEV void coupled_finish(const DevMesh& d, int i) {
     K[0][1] = K[1][0] = T(0.5) * (K[0][1] + K[1][0]);
     K[0][2] = K[2][0] = T(0.5) * (K[0][2] + K[2][0]);
     K[1][2] = K[2][1] = T(0.5) * (K[1][2] + K[2][1]);
+    T Kf[6];
     chol_packed<T, 3>(K, Kf);  // K >= I: positive definite
+    chol_inverse<T, 3>(Kf, Ki);
     T g[9], t[3];
 #pragma unroll
     for (int k = 0; k < 9; ++k) g[k] = gbar[k * m + i];
@@ -821,12 +855,12 @@ DEV void coupled_finish(const DevMesh& d, int i) {
       for (int k = 0; k < 9; ++k) v += V[k][c] * g[k];
       t[c] = v;
     }
-    chol_solve<T, 3>(Kf, t);
+    sym_apply<T, 3>(Ki, t);
 #pragma unroll
     for (int k = 0; k < 9; ++k) gbar[k * m + i] = g[k] - (W[k][0] * t[0] + W[k][1] * t[1] + W[k][2] * t[2]);
   }
 #pragma unroll
-  for (int k = 0; k < 6; ++k) Lf[(kLfSplit + k) * m + i] = Kf[k];
+  for (int k = 0; k < 6; ++k) Lf[(kLfSplit + k) * m + i] = Ki[k];
 }
 
 // ------------------------------------------------------------------ element data access
@@ -1015,6 +1049,11 @@ __global__ void __launch_bounds__(kBlock) k_rhs(DevMesh d, int add_pin, int chec
 // compute units; the rest use LPR = 8 (32 rows).  The vector the rows multiply
 // lives in LDS, loaded in chunks of kVecChunk.
 constexpr int kVecChunk = 1536;  // 36 KB of LDS: four workgroups per CU, and the merged root (<= 1536 wide) in one chunk
+// Levels whose supernodes are all narrow (no 32-lane rows, vectors of a few
+// hundred entries) run a variant with a 12 KB chunk and at most 64 VGPRs:
+// eight workgroups per CU instead of four, for levels whose short items are
+// bound by the latency of the frontal gather, not by bytes.
+constexpr int kVecChunkNarrow = kNarrowChunk;
 
 template <bool kFwd, int LPR>
 DEV void row_products(const double* __restrict__ V, int64_t base, int w, int h, int r0, int nrows,
@@ -1111,7 +1150,7 @@ DEV void gather_updates(const DevMesh& d, const SweepItem& it, int pos, double& 
   }
 }
 
-template <int LPR>
+template <int LPR, int CH>
 DEV void fwd_item(const DevMesh& d, const SweepItem& it, int r0, double* ft) {
   const int w = it.w, h = it.h, col0 = it.col0;
   const int t = threadIdx.x;
@@ -1130,8 +1169,8 @@ DEV void fwd_item(const DevMesh& d, const SweepItem& it, int r0, double* ft) {
     orow = d.dst[it.rowoff + r - w];
     gather_updates(d, it, r, b0, b1, b2);
   }
-  for (int vb = 0; vb < need; vb += kVecChunk) {
-    const int vl = min(kVecChunk, need - vb);
+  for (int vb = 0; vb < need; vb += CH) {
+    const int vl = min(CH, need - vb);
     __syncthreads();
     for (int k = t; k < vl; k += kBlock) {
       const int c = vb + k;
@@ -1157,7 +1196,8 @@ DEV void fwd_item(const DevMesh& d, const SweepItem& it, int r0, double* ft) {
     }
   }
 }
-DEV void b_fwd(const DevMesh& d, int bid, int check_done) {
+template <int CH>
+DEV void b_fwd_t(const DevMesh& d, int bid, int check_done) {
   // the item and the stop flag are read in the same scalar round trip (the
   // empty asm statement keeps the compiler from sinking the item load below
   // the flag test)
@@ -1165,28 +1205,37 @@ DEV void b_fwd(const DevMesh& d, int bid, int check_done) {
   const int done = check_done ? d.ctl->done : 0;
   __asm__ volatile("" ::"s"(it.first), "s"(done));
   if (done) return;
-  __shared__ double ft[kVecChunk * 3];
-  if (it.first & kItemWide) fwd_item<32>(d, it, it.first & ~kItemWide, ft);
-  else fwd_item<8>(d, it, it.first, ft);
+  __shared__ double ft[CH * 3];
+  if constexpr (CH == kVecChunk) {
+    if (it.first & kItemWide) {
+      fwd_item<32, CH>(d, it, it.first & ~kItemWide, ft);
+      return;
+    }
+  }
+  fwd_item<8, CH>(d, it, it.first, ft);
 }
+DEV void b_fwd(const DevMesh& d, int bid, int check_done) { b_fwd_t<kVecChunk>(d, bid, check_done); }
 // consecutive items of a level mostly belong to one supernode and read the
 // same input vector: keep them on one XCD
 __global__ void __launch_bounds__(kBlock) k_fwd(DevMesh d, int it0, int check_done) {
   b_fwd(d, it0 + xcd_block((int)blockIdx.x, (int)gridDim.x), check_done);
 }
+__global__ void __launch_bounds__(kBlock, 8) k_fwd_narrow(DevMesh d, int it0, int check_done) {
+  b_fwd_t<kVecChunkNarrow>(d, it0 + xcd_block((int)blockIdx.x, (int)gridDim.x), check_done);
+}
 
 // Backward sweep of one level with the transposed blocks.  Work item (s, c0):
 // columns [c0, c0 + 256/LPR) of supernode s.  With z = [y_s; -x[rows]],
 //   x_c = sum_{r >= c} L^{-T}-block[c][r - c] z[r].
-template <int LPR>
+template <int LPR, int CH>
 DEV void bwd_item(const DevMesh& d, const SweepItem& it, int c0, double* x, double* z) {
   const int w = it.w, h = it.h, col0 = it.col0;
   const int t = threadIdx.x;
   const int ncols = min(256 / LPR, w - c0);
   const int32_t* rows = d.rows + it.rowoff;
   double acc[3] = {0, 0, 0};
-  for (int vb = c0; vb < h; vb += kVecChunk) {
-    const int vl = min(kVecChunk, h - vb);
+  for (int vb = c0; vb < h; vb += CH) {
+    const int vl = min(CH, h - vb);
     __syncthreads();
     for (int k = t; k < vl; k += kBlock) {
       const int r = vb + k;
@@ -1213,17 +1262,42 @@ DEV void bwd_item(const DevMesh& d, const SweepItem& it, int c0, double* x, doub
     x[3 * (col0 + c) + 2] = acc[2];
   }
 }
-DEV void b_bwd(const DevMesh& d, int bid, double* x, int check_done) {
+template <int CH>
+DEV void b_bwd_t(const DevMesh& d, int bid, double* x, int check_done) {
   const SweepItem it = d.bwd_items[bid];
   const int done = check_done ? d.ctl->done : 0;
   __asm__ volatile("" ::"s"(it.first), "s"(done));
   if (done) return;
-  __shared__ double z[kVecChunk * 3];
-  if (it.first & kItemWide) bwd_item<32>(d, it, it.first & ~kItemWide, x, z);
-  else bwd_item<8>(d, it, it.first, x, z);
+  __shared__ double z[CH * 3];
+  if constexpr (CH == kVecChunk) {
+    if (it.first & kItemWide) {
+      bwd_item<32, CH>(d, it, it.first & ~kItemWide, x, z);
+      return;
+    }
+  }
+  bwd_item<8, CH>(d, it, it.first, x, z);
 }
+DEV void b_bwd(const DevMesh& d, int bid, double* x, int check_done) { b_bwd_t<kVecChunk>(d, bid, x, check_done); }
 __global__ void __launch_bounds__(kBlock) k_bwd(DevMesh d, int it0, double* x, int check_done) {
   b_bwd(d, it0 + xcd_block((int)blockIdx.x, (int)gridDim.x), x, check_done);
+}
+__global__ void __launch_bounds__(kBlock, 8) k_bwd_narrow(DevMesh d, int it0, double* x, int check_done) {
+  b_bwd_t<kVecChunkNarrow>(d, it0 + xcd_block((int)blockIdx.x, (int)gridDim.x), x, check_done);
+}
+
+// One level of each sweep, narrow or wide variant as the plan marks it.
+static void launch_fwd_level(const DevMesh& d, const SolvePlan& pl, int L, int check_done, hipStream_t st) {
+  const int n0 = pl.fwd_ptr[L], n1 = pl.fwd_ptr[L + 1];
+  if (n1 <= n0) return;
+  if (pl.fwd_narrow[L]) hipLaunchKernelGGL(k_fwd_narrow, dim3(n1 - n0), dim3(kBlock), 0, st, d, n0, check_done);
+  else hipLaunchKernelGGL(k_fwd, dim3(n1 - n0), dim3(kBlock), 0, st, d, n0, check_done);
+}
+static void launch_bwd_level(const DevMesh& d, const SolvePlan& pl, int k, double* x, int check_done,
+                             hipStream_t st) {
+  const int n0 = pl.bwd_ptr[k], n1 = pl.bwd_ptr[k + 1];
+  if (n1 <= n0) return;
+  if (pl.bwd_narrow[k]) hipLaunchKernelGGL(k_bwd_narrow, dim3(n1 - n0), dim3(kBlock), 0, st, d, n0, x, check_done);
+  else hipLaunchKernelGGL(k_bwd, dim3(n1 - n0), dim3(kBlock), 0, st, d, n0, x, check_done);
 }
 
 // q = solution at free vertices, pin targets at pinned vertices
@@ -1247,7 +1321,7 @@ __global__ void __launch_bounds__(kBlock) k_add_q(DevMesh d) { b_add_q(d, blockI
 // Accept the previous step (if sigma > 0): X = S + sigma D(p), R <- R polar(X),
 // S <- sym(polar(X)^T X).  Then at the new state: energy, exact gradient
 // G = vol P(F) + beta (F - A) (eq. gradient), the two clamped Hessian blocks
-// + beta I, their Cholesky factors and gbar = H^{-1} g.
+// + beta I, their inverses and gbar = H^{-1} g.
 template <typename T>
 DEV void b_element(const DevMesh& d, int bid) {
   Ctl* ctl = d.ctl;
@@ -1367,8 +1441,10 @@ DEV void b_element(const DevMesh& d, int bid) {
 }
 
 // Hessian blocks of the element pass: at the state left by b_element, the two
-// clamped blocks + beta I in the rotated basis (precision T), their Cholesky
-// factors, and gbar = H^{-1} g (g read from gbar, overwritten in place).
+// clamped blocks + beta I in the rotated basis (precision T), their inverses
+// (from their Cholesky factors), and gbar = H^{-1} g (g read from gbar,
+// overwritten in place).  The inverses are stored, not the factors: the Gram
+// pass needs them explicitly, and applying one is a matrix-vector product.
 // The two blocks at a stretch S with material scalars (vol mu, vol lhat,
 // a k_f): the element's own, or a bone's sums over its tets (the Hessian is
 // linear in vol mu and vol lhat at a fixed S).
@@ -1412,9 +1488,9 @@ DEV void hess_blocks(const DevMesh& d, int i, T (&Hs)[6][6], T (&Hk)[3][3], bool
 }
 
 // Both blocks are clamped to their positive semi-definite part, beta I is
-// added and the results factored; gbar = H^{-1} g in place.  The elements of
+// added and the results inverted; gbar = H^{-1} g in place.  The elements of
 // a workgroup are taken in rounds of kBlock; a 6x6 block that is not positive
-// definite (rare) is parked, lower triangle, in its factor's place and
+// definite (rare) is parked, lower triangle, in its inverse's place and
 // finished by thread 0 after the round with an LDS-resident Jacobi, so that
 // the eigen-decomposition holds no registers in the main loop.
 template <typename T, bool kC = false>
@@ -1445,14 +1521,15 @@ DEV void b_element_hess(const DevMesh& d, int bid) {
         T Ls[21];
         if (chol_packed<T, 6>(Hs, Ls)) {
           add_factor<T, 6>(Hs, beta, Ls);
-          T gs[6];
+          T Ps[21], gs[6];
+          chol_inverse<T, 6>(Ls, Ps);
 #pragma unroll
           for (int k = 0; k < 6; ++k) gs[k] = gbar[k * m + i];
-          chol_solve<T, 6>(Ls, gs);
+          sym_apply<T, 6>(Ps, gs);
 #pragma unroll
           for (int k = 0; k < 6; ++k) gbar[k * m + i] = gs[k];
 #pragma unroll
-          for (int k = 0; k < 21; ++k) Lf[k * m + i] = Ls[k];
+          for (int k = 0; k < 21; ++k) Lf[k * m + i] = Ps[k];
         } else {
 #pragma unroll
           for (int r = 0; r < 6; ++r)
@@ -1461,18 +1538,19 @@ DEV void b_element_hess(const DevMesh& d, int bid) {
           fix[atomicAdd(&nfix, 1)] = i;
         }
       }
-      T Lk[6];
+      T Lk[6], Pk[6];
       nclamp += clamp_add_factor<T, 3>(Hk, beta, Lk);
+      chol_inverse<T, 3>(Lk, Pk);
       T gk[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) gk[k] = gbar[(6 + k) * m + i];
-      chol_solve<T, 3>(Lk, gk);
+      sym_apply<T, 3>(Pk, gk);
 #pragma unroll
       for (int k = 0; k < 3; ++k) gbar[(6 + k) * m + i] = gk[k];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) Lf[(21 + k) * m + i] = Lk[k];
+      for (int k = 0; k < 6; ++k) Lf[(21 + k) * m + i] = Pk[k];
     } else if (i < m) {
-      // an affine bone tet: identity factors and gbar = 0, so that the Gram
+      // an affine bone tet: identity blocks and gbar = 0, so that the Gram
       // pass (which gives it weight 0) reads finite values; k_bone_blocks
       // then stores the bone's own block at its first tet
 #pragma unroll
@@ -1490,16 +1568,17 @@ DEV void b_element_hess(const DevMesh& d, int bid) {
 #pragma unroll 1
           for (int c = 0; c <= r; ++c) fixW[r][c] = fixW[c][r] = Lf[(r * (r + 1) / 2 + c) * m + j];
         clamp_psd_jacobi_lds<T, 6>(fixW, fixV);
-        T Ls[21];
+        T Ls[21], Ps[21];
         add_factor<T, 6>(fixW, (T)(d.alpha * d.w[j]), Ls);
+        chol_inverse<T, 6>(Ls, Ps);
         T gs[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) gs[k] = gbar[k * m + j];
-        chol_solve<T, 6>(Ls, gs);
+        sym_apply<T, 6>(Ps, gs);
 #pragma unroll
         for (int k = 0; k < 6; ++k) gbar[k * m + j] = gs[k];
 #pragma unroll
-        for (int k = 0; k < 21; ++k) Lf[k * m + j] = Ls[k];
+        for (int k = 0; k < 21; ++k) Lf[k * m + j] = Ps[k];
         ++nclamp;
       }
     }
@@ -1564,52 +1643,12 @@ DEV void gram_zblocks(const DevMesh& d, int i, int c, T* zr) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) R[k] = (T)d.R[k * m + i];
   const T* Lf = (const T*)d.Lf;
-  // explicit block inverses H^{-1} = L^{-T} L^{-1} (6x6 and 3x3, packed lower)
+  // the stored block inverses D^{-1} (6x6 and 3x3, packed lower)
   T Hs[21], Hk[6];
-  {
-    T Ls[21], Li[21];
 #pragma unroll
-    for (int k = 0; k < 21; ++k) Ls[k] = Lf[k * m + i];
+  for (int k = 0; k < 21; ++k) Hs[k] = Lf[k * m + i];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) Li[c * (c + 1) / 2 + c] = T(1) / Ls[c * (c + 1) / 2 + c];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-#pragma unroll
-      for (int r = c + 1; r < 6; ++r) {
-        T v = 0;
-#pragma unroll
-        for (int k = c; k < r; ++k) v += Ls[r * (r + 1) / 2 + k] * Li[k * (k + 1) / 2 + c];
-        Li[r * (r + 1) / 2 + c] = -v * Li[r * (r + 1) / 2 + r];
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < 6; ++r)
-#pragma unroll
-      for (int c = 0; c <= r; ++c) {
-        T v = 0;
-#pragma unroll
-        for (int k = r; k < 6; ++k) v += Li[k * (k + 1) / 2 + r] * Li[k * (k + 1) / 2 + c];
-        Hs[r * (r + 1) / 2 + c] = v;
-      }
-    T Lk[6], Lki[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) Lk[k] = Lf[(21 + k) * m + i];
-    Lki[0] = T(1) / Lk[0];
-    Lki[2] = T(1) / Lk[2];
-    Lki[5] = T(1) / Lk[5];
-    Lki[1] = -Lk[1] * Lki[0] * Lki[2];
-    Lki[4] = -Lk[4] * Lki[2] * Lki[5];
-    Lki[3] = -(Lk[3] * Lki[0] + Lk[4] * Lki[1]) * Lki[5];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int c = 0; c <= r; ++c) {
-        T v = 0;
-#pragma unroll
-        for (int k = r; k < 3; ++k) v += Lki[k * (k + 1) / 2 + r] * Lki[k * (k + 1) / 2 + c];
-        Hk[r * (r + 1) / 2 + c] = v;
-      }
-  }
+  for (int k = 0; k < 6; ++k) Hk[k] = Lf[(21 + k) * m + i];
   // coupled form: the full inverse blockdiag(D^{-1}) - W K^{-1} W^T in the
   // rotated (y) coordinates, packed lower, W = D^{-1} V
   [[maybe_unused]] T Hf[kC ? 45 : 1];
@@ -1631,17 +1670,12 @@ DEV void gram_zblocks(const DevMesh& d, int i, int c, T* zr) {
         }
         W[a][cc] = v;
       }
-    // K^{-1} from its stored factor
-    T Kf[6], Ki[3][3];
+    // K^{-1}, stored packed
+    T Ki[3][3];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) Kf[k] = Lf[(kLfSplit + k) * m + i];
+    for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int cc = 0; cc < 3; ++cc) {
-      T e[3] = {T(cc == 0), T(cc == 1), T(cc == 2)};
-      chol_solve<T, 3>(Kf, e);
-#pragma unroll
-      for (int r = 0; r < 3; ++r) Ki[r][cc] = e[r];
-    }
+      for (int cc = 0; cc <= r; ++cc) Ki[r][cc] = Ki[cc][r] = Lf[(kLfSplit + r * (r + 1) / 2 + cc) * m + i];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
       T u0 = W[a][0] * Ki[0][0] + W[a][1] * Ki[1][0] + W[a][2] * Ki[2][0];
@@ -2154,15 +2188,14 @@ DEV void b_uz(const DevMesh& d, int bid) {
 __global__ void __launch_bounds__(kBlock) k_uz(DevMesh d) { b_uz(d, blockIdx.x); }
 
 // Direction: d = gbar + alpha H^{-1} B^T z with B^T z = w Y^T vec(R^T G uz);
-// p = -d; g.p = (L^T gbar).(L^T p) per block; contributions of dF = R D(p).
+// p = -d; contributions of dF = R D(p).  (The Armijo slope g.p is the exact
+// linear coefficient of the line-search polynomial.)
 template <typename T, bool kC = false>
 DEV void b_direction(const DevMesh& d, int bid) {
   {
     const int i0 = xcd_block(bid, d.nb) * kBlock + threadIdx.x;
     if (stopped(d, i0 < d.m ? d.w[i0] : 0.0)) return;
   }
-  __shared__ DD sh[kBlock];
-  DD acc[1] = {DD{0, 0}};
   const int m = d.m;
   const T* Lf = (const T*)d.Lf;
   const T* gbar = (const T*)d.gbar;
@@ -2176,59 +2209,27 @@ DEV void b_direction(const DevMesh& d, int bid) {
     matTmul3(R, Az, RA);
     T ty[9];
     to_y<T, double>(RA, ty);
-    T Ls[21], Lk[6], gb[9];
+    T Ds[21], Dk[6], gb[9];
 #pragma unroll
-    for (int k = 0; k < 21; ++k) Ls[k] = Lf[k * m + i];
+    for (int k = 0; k < 21; ++k) Ds[k] = Lf[k * m + i];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) Lk[k] = Lf[(21 + k) * m + i];
+    for (int k = 0; k < 6; ++k) Dk[k] = Lf[(21 + k) * m + i];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       gb[k] = gbar[k * m + i];
       ty[k] *= (T)e.w;
     }
-    hinv_apply<T, kC>(d, i, Ls, Lk, ty);
+    hinv_apply<T, kC>(d, i, Ds, Dk, ty);
     double p[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       p[k] = -((double)gb[k] + d.alpha * (double)ty[k]);
       d.p[k * m + i] = p[k];
     }
-    // g . p
-    T pt[9], a1[9], a2[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) pt[k] = (T)p[k];
-    chol_lt_mul<T, 6>(Ls, gb, a1);
-    chol_lt_mul<T, 3>(Lk, gb + 6, a1 + 6);
-    chol_lt_mul<T, 6>(Ls, pt, a2);
-    chol_lt_mul<T, 3>(Lk, pt + 6, a2 + 6);
-    double gp = 0;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) gp += (double)a1[k] * (double)a2[k];
-    if constexpr (kC) {
-      // g = (L L^T + V V^T) gbar: add (V^T gbar) . (V^T p)
-      T V[9][3];
-      fiber_V<T>(d, i, V);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        T vg = 0, vp = 0;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-          vg += V[k][c] * gb[k];
-          vp += V[k][c] * pt[k];
-        }
-        gp += (double)vg * (double)vp;
-      }
-    }
-    acc[0] = dd_add_d(acc[0], gp);
     double D[9], dF[9];
     from_y<double>(p, D);
     matmul3(R, D, dF);
     write_contrib(d, i, e, dF);
-  }
-  block_reduce_dd<1>(acc, sh);
-  if (threadIdx.x == 0) {
-    d.part_ls[2 * kLsTerms * bid + 12] = acc[0].hi;
-    d.part_ls[2 * kLsTerms * bid + 13] = acc[0].lo;
   }
 }
 template <typename T, bool kC = false>
@@ -2244,11 +2245,11 @@ __global__ void __launch_bounds__(kBlock) k_direction(DevMesh d) { b_direction<T
 //                   + alpha sum_i w_i I  (d2Psi is linear in vol mu and vol lhat
 //                   at a fixed S; bone tets are passive)
 //   low rank  B_b = sum_i B_i, i.e. Gamma_b[j] = sum_i w_i gphi_j(i)
-// The bone's factor and gbar_b sit at its representative tet (its first in
-// element order).  The per-element passes leave bone tets out (the element
-// pass keeps their gradients aside and out of the norm, the Hessian pass skips
-// them, the Gram pass weights them 0, the direction pass leaves them to
-// k_bone_dir).  One workgroup per bone, a fixed assignment of its tets to
+// The bone's block inverses and gbar_b sit at its representative tet (its
+// first in element order).  The per-element passes leave bone tets out (the
+// element pass keeps their gradients aside and out of the norm, the Hessian
+// pass writes identity blocks for them, the Gram pass weights them 0, the
+// direction pass leaves them to k_bone_dir).  One workgroup per bone, a fixed assignment of its tets to
 // threads and fixed-order sums; its partial sums take the slots after the
 // element workgroups'.
 constexpr int kBoneSums = 9 + 3 * kMaxK1 + 3;  // g, Gamma, vol mu, vol lhat, w
@@ -2322,21 +2323,22 @@ __global__ void __launch_bounds__(kBlock) k_bone_blocks(DevMesh d) {
     T Hs[6][6], Hk[3][3];
     hess_blocks_s<T>(S, tot[kBoneSums - 3], tot[kBoneSums - 2], 0.0, u, Hs, Hk);
     const T beta = (T)(d.alpha * tot[kBoneSums - 1]);
-    T Ls[21], Lk[6];
+    T Ls[21], Lk[6], Ds[21], Dk[6];
     const int ncl = clamp_add_factor<T, 6>(Hs, beta, Ls) + clamp_add_factor<T, 3>(Hk, beta, Lk);
+    chol_inverse<T, 6>(Ls, Ds);
+    chol_inverse<T, 3>(Lk, Dk);
     T gy[9];
     double g2 = 0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       gy[k] = (T)tot[k];
       g2 += tot[k] * tot[k];
-      d.bone_g[9 * b + k] = tot[k];
     }
-    split_solve<T>(Ls, Lk, gy);
+    split_apply<T>(Ds, Dk, gy);
 #pragma unroll
-    for (int k = 0; k < 21; ++k) Lf[k * m + rep] = Ls[k];
+    for (int k = 0; k < 21; ++k) Lf[k * m + rep] = Ds[k];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) Lf[(21 + k) * m + rep] = Lk[k];
+    for (int k = 0; k < 6; ++k) Lf[(21 + k) * m + rep] = Dk[k];
 #pragma unroll
     for (int k = 0; k < 9; ++k) gbar[k * m + rep] = gy[k];
     const int slot = d.nb + b;
@@ -2381,8 +2383,7 @@ __global__ void __launch_bounds__(kBlock) k_bone_blocks(DevMesh d) {
 
 // The bone's step p_b = -(gbar_b + alpha H_b^{-1} R_b^T sum_i w_i A_z(i)) (A_z:
 // the compatible gradient of Phi^T z at tet i), copied to every bone tet with
-// its ACAP right-hand-side contribution; the bone's g . p into its line-search
-// slot (whose polynomial coefficients are zero).
+// its ACAP right-hand-side contribution.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_bone_dir(DevMesh d) {
   if (d.ctl->done) return;
@@ -2412,24 +2413,15 @@ __global__ void __launch_bounds__(kBlock) k_bone_dir(DevMesh d) {
     matTmul3(R, u, RA);
     const T* Lf = (const T*)d.Lf;
     const T* gbar = (const T*)d.gbar;
-    T Ls[21], Lk[6], ty[9];
+    T Ds[21], Dk[6], ty[9];
 #pragma unroll
-    for (int k = 0; k < 21; ++k) Ls[k] = Lf[k * m + rep];
+    for (int k = 0; k < 21; ++k) Ds[k] = Lf[k * m + rep];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) Lk[k] = Lf[(21 + k) * m + rep];
+    for (int k = 0; k < 6; ++k) Dk[k] = Lf[(21 + k) * m + rep];
     to_y<T, double>(RA, ty);
-    split_solve<T>(Ls, Lk, ty);
-    double gp = 0;
+    split_apply<T>(Ds, Dk, ty);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      pb[k] = -((double)gbar[k * m + rep] + d.alpha * (double)ty[k]);
-      gp += d.bone_g[9 * b + k] * pb[k];
-    }
-    double* ls = d.part_ls + 2 * kLsTerms * (d.nb + b);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) ls[k] = 0.0;
-    ls[12] = gp;
-    ls[13] = 0.0;
+    for (int k = 0; k < 9; ++k) pb[k] = -((double)gbar[k * m + rep] + d.alpha * (double)ty[k]);
   }
   __syncthreads();
   double D[9], R[9], dF[9];
@@ -2539,7 +2531,7 @@ DEV void b_control_b(const DevMesh& d, int bid) {
   DD acc[kLsTerms];
 #pragma unroll
   for (int k = 0; k < kLsTerms; ++k) acc[k] = DD{0, 0};
-  for (int b = t; b < d.nb + d.nbones; b += kBlock)
+  for (int b = t; b < d.nb; b += kBlock)
 #pragma unroll
     for (int k = 0; k < kLsTerms; ++k)
       acc[k] = dd_add(acc[k], DD{d.part_ls[2 * kLsTerms * b + 2 * k], d.part_ls[2 * kLsTerms * b + 2 * k + 1]});
@@ -2547,11 +2539,11 @@ DEV void b_control_b(const DevMesh& d, int bid) {
   if (t != 0) return;
   double c[6];
   for (int k = 0; k < 6; ++k) c[k] = acc[k].hi + acc[k].lo;
-  // Slope of the Armijo test.  FP64: g . p from the direction pass.  Mixed:
-  // that dot product is taken in FP32 (gbar, factors, p), so the exact FP64
-  // directional derivative dE/dsigma at 0, the linear coefficient c[0] of the
-  // energy polynomial, is used instead: the decision stays FP64 (form (1)).
-  const double gtp = d.mixed ? c[0] : acc[6].hi + acc[6].lo;
+  // Slope of the Armijo test: the directional derivative g . p = dE/dsigma at
+  // 0, which is the linear coefficient c[0] of the energy polynomial (the
+  // ACAP term's change through q cancels at q*).  It is an FP64 double-double
+  // sum in both precisions, so the decision stays FP64 (form (1)).
+  const double gtp = c[0];
   ctl->gtp = gtp;
   ctl->solves += 1;
   const double g2 = ctl->gnorm2, g02 = ctl->gnorm0_2;
@@ -3020,24 +3012,12 @@ void launch_scatter_F(const DevMesh& d, hipStream_t st) {
 }
 void launch_solve(const DevMesh& d, const SolvePlan& pl, int add_pin, double* x, int check_done, hipStream_t st) {
   hipLaunchKernelGGL(k_rhs, dim3(rhs_blocks(d.nf)), dim3(kBlock), 0, st, d, add_pin, check_done);
-  for (int L = 0; L < pl.nlevels; ++L) {
-    int n0 = pl.fwd_ptr[L], n1 = pl.fwd_ptr[L + 1];
-    if (n1 > n0) hipLaunchKernelGGL(k_fwd, dim3(n1 - n0), dim3(kBlock), 0, st, d, n0, check_done);
-  }
-  for (int L = 0; L < pl.nlevels; ++L) {
-    int n0 = pl.bwd_ptr[L], n1 = pl.bwd_ptr[L + 1];
-    if (n1 > n0) hipLaunchKernelGGL(k_bwd, dim3(n1 - n0), dim3(kBlock), 0, st, d, n0, x, check_done);
-  }
+  for (int L = 0; L < pl.nlevels; ++L) launch_fwd_level(d, pl, L, check_done, st);
+  for (int L = 0; L < pl.nlevels; ++L) launch_bwd_level(d, pl, L, x, check_done, st);
 }
 void launch_sweeps(const DevMesh& d, const SolvePlan& pl, double* x, hipStream_t st) {
-  for (int L = 0; L < pl.nlevels; ++L) {
-    int n0 = pl.fwd_ptr[L], n1 = pl.fwd_ptr[L + 1];
-    if (n1 > n0) hipLaunchKernelGGL(k_fwd, dim3(n1 - n0), dim3(kBlock), 0, st, d, n0, 0);
-  }
-  for (int L = 0; L < pl.nlevels; ++L) {
-    int n0 = pl.bwd_ptr[L], n1 = pl.bwd_ptr[L + 1];
-    if (n1 > n0) hipLaunchKernelGGL(k_bwd, dim3(n1 - n0), dim3(kBlock), 0, st, d, n0, x, 0);
-  }
+  for (int L = 0; L < pl.nlevels; ++L) launch_fwd_level(d, pl, L, 0, st);
+  for (int L = 0; L < pl.nlevels; ++L) launch_bwd_level(d, pl, L, x, 0, st);
 }
 void launch_field_solve(const DevMesh& d, const SolvePlan& pl, const double* V, double* x, hipStream_t st) {
   hipLaunchKernelGGL(k_contrib_field, dim3(blocks(d.m)), dim3(kBlock), 0, st, d, V);
@@ -3131,16 +3111,10 @@ void launch_class(int k, const DevMesh& d, const SolvePlan& pl, hipStream_t st) 
       break;
     case 6: hipLaunchKernelGGL(k_rhs, dim3(rhs_blocks(d.nf)), dim3(kBlock), 0, st, d, 0, 1); break;
     case 7:
-      for (int L = 0; L < pl.nlevels; ++L) {
-        int n0 = pl.fwd_ptr[L], n1 = pl.fwd_ptr[L + 1];
-        if (n1 > n0) hipLaunchKernelGGL(k_fwd, dim3(n1 - n0), dim3(kBlock), 0, st, d, n0, 1);
-      }
+      for (int L = 0; L < pl.nlevels; ++L) launch_fwd_level(d, pl, L, 1, st);
       break;
     case 8:
-      for (int L = 0; L < pl.nlevels; ++L) {
-        int n0 = pl.bwd_ptr[L], n1 = pl.bwd_ptr[L + 1];
-        if (n1 > n0) hipLaunchKernelGGL(k_bwd, dim3(n1 - n0), dim3(kBlock), 0, st, d, n0, d.dq, 1);
-      }
+      for (int L = 0; L < pl.nlevels; ++L) launch_bwd_level(d, pl, L, d.dq, 1, st);
       break;
     case 9: hipLaunchKernelGGL(k_lscoef, dim3(d.nb), dim3(kBlock), 0, st, d); break;
     case 10: hipLaunchKernelGGL(k_control_b, dim3(1), dim3(kBlock), 0, st, d); break;

@@ -20,6 +20,9 @@ namespace emu {
 struct SolvePlan {
   int nlevels = 0;
   std::vector<int> fwd_ptr, bwd_ptr;
+  // per level: every item is short (8 lanes per row, one vector chunk of
+  // kNarrowChunk), so the level runs the 8-waves-per-SIMD variant
+  std::vector<char> fwd_narrow, bwd_narrow;
 };
 
 // Launch layout of one iteration over several meshes (same precision): for
