@@ -35,6 +35,7 @@ import math
 import numpy as np
 import scipy.linalg as sla
 
+from . import contact as cnt
 from . import material as mat
 from . import mesh as msh
 
@@ -224,18 +225,23 @@ def gradient_norm(M, F, a_el):
 
 
 def solve(M, a, F0=None, tol=1e-8, max_iters=5000, sigma0=10.0, armijo_c=1e-4, rho=0.5,
-          min_sigma_exp=40, hessian="full", trials="fresh", history=False, callback=None):
+          min_sigma_exp=40, hessian="full", trials="fresh", history=False, callback=None, contact=None):
     """Run the EMU quasi-Newton iteration from F0 (rest if None) to |g|_2 <= tol.
 
     ``trials="fresh"`` re-solves the ACAP problem for every line-search trial as
     Algorithm 1 does.  ``trials="affine"`` uses that q*(F) is affine in F: one
     homogeneous solve of the direction gives q(sigma) = q + sigma dq for every
     trial -- the same values without the rounding noise of differencing two
-    independent solves, which sets a floor near 1e-10 on tiny meshes."""
+    independent solves, which sets a floor near 1e-10 on tiny meshes.
+
+    ``contact`` (``oracle.contact.obstacles(...)``) runs Algorithm 1's contact
+    loop after every accepted step with the iteration's Woodbury inverse."""
     a_el = msh.activation_per_element(M, a)
     F = rest_state(M) if F0 is None else np.array(F0, dtype=np.float64)
     hist = []
-    stats = dict(iters=0, trials=0, solves=0, converged=False, status="ok")
+    stats = dict(iters=0, trials=0, solves=0, converged=False, status="ok", contact_rounds=0)
+    if contact is not None and M.red_of is not None:
+        raise ValueError("the contact loop runs on per-tet variables")
     q = msh.acap_solve(M, F)
     stats["solves"] += 1
     while True:
@@ -296,6 +302,9 @@ def solve(M, a, F0=None, tol=1e-8, max_iters=5000, sigma0=10.0, armijo_c=1e-4, r
             stats["status"] = "linesearch"
             break
         F, q = Ft, qt
+        if contact is not None:
+            F, q, rounds = cnt.contact_loop(M, F, q, lambda nu: direction(M, H, nu), contact)
+            stats["contact_rounds"] += rounds
         stats["iters"] += 1
         if history:
             hist[-1]["sigma"] = sigma
