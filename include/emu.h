@@ -166,6 +166,7 @@ typedef struct {
      direction (eq. acap: right-hand side and triangular sweeps), line search
      (Algorithm 1: polynomial coefficients, Armijo test, q update) */
   double ms_elem, ms_woodbury, ms_solve, ms_linesearch;
+  int32_t contact_rounds;    /* contact rounds run (emu_set_contact), all steps  */
 } emu_solve_stats;
 
 /* Static information about a mesh. */
@@ -206,6 +207,40 @@ emu_status emu_set_pin_targets(emu_mesh* mesh, const double* pin_xyz);
    order, copied; forces at pinned vertices do no work; NULL removes the
    forces.  EMU_E_INVALID for non-finite entries. */
 emu_status emu_set_external_forces(emu_mesh* mesh, const double* f);
+
+/* Contact (Sec. 3.5, the collision block of Algorithm 1).  With obstacles
+   set, every emu_solve runs, after each accepted quasi-Newton step, rounds of:
+   the penalty forces f of the free vertices of q that penetrate an obstacle;
+   the step F <- F + Htilde^{-1} nu(f), where nu(f) = w G L_ff^{-1} f is the
+   F-gradient of the work f . q*(F) (as for external forces) and Htilde^{-1}
+   the step's own Woodbury inverse; q <- q*(F).  The rounds stop once
+   |f|_2 <= tol or after max_rounds.  The collision method the paper cites is
+   not described in it: analytic obstacles stand in for the colliding bodies.
+   A round moves a vertex by about its compliance C times the force, so the
+   rounds converge for k C < 1 and overshoot for stiffer penalties.  Contact
+   forces are not part of the energy: with active contacts the iteration
+   balances the quasi-Newton step against the push-out and |g| stays away from
+   0; emu_solve then ends at max_iters (EMU_E_NOT_CONVERGED, state kept).
+   Iterations with contact run one per launch; the phase times report 0.
+   Not available with affine bones.  NULL (or no obstacles) removes contact.
+   EMU_E_INVALID: counts outside [0, EMU_MAX_OBSTACLES] in total, a normal
+   that is not unit length (within 1e-9), r <= 0, k <= 0, tol < 0,
+   max_rounds < 1, non-finite values, affine bones. */
+#define EMU_MAX_OBSTACLES 64
+typedef struct {
+  int32_t n_planes;          /* half-spaces: host rows (nx, ny, nz, b), |n| = 1;
+                                x penetrates where n . x < b by b - n . x and is
+                                pushed along n                                 */
+  const double* planes;      /* [n_planes][4]                                   */
+  int32_t n_spheres;         /* spheres: host rows (cx, cy, cz, r), r > 0; x
+                                penetrates where |x - c| < r by r - |x - c| and
+                                is pushed along (x - c) / |x - c|              */
+  const double* spheres;     /* [n_spheres][4]                                  */
+  double stiffness;          /* penalty k > 0: force k * depth (N/m)            */
+  double tol;                /* |f|_2 (N) at which a contact loop stops          */
+  int32_t max_rounds;        /* rounds per accepted step (>= 1)                 */
+} emu_contact_desc;
+emu_status emu_set_contact(emu_mesh* mesh, const emu_contact_desc* desc);
 
 /* Replace the low-rank modes (eq. low-rank): k1 = k/3 scalar modes, nu host
    [k1] > 0, phi host [k1][n] (values at pinned vertices are ignored). */

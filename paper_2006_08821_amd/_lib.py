@@ -48,7 +48,7 @@ class SolveStats(C.Structure):
                 ("acap_solves", C.c_int32), ("inverted", C.c_int32), ("clamped", C.c_int32),
                 ("energy", C.c_double), ("grad_norm", C.c_double), ("grad_norm0", C.c_double),
                 ("ms_total", C.c_double), ("ms_elem", C.c_double), ("ms_woodbury", C.c_double),
-                ("ms_solve", C.c_double), ("ms_linesearch", C.c_double)]
+                ("ms_solve", C.c_double), ("ms_linesearch", C.c_double), ("contact_rounds", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -68,6 +68,11 @@ class MeshInfo(C.Structure):
 class ServerOpts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_slots", C.c_int32),
                 ("setup_threads", C.c_int32), ("iters_per_round", C.c_int32)]
+
+
+class ContactDesc(C.Structure):
+    _fields_ = [("n_planes", C.c_int32), ("planes", DP), ("n_spheres", C.c_int32), ("spheres", DP),
+                ("stiffness", C.c_double), ("tol", C.c_double), ("max_rounds", C.c_int32)]
 
 
 class RequestTimes(C.Structure):
@@ -97,6 +102,7 @@ SIGNATURES = {
     "emu_set_activation": (C.c_int, [P, DP]),
     "emu_set_pin_targets": (C.c_int, [P, DP]),
     "emu_set_external_forces": (C.c_int, [P, DP]),
+    "emu_set_contact": (C.c_int, [P, C.POINTER(ContactDesc)]),
     "emu_set_modes": (C.c_int, [P, C.c_int32, DP, DP]),
     "emu_get_modes": (C.c_int, [P, DP, DP]),
     "emu_solve": (C.c_int, [P, C.POINTER(SolveOpts), P, C.POINTER(SolveStats), P]),

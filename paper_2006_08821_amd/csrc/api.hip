@@ -633,6 +633,120 @@ emu_status emu_set_external_forces(emu_mesh* M, const double* f) {
   }
 }
 
+namespace {
+// Work arrays of the contact rounds, carved from M->c_work.
+struct ContactWork {
+  double *x, *x2, *nu, *z, *zc, *scr, *ypart, *part, *fpart;
+};
+size_t contact_work_doubles(const emu_mesh* M) {
+  const size_t n = M->hm.n, m = M->hm.m, nb = M->d.nb;
+  return 6 * n + 36 * m + 50 * nb + (size_t)std::max(1, emu::contact_blocks(M->d));
+}
+ContactWork contact_carve(emu_mesh* M) {
+  const size_t n = M->hm.n, m = M->hm.m, nb = M->d.nb;
+  ContactWork w;
+  double* p = M->c_work;
+  w.x = p;
+  p += 3 * n;
+  w.x2 = p;
+  p += 3 * n;
+  w.nu = p;
+  p += 9 * m;
+  w.z = p;
+  p += 9 * m;
+  w.zc = p;
+  p += 9 * m;
+  w.scr = p;
+  p += 9 * m;
+  w.ypart = p;
+  p += 48 * nb;
+  w.part = p;
+  p += 2 * nb;
+  w.fpart = p;
+  return w;
+}
+// Algorithm 1's contact rounds after one accepted step (q already holds
+// q*(F + sigma P); the step itself is still pending in (R, S, p, sigma)).
+void contact_rounds(emu_mesh* M) {
+  const emu::DevMesh& d = M->d;
+  ContactWork w = contact_carve(M);
+  const int nbv = std::max(1, emu::contact_blocks(d));
+  int r = 0;
+  for (; r < M->c_max_rounds; ++r) {
+    emu::launch_contact_force(d, M->c_obs, M->c_np, M->c_ns, M->c_k, w.fpart, M->st);
+    HIPCHK(hipMemcpyAsync(M->c_host, w.fpart, 8 * (size_t)nbv, hipMemcpyDeviceToHost, M->st));
+    HIPCHK(hipStreamSynchronize(M->st));
+    double f2 = 0;
+    for (int b = 0; b < nbv; ++b) f2 += M->c_host[b];
+    if (!(std::sqrt(f2) > M->c_tol)) break;
+    if (r == 0) HIPCHK(hipMemsetAsync(w.zc, 0, 72 * (size_t)M->hm.m, M->st));
+    emu::launch_sweeps(d, M->plan, w.x, M->st);                                // x = L_ff^{-1} f
+    emu::launch_weighted_grad(d, w.x, w.nu, M->st);                            // nu = w G x
+    emu::launch_precond(d, w.nu, w.z, w.ypart, w.part, w.scr, M->st);          // z = Htilde^{-1} nu
+    emu::launch_field_solve(d, M->plan, w.z, w.x2, M->st);                     // x2 = L^{-1} G^T W z
+    emu::launch_contact_accum(d, w.x2, w.z, w.zc, M->st);                      // q += x2, zc += z
+  }
+  if (r > 0) emu::launch_accept_contact(d, w.zc, M->st);
+  HIPCHK(hipGetLastError());
+  M->c_rounds += r;
+}
+}  // namespace
+
+emu_status emu_set_contact(emu_mesh* M, const emu_contact_desc* c) {
+  if (!M) {
+    emu::set_error("NULL argument");
+    return EMU_E_INVALID;
+  }
+  try {
+    const int np = c ? c->n_planes : 0, ns = c ? c->n_spheres : 0;
+    if (np < 0 || ns < 0 || np + ns > EMU_MAX_OBSTACLES)
+      throw emu::Error{EMU_E_INVALID, "obstacle counts must be in [0, EMU_MAX_OBSTACLES]"};
+    if (np + ns == 0) {
+      M->c_np = M->c_ns = 0;
+      return EMU_OK;
+    }
+    if (M->d.nbones > 0) throw emu::Error{EMU_E_INVALID, "contact is not available with affine bones"};
+    if ((np > 0 && !c->planes) || (ns > 0 && !c->spheres)) throw emu::Error{EMU_E_INVALID, "NULL obstacle rows"};
+    if (!(c->stiffness > 0) || !std::isfinite(c->stiffness)) throw emu::Error{EMU_E_INVALID, "stiffness must be > 0"};
+    if (!(c->tol >= 0) || !std::isfinite(c->tol)) throw emu::Error{EMU_E_INVALID, "tol must be >= 0"};
+    if (c->max_rounds < 1) throw emu::Error{EMU_E_INVALID, "max_rounds must be >= 1"};
+    std::vector<double> rows(4 * (size_t)(np + ns));
+    for (int o = 0; o < np; ++o) {
+      const double* P = c->planes + 4 * o;
+      for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(P[k])) throw emu::Error{EMU_E_INVALID, "non-finite plane"};
+      if (std::abs(std::sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2]) - 1.0) > 1e-9)
+        throw emu::Error{EMU_E_INVALID, "plane normals must have unit length"};
+      std::copy(P, P + 4, rows.begin() + 4 * o);
+    }
+    for (int o = 0; o < ns; ++o) {
+      const double* Q = c->spheres + 4 * o;
+      for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(Q[k])) throw emu::Error{EMU_E_INVALID, "non-finite sphere"};
+      if (!(Q[3] > 0)) throw emu::Error{EMU_E_INVALID, "sphere radii must be > 0"};
+      std::copy(Q, Q + 4, rows.begin() + 4 * (np + o));
+    }
+    HIPCHK(hipStreamSynchronize(M->st));
+    if (!M->c_obs) {
+      M->c_obs = M->dalloc<double>(4 * (size_t)EMU_MAX_OBSTACLES);
+      const size_t nw = contact_work_doubles(M);
+      M->c_work = M->dalloc<double>(nw);
+      HIPCHK(hipMemset(M->c_work, 0, 8 * nw));  // the pinned rows of x and x2 stay 0
+      HIPCHK(hipHostMalloc((void**)&M->c_host, 8 * (size_t)std::max(1, emu::contact_blocks(M->d))));
+    }
+    HIPCHK(hipMemcpy(M->c_obs, rows.data(), 8 * rows.size(), hipMemcpyHostToDevice));
+    M->c_np = np;
+    M->c_ns = ns;
+    M->c_k = c->stiffness;
+    M->c_tol = c->tol;
+    M->c_max_rounds = c->max_rounds;
+    M->converged = false;
+    return EMU_OK;
+  } catch (const emu::Error& e) {
+    return fail_with(e);
+  }
+}
+
 emu_status emu_set_modes(emu_mesh* M, int32_t k1, const double* nu, const double* phi) {
   if (!M || (k1 > 0 && (!nu || !phi))) {
     emu::set_error("NULL argument");
@@ -696,9 +810,10 @@ emu_status emu_solve(emu_mesh* M, const emu_solve_opts* opts, double* q_out, emu
     if (!o.warm_start) emu::launch_init_rest(M->d, M->st);
     init_ctl(M, o, 0);
     fresh_solve(M);
+    M->c_rounds = 0;
     const int max_launch = o.max_iters / per + 2;
     double phase_ms[4] = {0, 0, 0, 0};
-    if (o.phase_timing) {
+    if (o.phase_timing && M->c_np + M->c_ns == 0) {
       // the same kernels launched one by one, with events between the phases
       if ((int)M->t_ev.size() < 5 * per) {
         const size_t have = M->t_ev.size();
@@ -715,6 +830,15 @@ emu_status emu_solve(emu_mesh* M, const emu_solve_opts* opts, double* q_out, emu
             phase_ms[ph] += ms;
           }
         if (M->h_ctl->done) break;
+      }
+    } else if (M->c_np + M->c_ns > 0) {
+      // contact: the rounds follow every accepted step (one iteration per launch)
+      ensure_graph(M, 1);
+      for (int k = 0; k < o.max_iters + 2; ++k) {
+        HIPCHK(hipGraphLaunch(M->gexec, M->st));
+        read_ctl(M);
+        if (M->h_ctl->done) break;
+        contact_rounds(M);
       }
     } else {
       ensure_graph(M, per);
@@ -740,6 +864,7 @@ emu_status emu_solve(emu_mesh* M, const emu_solve_opts* opts, double* q_out, emu
     emu::fill_stats(*M->h_ctl, stats, ms);
     if (stats) {
       stats->energy -= M->ext_c0;
+      stats->contact_rounds = M->c_rounds;
       stats->ms_elem = phase_ms[0];
       stats->ms_woodbury = phase_ms[1];
       stats->ms_solve = phase_ms[2];
@@ -962,7 +1087,7 @@ emu_status adjoint_run(emu_mesh* M, const AdjWork& w, const double* dL_dq, doubl
   HIPCHK(hipMemsetAsync(w.lam, 0, 9 * m * 8, M->st));
   HIPCHK(hipMemsetAsync(w.hp, 0, 9 * m * 8, M->st));
   // preconditioned conjugate gradients on d2E/dF2 lam = b
-  emu::launch_precond(d, w.r, w.z, w.ypart, w.part, M->st);
+  emu::launch_precond(d, w.r, w.z, w.ypart, w.part, d.p, M->st);
   double rz = host_dd_sum(M, w.part, d.nb);
   HIPCHK(hipMemcpyAsync(w.p, w.z, 9 * m * 8, hipMemcpyDeviceToDevice, M->st));
   // |b| for the relative stopping test
@@ -986,7 +1111,7 @@ emu_status adjoint_run(emu_mesh* M, const AdjWork& w, const double* dL_dq, doubl
     rnorm = std::sqrt(std::max(0.0, host_dd_sum(M, w.part, d.nb)));
     ++it;
     if (rnorm <= tol) break;
-    emu::launch_precond(d, w.r, w.z, w.ypart, w.part, M->st);
+    emu::launch_precond(d, w.r, w.z, w.ypart, w.part, d.p, M->st);
     const double rz2 = host_dd_sum(M, w.part, d.nb);
     const double beta = rz2 / rz;
     rz = rz2;

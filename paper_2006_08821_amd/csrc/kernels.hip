@@ -1317,6 +1317,46 @@ DEV void b_add_q(const DevMesh& d, int bid) {
 }
 __global__ void __launch_bounds__(kBlock) k_add_q(DevMesh d) { b_add_q(d, blockIdx.x); }
 
+// Accept a step at element i: X = S + sigma D(p) (plus R^T Zc_i, a world-frame
+// field such as the contact step, with kZc), R <- R polar(X) (re-orthonormalized),
+// S <- polar(X)^T X; R and S are updated in memory and in place.
+template <bool kZc>
+DEV void accept_elem(const DevMesh& d, int i, double sigma, const double* zc, double (&R)[9], double (&S)[9]) {
+  const int m = d.m;
+  double py[9], D[9], X[9], Rx[9], Rn[9], Sn[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) py[k] = d.p[k * m + i];
+  from_y<double>(py, D);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) X[k] = S[k] + sigma * D[k];
+  if constexpr (kZc) {
+    double Z[9], RZ[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Z[k] = zc[k * m + i];
+    matTmul3(R, Z, RZ);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) X[k] += RZ[k];
+  }
+  if (!polar3_newton(X, Rx)) {
+    const Mat3 r = polar3_fallback(load_mat3(X));
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rx[k] = r.v[k];
+  }
+  matmul3(R, Rx, Rn);
+  reorthonormalize(Rn);
+  matTmul3(Rx, X, Sn);
+  double sy[9];
+  to_y<double, double>(Sn, sy);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    R[k] = Rn[k];
+    d.R[k * m + i] = Rn[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) d.S[k * m + i] = sy[k];
+  s_from6(sy, S);
+}
+
 // --------------------------------------------------------------- element pass
 // Accept the previous step (if sigma > 0): X = S + sigma D(p), R <- R polar(X),
 // S <- sym(polar(X)^T X).  Then at the new state: energy, exact gradient
@@ -1341,32 +1381,7 @@ DEV void b_element(const DevMesh& d, int bid) {
     double R[9], S[9];
     load_R(d, i, R);
     load_S(d, i, S);
-    if (sigma != 0.0) {
-      double py[9], D[9], X[9], Rx[9], Rn[9], Sn[9];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) py[k] = d.p[k * m + i];
-      from_y<double>(py, D);
-#pragma unroll
-      for (int k = 0; k < 9; ++k) X[k] = S[k] + sigma * D[k];
-      if (!polar3_newton(X, Rx)) {
-        const Mat3 r = polar3_fallback(load_mat3(X));
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Rx[k] = r.v[k];
-      }
-      matmul3(R, Rx, Rn);
-      reorthonormalize(Rn);
-      matTmul3(Rx, X, Sn);
-      double sy[9];
-      to_y<double, double>(Sn, sy);
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        R[k] = Rn[k];
-        d.R[k * m + i] = Rn[k];
-      }
-#pragma unroll
-      for (int k = 0; k < 6; ++k) d.S[k * m + i] = sy[k];
-      s_from6(sy, S);
-    }
+    if (sigma != 0.0) accept_elem<false>(d, i, sigma, nullptr, R, S);
     double A[9], At[9];
     gather_grad(d.q, e, A);
     matTmul3(R, A, At);
@@ -2620,6 +2635,71 @@ __global__ void __launch_bounds__(kBlock) k_weighted_grad(DevMesh d, const doubl
   for (int k = 0; k < 9; ++k) out[k * d.m + i] = e.w * A[k];
 }
 
+// ------------------------------------------------------------------ contact
+// Algorithm 1's contact loop (Sec. 3.5) against analytic obstacles: rows
+// (n, b) of half-spaces (a vertex x with n . x < b penetrates by b - n . x and
+// is pushed along n), then rows (c, r) of spheres (|x - c| < r: depth
+// r - |x - c|, pushed along (x - c) / |x - c|).  Penalty force k * depth per
+// free vertex, written to d.rhs (the right-hand side of the sweeps); block
+// partials of |f|^2, added in a fixed order.
+__global__ void __launch_bounds__(kBlock) k_contact_force(DevMesh d, const double* obs, int np, int ns, double k,
+                                                          double* part) {
+  __shared__ double red[kBlock / 64];
+  const int v = blockIdx.x * kBlock + threadIdx.x;
+  double f0 = 0, f1 = 0, f2 = 0;
+  if (v < d.nf) {
+    const double x0 = d.q[3 * v], x1 = d.q[3 * v + 1], x2 = d.q[3 * v + 2];
+    for (int o = 0; o < np; ++o) {
+      const double* P = obs + 4 * o;
+      const double dep = P[3] - (P[0] * x0 + P[1] * x1 + P[2] * x2);
+      if (dep > 0.0) {
+        f0 += k * dep * P[0];
+        f1 += k * dep * P[1];
+        f2 += k * dep * P[2];
+      }
+    }
+    for (int o = np; o < np + ns; ++o) {
+      const double* Q = obs + 4 * o;
+      const double r0 = x0 - Q[0], r1 = x1 - Q[1], r2 = x2 - Q[2];
+      const double dist = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+      if (dist < Q[3] && dist > 0.0) {
+        const double sc = k * (Q[3] - dist) / dist;
+        f0 += sc * r0;
+        f1 += sc * r1;
+        f2 += sc * r2;
+      }
+    }
+    d.rhs[3 * v] = f0;
+    d.rhs[3 * v + 1] = f1;
+    d.rhs[3 * v + 2] = f2;
+  }
+  double s2 = f0 * f0 + f1 * f1 + f2 * f2;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s2;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+// q += x2 at the free vertices (the ACAP response of a contact step z), zc += z
+__global__ void __launch_bounds__(kBlock) k_contact_accum(DevMesh d, const double* x2, const double* z, double* zc) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t < 3 * (int64_t)d.nf) d.q[t] += x2[t];
+  if (t < 9 * (int64_t)d.m) zc[t] += z[t];
+}
+// The pending step of the iteration together with the contact field zc:
+// F <- R (S + sigma D(p)) + zc, re-split; then no step is pending.
+__global__ void __launch_bounds__(kBlock) k_accept_contact(DevMesh d, const double* zc) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= d.m) return;
+  double R[9], S[9];
+  load_R(d, i, R);
+  load_S(d, i, S);
+  accept_elem<true>(d, i, d.ctl->sigma, zc, R, S);
+}
+__global__ void k_clear_step(DevMesh d) {
+  if (threadIdx.x == 0) d.ctl->sigma = 0.0;
+}
+
 // out = H v with H = d2E/dF2 = blockdiag(vol d2Psi(F_i)) + alpha W - alpha W G L^{-1} G^T W:
 //   out_i = vol d2Psi(F_i)[v_i] + beta_i (v_i - A_i(x)),  x = L^{-1} G^T W v.
 // d2Psi[V] in the rotated frame at the symmetric S (X = R^T V):
@@ -2699,10 +2779,10 @@ __global__ void __launch_bounds__(kBlock) k_cg_dir(DevMesh d, double beta, const
     P[k] = Z[k] + beta * P[k];
 }
 
-// Preconditioner, part 1: rbar = H^{-1} Y^T vec(R^T r) (blocks), stored in d.p,
-// and block partials of y[(c,j)] = sum_i w_i (R D(rbar) gphi_j)[c].
+// Preconditioner, part 1: rbar = H^{-1} Y^T vec(R^T r) (blocks), stored in rbar
+// ([9][m]), and block partials of y[(c,j)] = sum_i w_i (R D(rbar) gphi_j)[c].
 template <typename T, bool kC = false>
-__global__ void __launch_bounds__(kBlock) k_pc1(DevMesh d, const double* r, double* ypart) {
+__global__ void __launch_bounds__(kBlock) k_pc1(DevMesh d, const double* r, double* ypart, double* rbar) {
   __shared__ double red[kBlock / 64][48];
   const int m = d.m;
   const T* Lf = (const T*)d.Lf;
@@ -2729,7 +2809,7 @@ __global__ void __launch_bounds__(kBlock) k_pc1(DevMesh d, const double* r, doub
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
       rb[k] = (double)ry[k];
-      d.p[k * m + i] = rb[k];
+      rbar[k * m + i] = rb[k];
     }
     from_y<double>(rb, D);
     matmul3(R, D, RD);
@@ -2815,7 +2895,8 @@ __global__ void __launch_bounds__(64) k_pc_solve(DevMesh d, const double* ypart)
 // Preconditioner, part 3: z_i = R D(rbar_i + alpha H^{-1} w Y^T vec(R^T A_i(uz)))
 // (F coordinates); block partials of r . z.
 template <typename T, bool kC = false>
-__global__ void __launch_bounds__(kBlock) k_pc2(DevMesh d, const double* r, double* zout, double* part) {
+__global__ void __launch_bounds__(kBlock) k_pc2(DevMesh d, const double* r, double* zout, double* part,
+                                                const double* rbar) {
   __shared__ DD sh[kBlock];
   DD acc[1] = {DD{0, 0}};
   const int m = d.m;
@@ -2839,7 +2920,7 @@ __global__ void __launch_bounds__(kBlock) k_pc2(DevMesh d, const double* r, doub
     hinv_apply<T, kC>(d, i, Ls, Lk, ty);
     double zy[9], D[9], Z[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) zy[k] = d.p[k * m + i] + d.alpha * (double)ty[k];
+    for (int k = 0; k < 9; ++k) zy[k] = rbar[k * m + i] + d.alpha * (double)ty[k];
     from_y<double>(zy, D);
     matmul3(R, D, Z);
     double rz = 0;
@@ -2966,8 +3047,8 @@ static void launch_bone_dir(const DevMesh& d, hipStream_t st) {
   if (d.nbones > 0)
     hipLaunchKernelGGL(d.mixed ? k_bone_dir<float> : k_bone_dir<double>, dim3(d.nbones), dim3(kBlock), 0, st, d);
 }
-typedef void (*Pc1Kernel)(DevMesh, const double*, double*);
-typedef void (*Pc2Kernel)(DevMesh, const double*, double*, double*);
+typedef void (*Pc1Kernel)(DevMesh, const double*, double*, double*);
+typedef void (*Pc2Kernel)(DevMesh, const double*, double*, double*, const double*);
 static Pc1Kernel pick_pc1(const DevMesh& d) {
   return d.mixed ? (d.coupled ? k_pc1<float, true> : k_pc1<float, false>)
                  : (d.coupled ? k_pc1<double, true> : k_pc1<double, false>);
@@ -3037,11 +3118,26 @@ void launch_cg_update(const DevMesh& d, double alpha, const double* P, const dou
 void launch_cg_dir(const DevMesh& d, double beta, const double* Z, double* P, hipStream_t st) {
   hipLaunchKernelGGL(k_cg_dir, dim3(d.nb), dim3(kBlock), 0, st, d, beta, Z, P);
 }
-void launch_precond(const DevMesh& d, const double* r, double* z, double* ypart, double* part, hipStream_t st) {
-  hipLaunchKernelGGL(pick_pc1(d), dim3(d.nb), dim3(kBlock), 0, st, d, r, ypart);
+void launch_precond(const DevMesh& d, const double* r, double* z, double* ypart, double* part, double* rbar,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(pick_pc1(d), dim3(d.nb), dim3(kBlock), 0, st, d, r, ypart, rbar);
   hipLaunchKernelGGL(k_pc_solve, dim3(1), dim3(64), 0, st, d, ypart);
   hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d);
-  hipLaunchKernelGGL(pick_pc2(d), dim3(d.nb), dim3(kBlock), 0, st, d, r, z, part);
+  hipLaunchKernelGGL(pick_pc2(d), dim3(d.nb), dim3(kBlock), 0, st, d, r, z, part, (const double*)rbar);
+}
+int contact_blocks(const DevMesh& d) { return (d.nf + kBlock - 1) / kBlock; }
+void launch_contact_force(const DevMesh& d, const double* obs, int np, int ns, double k, double* part,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_contact_force, dim3(std::max(1, contact_blocks(d))), dim3(kBlock), 0, st, d, obs, np, ns, k,
+                     part);
+}
+void launch_contact_accum(const DevMesh& d, const double* x2, const double* z, double* zc, hipStream_t st) {
+  const int64_t n = std::max(3 * (int64_t)d.nf, 9 * (int64_t)d.m);
+  hipLaunchKernelGGL(k_contact_accum, dim3(blocks(n)), dim3(kBlock), 0, st, d, x2, z, zc);
+}
+void launch_accept_contact(const DevMesh& d, const double* zc, hipStream_t st) {
+  hipLaunchKernelGGL(k_accept_contact, dim3(blocks(d.m)), dim3(kBlock), 0, st, d, zc);
+  hipLaunchKernelGGL(k_clear_step, dim3(1), dim3(64), 0, st, d);
 }
 void launch_adj_da(const DevMesh& d, const double* lam, double* part, hipStream_t st) {
   hipLaunchKernelGGL(k_adj_da, dim3(d.nb), dim3(kBlock), 0, st, d, lam, part);

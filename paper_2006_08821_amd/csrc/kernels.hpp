@@ -67,7 +67,18 @@ void launch_hvp(const DevMesh& d, const double* V, const double* x, double* out,
 void launch_cg_update(const DevMesh& d, double alpha, const double* P, const double* HP, double* lam, double* r,
                       double* part, hipStream_t st);
 void launch_cg_dir(const DevMesh& d, double beta, const double* Z, double* P, hipStream_t st);
-void launch_precond(const DevMesh& d, const double* r, double* z, double* ypart, double* part, hipStream_t st);
+// z = Htilde^{-1} r (world-frame F fields [9][m]) with the iteration's blocks and
+// Woodbury factor; rbar ([9][m]) is scratch.
+void launch_precond(const DevMesh& d, const double* r, double* z, double* ypart, double* part, double* rbar,
+                    hipStream_t st);
+// contact loop: penalty forces of the free vertices into d.rhs (block partials
+// of |f|^2, contact_blocks(d) of them); q += x2, zc += z; the pending step
+// together with zc (then none is pending)
+int contact_blocks(const DevMesh& d);
+void launch_contact_force(const DevMesh& d, const double* obs, int np, int ns, double k, double* part,
+                          hipStream_t st);
+void launch_contact_accum(const DevMesh& d, const double* x2, const double* z, double* zc, hipStream_t st);
+void launch_accept_contact(const DevMesh& d, const double* zc, hipStream_t st);
 void launch_adj_da(const DevMesh& d, const double* lam, double* part, hipStream_t st);
 void launch_group_sum(const DevMesh& d, const double* per, double scale, double* out, hipStream_t st);
 

@@ -83,6 +83,15 @@ struct emu_mesh {
   double* a_work = nullptr;
   // phase-timing events (emu_solve_opts.phase_timing), 5 per iteration of a sync block
   std::vector<hipEvent_t> t_ev;
+  // contact (emu_set_contact): obstacle rows (planes, then spheres), the
+  // parameters, the work arrays of the rounds and a pinned host copy of the
+  // force partials (all allocated on the first call)
+  int32_t c_np = 0, c_ns = 0, c_max_rounds = 0;
+  double c_k = 0, c_tol = 0;
+  double* c_obs = nullptr;
+  double* c_work = nullptr;
+  double* c_host = nullptr;
+  int32_t c_rounds = 0;
 
   explicit emu_mesh(std::shared_ptr<emu::HostMesh> p) : hmp(std::move(p)), hm(*hmp) {}
   emu_mesh(const emu_mesh&) = delete;
@@ -118,6 +127,7 @@ struct emu_mesh {
       else (void)hipFree(p);
     }
     if (h_ctl) (void)hipHostFree(h_ctl);
+    if (c_host) (void)hipHostFree(c_host);
     if (t_ev.size())
       for (hipEvent_t e : t_ev) (void)hipEventDestroy(e);
     if (ev_a) (void)hipEventDestroy(ev_a);

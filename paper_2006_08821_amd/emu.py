@@ -222,6 +222,17 @@ class Mesh:
         f = np.ascontiguousarray(f, np.float64).reshape(self.n, 3)
         check(self._lib.emu_set_external_forces(self._h, dptr(f)), "emu_set_external_forces")
 
+    def set_contact(self, planes=None, spheres=None, stiffness=1.0, tol=1e-8, max_rounds=8):
+        """Obstacles for the contact loop after every accepted step: planes
+        [np,4] rows (unit normal, b), spheres [ns,4] rows (center, radius),
+        penalty stiffness (N/m), stop tolerance on |f|_2 (N) and the round
+        limit; no obstacles removes contact."""
+        P = np.zeros((0, 4)) if planes is None else np.ascontiguousarray(planes, np.float64).reshape(-1, 4)
+        S = np.zeros((0, 4)) if spheres is None else np.ascontiguousarray(spheres, np.float64).reshape(-1, 4)
+        desc = _lib.ContactDesc(len(P), dptr(P) if len(P) else None, len(S), dptr(S) if len(S) else None,
+                                float(stiffness), float(tol), int(max_rounds))
+        check(self._lib.emu_set_contact(self._h, C.byref(desc)), "emu_set_contact")
+
     def set_modes(self, nu, phi):
         nu = np.ascontiguousarray(nu, np.float64)
         phi = np.ascontiguousarray(phi, np.float64)
