@@ -13,7 +13,8 @@ not described there, so analytic obstacles stand in for the colliding bodies:
 * half-spaces, rows (n, b) with a unit normal n: a vertex x penetrates where
   n . x < b, by depth b - n . x, and is pushed along +n;
 * spheres, rows (c, r): x penetrates where |x - c| < r, by r - |x - c|, and is
-  pushed along (x - c) / |x - c|.
+  pushed along (x - c) / |x - c| (a vertex exactly at c has no direction and
+  gets no force).
 
 Each penetrating free vertex receives the penalty force k * depth along the
 push direction (the negative gradient of 1/2 k depth^2); pinned vertices get
@@ -23,7 +24,7 @@ none.  One round, with f the force increment of the current q:
     z  = Htilde^{-1} nu             (the iteration's Woodbury inverse)
     F <- F + z,   q <- q*(F)        (an ACAP solve; q* is affine in F)
 
-and rounds repeat until |f|_2 <= tol or max_rounds are done (reading R19).
+and rounds repeat until |f|_2 <= tol or max_rounds are done.
 """
 from __future__ import annotations
 
@@ -57,7 +58,7 @@ def penetrations(x, contact):
     for k, (cx, cy, cz, r) in enumerate(S):
         rel = x - np.array([cx, cy, cz])
         dist = np.linalg.norm(rel, axis=1)
-        inside = dist < r
+        inside = (dist < r) & (dist > 0.0)  # no push direction at the center
         j = len(P) + k
         depth[inside, j] = r - dist[inside]
         dirs[inside, j] = rel[inside] / dist[inside, None]
