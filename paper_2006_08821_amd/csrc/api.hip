@@ -7,6 +7,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -43,6 +44,7 @@ emu_status fail_with(const emu::Error& e) {
 void modes_layout(const emu::HostMesh& hm, std::vector<double>& phi, std::vector<double>& nu) {
   phi.assign((size_t)emu::kMaxK1 * hm.n, 0.0);
   nu.assign(emu::kMaxK1, 1.0);
+  if ((int)hm.nu.size() < hm.k1) return;  // modes not computed yet (device eigenpairs follow)
   for (int j = 0; j < hm.k1; ++j) {
     nu[j] = hm.nu[j];
     for (int32_t f = 0; f < hm.nf; ++f) phi[(size_t)emu::kMaxK1 * f + j] = hm.phi[(size_t)j * hm.nf + f];
@@ -54,6 +56,187 @@ void upload_modes(emu_mesh* M) {
   modes_layout(M->hm, phi, nu);
   HIPCHK(hipMemcpy((void*)M->d.phi, phi.data(), phi.size() * 8, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy((void*)M->d.nu, nu.data(), nu.size() * 8, hipMemcpyHostToDevice));
+}
+
+// Device memory for the duration of one call (the caller's allocator when
+// it has one), released after the mesh's stream has drained.
+struct TmpDev {
+  emu_mesh* M;
+  double* p = nullptr;
+  TmpDev(emu_mesh* m, size_t count) : M(m) {
+    const size_t nb = std::max<size_t>(1, count) * sizeof(double);
+    if (M->dev_alloc) p = (double*)M->dev_alloc(nb, M->alloc_ctx);
+    else if (hipMalloc((void**)&p, nb) != hipSuccess) p = nullptr;
+    if (!p) throw emu::Error{EMU_E_OOM, "device allocation of the eigen work arrays failed"};
+  }
+  ~TmpDev() {
+    (void)hipStreamSynchronize(M->st);
+    if (M->dev_free) M->dev_free(p, M->alloc_ctx);
+    else (void)hipFree(p);
+  }
+  TmpDev(const TmpDev&) = delete;
+  TmpDev& operator=(const TmpDev&) = delete;
+};
+
+// Upper-triangular R with R^T R = G (kEigCols square, row-major) and its
+// inverse; false if G is not numerically positive definite.
+bool chol_upper_inverse(const std::vector<double>& G, std::vector<double>& Rinv) {
+  constexpr int B = emu::kEigCols;
+  std::vector<double> R((size_t)B * B, 0.0);
+  double dmax = 0;
+  for (int i = 0; i < B; ++i) dmax = std::max(dmax, G[(size_t)i * B + i]);
+  for (int i = 0; i < B; ++i) {
+    double s = G[(size_t)i * B + i];
+    for (int k = 0; k < i; ++k) s -= R[(size_t)k * B + i] * R[(size_t)k * B + i];
+    if (!(s > 1e-13 * dmax)) return false;
+    const double rii = std::sqrt(s);
+    R[(size_t)i * B + i] = rii;
+    for (int j = i + 1; j < B; ++j) {
+      double t = 0.5 * (G[(size_t)i * B + j] + G[(size_t)j * B + i]);
+      for (int k = 0; k < i; ++k) t -= R[(size_t)k * B + i] * R[(size_t)k * B + j];
+      R[(size_t)i * B + j] = t / rii;
+    }
+  }
+  Rinv.assign((size_t)B * B, 0.0);
+  for (int j = 0; j < B; ++j) {  // column j of R^{-1}: back substitution
+    for (int i = j; i >= 0; --i) {
+      double t = i == j ? 1.0 : 0.0;
+      for (int k = i + 1; k <= j; ++k) t -= R[(size_t)i * B + k] * Rinv[(size_t)k * B + j];
+      Rinv[(size_t)i * B + j] = t / R[(size_t)i * B + i];
+    }
+  }
+  return true;
+}
+
+// The lowest k1 eigenpairs of L_ff (eq. low-rank) on the device: block
+// inverse subspace iteration on kEigCols vectors (CholQR2 after each solve
+// with the factor), Rayleigh-Ritz with L_ff each step, stopped at the host
+// solver's test (relative residual <= 1e-8 for the k1 lowest pairs); then the
+// host's sign and normalization, and the captured fraction of trace(L_ff^-1)
+// from nine probes.  false (nothing written) if the mesh is too small for the
+// block or the iteration does not reach the test.
+bool device_modes(emu_mesh* M) {
+  auto& hm = M->hm;
+  const emu::DevMesh& d = M->d;
+  constexpr int B = emu::kEigCols, NP = B / 3;
+  const int k1 = hm.k1, nf = hm.nf;
+  if (k1 == 0) return true;
+  if (nf < 4 * B) return false;
+  hipStream_t st = M->st;
+  const int64_t ps = 3 * (int64_t)hm.n;
+  const int nblk = std::max(emu::eig_gram_blocks(nf), (nf + 255) / 256);
+  const size_t nd = 3 * (size_t)NP * ps + 9 * (size_t)hm.m + (size_t)nblk * B * B + 2 * (size_t)B * B + B;
+  TmpDev tmp(M, nd);
+  double* X = tmp.p;
+  double* Y = X + NP * ps;
+  double* LX = Y + NP * ps;
+  double* V = LX + NP * ps;
+  double* part = V + 9 * (size_t)hm.m;
+  double* W = part + (size_t)nblk * B * B;
+  double* out = W + (size_t)B * B;
+  double* lam = out + (size_t)B * B;
+  HIPCHK(hipMemsetAsync(X, 0, 8 * 3 * (size_t)NP * ps, st));
+  {
+    std::vector<double> h((size_t)NP * ps, 0.0);
+    std::mt19937_64 rng(20200615ULL);
+    std::normal_distribution<double> nd01(0.0, 1.0);
+    for (int c = 0; c < B; ++c)
+      for (int i = 0; i < nf; ++i) h[(c / 3) * ps + 3 * (int64_t)i + c % 3] = nd01(rng);
+    HIPCHK(hipMemcpyAsync(X, h.data(), 8 * h.size(), hipMemcpyHostToDevice, st));
+  }
+  std::vector<double> G, Rinv, T((size_t)B * B), Wv((size_t)B * B), ev(B), r(B);
+  auto fetch = [&](size_t count, double* dst) {
+    HIPCHK(hipMemcpyAsync(dst, out, 8 * count, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  };
+  auto cholqr = [&](const double* src, double* dst) {
+    G.resize((size_t)B * B);
+    emu::launch_eig_gram(nf, ps, src, src, part, out, st);
+    fetch(G.size(), G.data());
+    if (!chol_upper_inverse(G, Rinv)) return false;
+    HIPCHK(hipMemcpyAsync(W, Rinv.data(), 8 * Rinv.size(), hipMemcpyHostToDevice, st));
+    emu::launch_eig_mul(nf, ps, src, W, dst, st);
+    return true;
+  };
+  if (!cholqr(X, Y) || !cholqr(Y, X)) return false;
+  bool conv = false;
+  for (int it = 0; it < 300 && !conv; ++it) {
+    for (int p = 0; p < NP; ++p) {  // Y = L_ff^{-1} X
+      HIPCHK(hipMemcpyAsync(d.rhs, X + p * ps, 24 * (size_t)nf, hipMemcpyDeviceToDevice, st));
+      emu::launch_sweeps(d, M->plan, Y + p * ps, st);
+    }
+    if (!cholqr(Y, X) || !cholqr(X, Y)) return false;  // orthonormal basis in Y
+    for (int p = 0; p < NP; ++p) {                       // LX = L_ff Y
+      emu::launch_lff_apply(d, Y + p * ps, V, st);
+      HIPCHK(hipMemcpyAsync(LX + p * ps, d.rhs, 24 * (size_t)nf, hipMemcpyDeviceToDevice, st));
+    }
+    emu::launch_eig_gram(nf, ps, Y, LX, part, out, st);  // Rayleigh-Ritz
+    fetch(T.size(), T.data());
+    for (int a = 0; a < B; ++a)
+      for (int c = 0; c < a; ++c) T[(size_t)a * B + c] = T[(size_t)c * B + a] = 0.5 * (T[(size_t)a * B + c] + T[(size_t)c * B + a]);
+    emu::jacobi_eigh(B, T.data(), ev.data(), Wv.data());
+    HIPCHK(hipMemcpyAsync(W, Wv.data(), 8 * Wv.size(), hipMemcpyHostToDevice, st));
+    emu::launch_eig_mul(nf, ps, Y, W, X, st);  // Ritz vectors
+    emu::launch_eig_mul(nf, ps, LX, W, Y, st);  // and L_ff times them
+    HIPCHK(hipMemcpyAsync(lam, ev.data(), 8 * (size_t)B, hipMemcpyHostToDevice, st));
+    emu::launch_eig_resid(nf, ps, X, Y, lam, k1, part, out, st);
+    fetch((size_t)k1, r.data());
+    double worst = 0;
+    for (int j = 0; j < k1; ++j) worst = std::max(worst, std::sqrt(std::max(0.0, r[j])) / std::fabs(ev[j]));
+    conv = worst < 1e-8;
+  }
+  if (!conv) return false;
+  std::vector<double> h((size_t)NP * ps);
+  HIPCHK(hipMemcpyAsync(h.data(), X, 8 * h.size(), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  hm.nu.assign(ev.begin(), ev.begin() + k1);
+  hm.phi.assign((size_t)k1 * nf, 0.0);
+  for (int j = 0; j < k1; ++j) {
+    auto at = [&](int i) { return h[(j / 3) * ps + 3 * (int64_t)i + j % 3]; };
+    int im = 0;
+    double nn = 0;
+    for (int i = 0; i < nf; ++i) {
+      if (std::fabs(at(i)) > std::fabs(at(im))) im = i;
+      nn += at(i) * at(i);
+    }
+    const double sg = (at(im) < 0 ? -1.0 : 1.0) / std::sqrt(nn);
+    for (int i = 0; i < nf; ++i) hm.phi[(size_t)j * nf + i] = sg * at(i);
+  }
+  {
+    // trace(L_ff^{-1}) from nine +-1 probes (three packs) for the captured fraction
+    std::vector<double> z(3 * (size_t)ps, 0.0), zi(3 * (size_t)ps);
+    std::mt19937_64 r2(7);
+    for (int p = 0; p < 3; ++p)
+      for (int64_t k = 0; k < 3 * (int64_t)nf; ++k) z[p * ps + k] = (r2() & 1) ? 1.0 : -1.0;
+    HIPCHK(hipMemcpyAsync(X, z.data(), 8 * z.size(), hipMemcpyHostToDevice, st));
+    for (int p = 0; p < 3; ++p) {
+      HIPCHK(hipMemcpyAsync(d.rhs, X + p * ps, 24 * (size_t)nf, hipMemcpyDeviceToDevice, st));
+      emu::launch_sweeps(d, M->plan, Y + p * ps, st);
+    }
+    HIPCHK(hipMemcpyAsync(zi.data(), Y, 8 * zi.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double tr = 0;
+    for (size_t k = 0; k < z.size(); ++k) tr += z[k] * zi[k];
+    tr /= 9.0;
+    double capd = 0;
+    for (int j = 0; j < k1; ++j) capd += 1.0 / hm.nu[j];
+    hm.mode_captured = tr > 0 ? capd / tr : 0;
+  }
+  upload_modes(M);
+  return true;
+}
+
+// Modes of a mesh whose image was uploaded without them: on the device, or
+// by the host solver where the device iteration declines.
+void ensure_modes(emu_mesh* M) {
+  if ((int)M->hm.nu.size() == M->hm.k1) {
+    upload_modes(M);
+    return;
+  }
+  if (!device_modes(M)) {
+    emu::host_modes(M->hm, M->hm.k1);
+    upload_modes(M);
+  }
 }
 
 void upload_pins(emu_mesh* M) {
@@ -422,6 +605,8 @@ void emu::fill_stats(const emu::Ctl& c, emu_solve_stats* s, float ms) {
   s->ms_total = ms;
 }
 
+void emu::ensure_modes_of(emu_mesh* M) { ensure_modes(M); }
+
 void emu::launch_to_user_q(emu_mesh* M, double* out) {
   hipLaunchKernelGGL(k_to_user_q, dim3((M->hm.n + 255) / 256), dim3(256), 0, M->st, M->d.q, M->d_vold, M->hm.n,
                      out);
@@ -502,8 +687,9 @@ emu_status emu_create_mesh(const emu_mesh_desc* desc, emu_mesh** out) {
     M->dev_free = desc->dev_free;
     M->alloc_ctx = desc->alloc_ctx;
     auto t0 = std::chrono::steady_clock::now();
-    emu::host_setup(*desc, M->hm, true);
+    emu::host_setup(*desc, M->hm, false);
     emu::upload_image(M, emu::prepare_image(M->hm), nullptr);
+    ensure_modes(M);
     emu::launch_init_rest(M->d, M->st);
     emu_solve_opts o = emu_solve_opts_default();
     init_ctl(M, o, 0);

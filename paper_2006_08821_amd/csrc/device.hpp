@@ -21,6 +21,7 @@ constexpr int kWideRowMin = 64;
 constexpr int kNarrowChunk = 512;     // vector chunk of the narrow sweep variant (12 KB of LDS)
 constexpr int kNarrowFwdW = 64;       // widest supernode of a forward level run narrow
 constexpr int kNarrowBwdH = 256;      // tallest supernode of a backward level run narrow
+constexpr int kEigCols = 33;          // columns of the device eigen block (11 packs of 3)
 
 // Iteration control block (device memory, one per mesh).
 struct Ctl {

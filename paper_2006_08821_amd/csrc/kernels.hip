@@ -1918,8 +1918,14 @@ DEV void b_gram(const DevMesh& d, int bid) {
     }
   }
 }
+// FP32: at most three waves per SIMD.  With 101 VGPRs the compiler allowed
+// four, and the pass took 679 us instead of 434 us on the 1.5M-tet hinge limb
+// (more element gathers in flight per CU than its caches serve).
+template <typename T>
+constexpr int gram_max_waves() { return sizeof(T) == 4 ? 3 : 8; }
 template <typename T, bool kC = false>
-__global__ void __launch_bounds__(kBlock) k_gram(DevMesh d) { b_gram<T, kC>(d, blockIdx.x); }
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, gram_max_waves<T>())))
+k_gram(DevMesh d) { b_gram<T, kC>(d, blockIdx.x); }
 
 // Partial Gram sums: 16 threads per entry sum interleaved workgroup partials,
 // then add their results in a fixed order.
@@ -2635,6 +2641,118 @@ __global__ void __launch_bounds__(kBlock) k_weighted_grad(DevMesh d, const doubl
   for (int k = 0; k < 9; ++k) out[k * d.m + i] = e.w * A[k];
 }
 
+// ------------------------------------------------------------------ device eigenpairs
+// The lowest eigenpairs of L_ff (the modes of eq. low-rank) by block inverse
+// subspace iteration with the device factor.  A block is kEigCols columns in
+// kEigCols / 3 packs; a pack is a vertex field in the sweeps' [n][3] layout
+// (column 3 p + c of the block is component c of pack p, free rows first,
+// pinned rows zero); packs are pstride doubles apart.
+
+// V = G x per element (unweighted): L x = G^T W G x through the ACAP
+// right-hand side of V.
+__global__ void __launch_bounds__(kBlock) k_grad_field(DevMesh d, const double* x, double* V) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.m) return;
+  Elem e;
+  load_elem(d, i, e);
+  double A[9];
+  gather_grad(x, e, A);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) V[k * d.m + i] = A[k];
+}
+
+DEV double eig_at(const double* A, int64_t pstride, int row, int col) {
+  return A[(col / 3) * pstride + 3 * (int64_t)row + (col % 3)];
+}
+
+// Partial products A^T B (kEigCols x kEigCols) of a contiguous row range per
+// workgroup, in tiles of kEigTile rows staged in LDS; part[blk][a * kEigCols + b].
+constexpr int kEigTile = 32;
+constexpr int kEigPairs = kEigCols * kEigCols;
+constexpr int kEigPerThread = (kEigPairs + kBlock - 1) / kBlock;
+__global__ void __launch_bounds__(kBlock) k_eig_gram(int nf, int64_t pstride, const double* A, const double* B,
+                                                     int rows_per_blk, double* part) {
+  __shared__ double ta[kEigTile][kEigCols], tb[kEigTile][kEigCols];
+  const int t = threadIdx.x;
+  const int r0 = blockIdx.x * rows_per_blk, r1 = min(nf, r0 + rows_per_blk);
+  double acc[kEigPerThread];
+#pragma unroll
+  for (int q = 0; q < kEigPerThread; ++q) acc[q] = 0.0;
+  for (int base = r0; base < r1; base += kEigTile) {
+    const int nr = min(kEigTile, r1 - base);
+    __syncthreads();
+    for (int k = t; k < kEigTile * kEigCols; k += kBlock) {
+      const int rr = k / kEigCols, c = k % kEigCols;
+      ta[rr][c] = rr < nr ? eig_at(A, pstride, base + rr, c) : 0.0;
+      tb[rr][c] = rr < nr ? eig_at(B, pstride, base + rr, c) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kEigPerThread; ++q) {
+      const int pr = t + q * kBlock;
+      if (pr < kEigPairs) {
+        const int a = pr / kEigCols, b = pr % kEigCols;
+        double s = acc[q];
+        for (int rr = 0; rr < kEigTile; ++rr) s += ta[rr][a] * tb[rr][b];
+        acc[q] = s;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kEigPerThread; ++q) {
+    const int pr = t + q * kBlock;
+    if (pr < kEigPairs) part[(int64_t)blockIdx.x * kEigPairs + pr] = acc[q];
+  }
+}
+// out[e] = sum over blocks of part[blk][e], in block order
+__global__ void __launch_bounds__(kBlock) k_eig_reduce(int nblk, int nent, const double* part, double* out) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= nent) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * nent + e];
+  out[e] = s;
+}
+// X = Y W (W kEigCols x kEigCols, row-major), one row per thread
+__global__ void __launch_bounds__(kBlock) k_eig_mul(int nf, int64_t pstride, const double* Y, const double* W,
+                                                    double* X) {
+  __shared__ double w[kEigPairs];
+  for (int k = threadIdx.x; k < kEigPairs; k += kBlock) w[k] = W[k];
+  __syncthreads();
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nf) return;
+  double y[kEigCols];
+#pragma unroll
+  for (int c = 0; c < kEigCols; ++c) y[c] = eig_at(Y, pstride, i, c);
+  for (int j = 0; j < kEigCols; ++j) {
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < kEigCols; ++c) s += y[c] * w[c * kEigCols + j];
+    X[(j / 3) * pstride + 3 * (int64_t)i + (j % 3)] = s;
+  }
+}
+// part[blk][j] = sum over the block's rows of (LX[:, j] - lam[j] X[:, j])^2, j < ncols
+__global__ void __launch_bounds__(kBlock) k_eig_resid(int nf, int64_t pstride, const double* X, const double* LX,
+                                                      const double* lam, int ncols, double* part) {
+  __shared__ double red[kBlock / 64][kEigCols];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = 0; j < ncols; ++j) {
+    double r = 0.0;
+    if (i < nf) {
+      const double dv = eig_at(LX, pstride, i, j) - lam[j] * eig_at(X, pstride, i, j);
+      r = dv * dv;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) r += __shfl_xor(r, off);
+    if (lane == 0) red[wave][j] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < ncols) {
+    const int j = threadIdx.x;
+    part[(int64_t)blockIdx.x * ncols + j] = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
+  }
+}
+
 // ------------------------------------------------------------------ contact
 // Algorithm 1's contact loop (Sec. 3.5) against analytic obstacles: rows
 // (n, b) of half-spaces (a vertex x with n . x < b penetrates by b - n . x and
@@ -3124,6 +3242,32 @@ void launch_precond(const DevMesh& d, const double* r, double* z, double* ypart,
   hipLaunchKernelGGL(k_pc_solve, dim3(1), dim3(64), 0, st, d, ypart);
   hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(pick_pc2(d), dim3(d.nb), dim3(kBlock), 0, st, d, r, z, part, (const double*)rbar);
+}
+void launch_grad_field(const DevMesh& d, const double* x, double* V, hipStream_t st) {
+  hipLaunchKernelGGL(k_grad_field, dim3(blocks(d.m)), dim3(kBlock), 0, st, d, x, V);
+}
+void launch_lff_apply(const DevMesh& d, const double* x, double* V, hipStream_t st) {
+  hipLaunchKernelGGL(k_grad_field, dim3(blocks(d.m)), dim3(kBlock), 0, st, d, x, V);
+  hipLaunchKernelGGL(k_contrib_field, dim3(blocks(d.m)), dim3(kBlock), 0, st, d, (const double*)V);
+  hipLaunchKernelGGL(k_rhs, dim3(rhs_blocks(d.nf)), dim3(kBlock), 0, st, d, 0, 0);
+}
+int eig_gram_blocks(int nf) { return std::max(1, std::min(512, (nf + 255) / 256)); }
+void launch_eig_gram(int nf, int64_t pstride, const double* A, const double* B, double* part, double* out,
+                     hipStream_t st) {
+  const int nblk = eig_gram_blocks(nf);
+  const int rows = (nf + nblk - 1) / nblk;
+  hipLaunchKernelGGL(k_eig_gram, dim3(nblk), dim3(kBlock), 0, st, nf, pstride, A, B, rows, part);
+  hipLaunchKernelGGL(k_eig_reduce, dim3((kEigPairs + kBlock - 1) / kBlock), dim3(kBlock), 0, st, nblk, kEigPairs,
+                     (const double*)part, out);
+}
+void launch_eig_mul(int nf, int64_t pstride, const double* Y, const double* W, double* X, hipStream_t st) {
+  hipLaunchKernelGGL(k_eig_mul, dim3(blocks(nf)), dim3(kBlock), 0, st, nf, pstride, Y, W, X);
+}
+void launch_eig_resid(int nf, int64_t pstride, const double* X, const double* LX, const double* lam, int ncols,
+                      double* part, double* out, hipStream_t st) {
+  const int nblk = blocks(nf);
+  hipLaunchKernelGGL(k_eig_resid, dim3(nblk), dim3(kBlock), 0, st, nf, pstride, X, LX, lam, ncols, part);
+  hipLaunchKernelGGL(k_eig_reduce, dim3(1), dim3(kBlock), 0, st, nblk, ncols, (const double*)part, out);
 }
 int contact_blocks(const DevMesh& d) { return (d.nf + kBlock - 1) / kBlock; }
 void launch_contact_force(const DevMesh& d, const double* obs, int np, int ns, double k, double* part,

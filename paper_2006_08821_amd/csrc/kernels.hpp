@@ -75,6 +75,16 @@ void launch_precond(const DevMesh& d, const double* r, double* z, double* ypart,
 // of |f|^2, contact_blocks(d) of them); q += x2, zc += z; the pending step
 // together with zc (then none is pending)
 int contact_blocks(const DevMesh& d);
+// device eigenpairs of L_ff: blocks of kEigCols columns in packs of three
+// ([n][3] vertex fields, pstride doubles apart); partial and reduced column
+// products, X = Y W, residual norms, and L_ff x (into d.rhs, V scratch [9][m])
+void launch_lff_apply(const DevMesh& d, const double* x, double* V, hipStream_t st);
+int eig_gram_blocks(int nf);
+void launch_eig_gram(int nf, int64_t pstride, const double* A, const double* B, double* part, double* out,
+                     hipStream_t st);
+void launch_eig_mul(int nf, int64_t pstride, const double* Y, const double* W, double* X, hipStream_t st);
+void launch_eig_resid(int nf, int64_t pstride, const double* X, const double* LX, const double* lam, int ncols,
+                      double* part, double* out, hipStream_t st);
 void launch_contact_force(const DevMesh& d, const double* obs, int np, int ns, double k, double* part,
                           hipStream_t st);
 void launch_contact_accum(const DevMesh& d, const double* x2, const double* z, double* zc, hipStream_t st);

@@ -146,4 +146,8 @@ void init_ctl(emu_mesh* M, const emu_solve_opts& o, int eval_only);
 void fresh_solve(emu_mesh* M);
 void fill_stats(const emu::Ctl& c, emu_solve_stats* s, float ms);
 void launch_to_user_q(emu_mesh* M, double* out);
+// The modes of a mesh uploaded without them (host_setup without modes): the
+// cached ones of its host setup, else computed on the device (host solver as
+// the fallback) and kept in the host setup for later copies of the mesh.
+void ensure_modes_of(emu_mesh* M);
 }  // namespace emu

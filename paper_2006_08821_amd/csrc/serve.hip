@@ -223,7 +223,7 @@ std::shared_ptr<const Setup> run_setup(const DescCopy& dc) {
   auto s = std::make_shared<Setup>();
   try {
     s->hm = std::make_shared<emu::HostMesh>();
-    emu::host_setup(dc.d, *s->hm, true);
+    emu::host_setup(dc.d, *s->hm, false);  // the modes follow on the device at admission
     s->img = emu::prepare_image(*s->hm);
   } catch (const emu::Error& e) {
     s->code = e.code;
@@ -450,6 +450,7 @@ void admit(emu_server* S, std::unique_lock<std::mutex>& lk) {
         res->mesh.reset(new emu_mesh(s.hm));
         emu::upload_image(res->mesh.get(), s.img, S->st);
         res->mesh->img.reset();
+        emu::ensure_modes_of(res->mesh.get());
         S->resident += res->mesh->bytes;
         fresh = true;
       }
