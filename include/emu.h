@@ -353,10 +353,16 @@ typedef struct {
   int32_t peak_active;
   int32_t submitted, completed, failed;
   int32_t rounds;            /* scheduler rounds that launched work              */
+  int64_t resident_bytes;    /* device bytes of the meshes resident now          */
 } emu_server_report;
 
 /* Create a server on the current HIP device.  opts may be NULL (defaults).
-   EMU_E_INVALID for negative options, EMU_E_HIP without a device. */
+   EMU_E_INVALID for negative options, EMU_E_HIP without a device.
+   A request that fails (any status but EMU_OK, or EMU_E_NOT_CONVERGED with a
+   finite gradient) releases its slot and its mesh's device memory; the other
+   requests are unaffected.  Test hook for that path: with the environment
+   variable EMU_FAULT=linesearch:T at creation, the request with ticket T
+   ends with EMU_E_LINESEARCH after its first round. */
 emu_status emu_server_create(const emu_server_opts* opts, emu_server** out);
 /* Queue one request; the description's arrays and activation (host,
    [n_groups]) are copied; opts may be NULL (emu_solve_opts_default).  Writes a

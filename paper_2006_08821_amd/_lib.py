@@ -86,7 +86,7 @@ class RequestTimes(C.Structure):
 class ServerReport(C.Structure):
     _fields_ = [("peak_resident_bytes", C.c_int64), ("peak_active", C.c_int32),
                 ("submitted", C.c_int32), ("completed", C.c_int32), ("failed", C.c_int32),
-                ("rounds", C.c_int32)]
+                ("rounds", C.c_int32), ("resident_bytes", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -27,6 +27,7 @@ LIB = os.path.join(HERE, "libemu.so")
 HOST_SRC = ["host_setup.cpp", "api_host.cpp"]
 HIP_SRC = ["kernels.hip", "api.hip", "serve.hip"]
 ARCH = os.environ.get("EMU_OFFLOAD_ARCH", "gfx950")
+ROCM_LIB = "/opt/rocm/lib"  # roctx ranges (rocprofiler-sdk-roctx)
 
 
 def _hipcc():
@@ -67,7 +68,8 @@ def build(verbose: bool = False) -> str:
                 if lg.strip():
                     print(lg)
         tmp_lib = LIB + ".tmp"
-        _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp_lib] + objs + ["-lpthread"])
+        _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp_lib] + objs +
+             ["-L" + ROCM_LIB, "-Wl,-rpath," + ROCM_LIB, "-lrocprofiler-sdk-roctx", "-lpthread"])
         os.replace(tmp_lib, LIB)
     finally:
         shutil.rmtree(out_dir, ignore_errors=True)

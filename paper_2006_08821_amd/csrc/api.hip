@@ -116,6 +116,7 @@ bool chol_upper_inverse(const std::vector<double>& G, std::vector<double>& Rinv)
 // from nine probes.  false (nothing written) if the mesh is too small for the
 // block or the iteration does not reach the test.
 bool device_modes(emu_mesh* M) {
+  emu::Range range("emu device eigenpairs");
   auto& hm = M->hm;
   const emu::DevMesh& d = M->d;
   constexpr int B = emu::kEigCols, NP = B / 3;
@@ -686,8 +687,12 @@ emu_status emu_create_mesh(const emu_mesh_desc* desc, emu_mesh** out) {
     M->dev_alloc = desc->dev_alloc;
     M->dev_free = desc->dev_free;
     M->alloc_ctx = desc->alloc_ctx;
+    emu::Range range("emu_create_mesh");
     auto t0 = std::chrono::steady_clock::now();
-    emu::host_setup(*desc, M->hm, false);
+    {
+      emu::Range r2("emu host setup");
+      emu::host_setup(*desc, M->hm, false);
+    }
     emu::upload_image(M, emu::prepare_image(M->hm), nullptr);
     ensure_modes(M);
     emu::launch_init_rest(M->d, M->st);
@@ -854,6 +859,7 @@ ContactWork contact_carve(emu_mesh* M) {
 // Algorithm 1's contact rounds after one accepted step (q already holds
 // q*(F + sigma P); the step itself is still pending in (R, S, p, sigma)).
 void contact_rounds(emu_mesh* M) {
+  emu::Range range("emu contact rounds");
   const emu::DevMesh& d = M->d;
   ContactWork w = contact_carve(M);
   const int nbv = std::max(1, emu::contact_blocks(d));
@@ -986,6 +992,7 @@ emu_status emu_solve(emu_mesh* M, const emu_solve_opts* opts, double* q_out, emu
     return EMU_E_INVALID;
   }
   try {
+    emu::Range range("emu_solve");
     emu_solve_opts o = opts ? *opts : emu_solve_opts_default();
     if (!(o.grad_tol >= 0) || o.max_iters < 0 || !(o.sigma0 > 0) || !(o.rho > 0 && o.rho < 1) ||
         !(o.armijo_c > 0 && o.armijo_c < 1))
@@ -1114,6 +1121,7 @@ emu_status emu_evaluate(emu_mesh* M, const double* F, double* q, double* energy,
     emu::set_error("NULL argument");
     return EMU_E_INVALID;
   }
+  emu::Range range("emu_evaluate");
   try {
     join_user_stream(M, stream);
     backup_state(M);
@@ -1255,6 +1263,7 @@ size_t adj_block_doubles(const emu_mesh* M) { return adj_work_doubles(M) + 11 * 
 // Allocates nothing: every device buffer is either the mesh's or in `w`.
 emu_status adjoint_run(emu_mesh* M, const AdjWork& w, const double* dL_dq, double* dL_da, emu_solve_stats* stats,
                        void* stream) {
+  emu::Range range("emu adjoint");
   auto& d = M->d;
   const size_t m = M->hm.m, n = M->hm.n, nf = M->hm.nf;
   join_user_stream(M, stream);

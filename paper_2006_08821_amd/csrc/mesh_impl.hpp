@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cstddef>
@@ -25,6 +26,16 @@
 namespace emu {
 
 const std::string& last_error_str();
+
+// roctx range over a scope: marks the library's host-side phases (mesh setup,
+// device eigenpairs, solves, contact rounds, adjoint, serving rounds) for
+// rocprofv3 --marker-trace; no cost without a profiler attached.
+struct Range {
+  explicit Range(const char* what) { roctxRangePushA(what); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 // Everything a mesh uploads at creation, laid out in one device block: the
 // piece for DevMesh member `slot` (a byte offset into DevMesh, or one of the

@@ -23,6 +23,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <future>
@@ -181,6 +182,7 @@ struct emu_server {
   std::condition_variable cv_setup, cv_sched, cv_done;
   bool stop = false;
   uint64_t next_ticket = 1;
+  uint64_t fault_ticket = 0;  // EMU_FAULT=linesearch:T (0: none)
   std::map<uint64_t, std::unique_ptr<Request>> reqs;
   std::deque<Request*> setup_q;
   std::map<uint64_t, Request*> ready;  // by ticket: admission order
@@ -220,6 +222,7 @@ constexpr int kCtlWords = (int)(sizeof(emu::Ctl) / 4);
 constexpr size_t kMaxCacheEntries = 256;
 
 std::shared_ptr<const Setup> run_setup(const DescCopy& dc) {
+  emu::Range range("emu_server host setup");
   auto s = std::make_shared<Setup>();
   try {
     s->hm = std::make_shared<emu::HostMesh>();
@@ -416,6 +419,7 @@ void rebuild_batch(emu_server* S) {
 // Admit ready requests in submission order while a slot is free and the
 // budget allows (caller holds the lock; device work happens here too).
 void admit(emu_server* S, std::unique_lock<std::mutex>& lk) {
+  emu::Range range("emu_server admit");
   (void)lk;
   while (!S->ready.empty() && (int)S->active.size() < S->opts.max_slots) {
     Request* r = S->ready.begin()->second;
@@ -478,6 +482,7 @@ void admit(emu_server* S, std::unique_lock<std::mutex>& lk) {
 
 // One round: K iterations of every active mesh, then retire finished ones.
 void run_round(emu_server* S, std::unique_lock<std::mutex>& lk) {
+  emu::Range range("emu_server round");
   if (S->dirty) rebuild_batch(S);
   const int na = (int)S->active.size();
   HIPCHK(hipGraphLaunch(S->gexec, S->st));
@@ -502,7 +507,8 @@ void run_round(emu_server* S, std::unique_lock<std::mutex>& lk) {
     Active& a = S->active[j];
     a.req->rounds++;
     const bool cap = a.req->rounds > a.req->opts.max_iters / std::max(1, S->opts.iters_per_round) + 2;
-    if (!c.done && !cap) continue;
+    const bool fault = a.req->ticket == S->fault_ticket;  // the test hook fails this request now
+    if (!c.done && !cap && !fault) continue;
     done[j] = true;
     emu_mesh* M = a.res->mesh.get();
     std::memcpy(M->h_ctl, &c, sizeof(c));
@@ -520,8 +526,8 @@ void run_round(emu_server* S, std::unique_lock<std::mutex>& lk) {
     HIPCHK(hipStreamSynchronize(S->st));
     const double t = S->now();
     emu::fill_stats(c, &r->stats, (float)((t - r->times.t_admit) * 1e3));
-    emu_status code = c.done ? (emu_status)c.status : EMU_E_NOT_CONVERGED;
-    if (!c.done) r->stats.status = EMU_E_NOT_CONVERGED;
+    emu_status code = fault ? EMU_E_LINESEARCH : c.done ? (emu_status)c.status : EMU_E_NOT_CONVERGED;
+    r->stats.status = code;
     finish_request(S, r, code,
                    code == EMU_OK                ? ""
                    : code == EMU_E_NOT_CONVERGED ? "max_iters reached"
@@ -529,7 +535,12 @@ void run_round(emu_server* S, std::unique_lock<std::mutex>& lk) {
                                                  : "non-finite value in the iteration");
     a.res->used = Clock::now();
     a.res->state_ok = warm_start_ok(code, r->stats.grad_norm);
-    S->idle.push_back(std::move(a.res));  // stays resident for reuse
+    if (a.res->state_ok) {
+      S->idle.push_back(std::move(a.res));  // stays resident for reuse
+    } else {
+      S->resident -= a.res->mesh->bytes;  // a failed request releases its device memory
+      a.res.reset();
+    }
   }
   std::vector<Active> keep;
   for (int j = 0; j < na; ++j)
@@ -588,6 +599,10 @@ emu_status emu_server_create(const emu_server_opts* opts, emu_server** out) {
     if (S->opts.max_slots == 0) S->opts.max_slots = 64;
     if (S->opts.setup_threads == 0) S->opts.setup_threads = 4;
     if (S->opts.iters_per_round == 0) S->opts.iters_per_round = 16;
+    if (const char* f = std::getenv("EMU_FAULT")) {
+      const std::string spec(f);
+      if (spec.rfind("linesearch:", 0) == 0) S->fault_ticket = std::strtoull(spec.c_str() + 11, nullptr, 10);
+    }
     S->opts.iters_per_round = std::min(S->opts.iters_per_round, 256);
     HIPCHK(hipGetDevice(&S->device));
     if (S->opts.hbm_budget_bytes == 0) {
@@ -685,6 +700,7 @@ emu_status emu_server_report_get(emu_server* S, emu_server_report* rep) {
   }
   std::lock_guard<std::mutex> lk(S->mu);
   *rep = S->rep;
+  rep->resident_bytes = S->resident;
   return EMU_OK;
 }
 

@@ -132,3 +132,29 @@ def test_warm_reuse_of_resident_mesh(torch):
     # restarting at the converged state: one check, no further iterations
     assert st1["iters"] <= 1
     assert _disp_err(q1, q0, p.rest_xyz) <= 1e-8
+
+
+def test_failed_request_releases_slot_and_memory(torch, monkeypatch):
+    # the fault hook EMU_FAULT=linesearch:T fails the request with ticket T in
+    # its first round; it releases its slot and its mesh's device memory, and
+    # every other request of the mix ends with the same bits as without it
+    probs = _mix()[:4]
+    s = _server(iters_per_round=8)
+    tk = [s.submit(p, **OPTS) for p in probs]
+    ref = [s.wait(k) for k in tk]
+    s.close()
+    monkeypatch.setenv("EMU_FAULT", f"linesearch:{tk[1]}")
+    s = _server(iters_per_round=8)
+    tk2 = [s.submit(p, **OPTS) for p in probs]
+    assert tk2 == tk
+    out = [s.wait(k) for k in tk2]
+    rep = s.report()
+    s.close()
+    assert out[1][1]["status"] == 4  # EMU_E_LINESEARCH
+    for i in (0, 2, 3):
+        assert out[i][1]["status"] == ref[i][1]["status"] and out[i][1]["status"] in (0, 3)
+        assert np.array_equal(out[i][0], ref[i][0]), i
+    n_ok = sum(ref[i][1]["status"] == 0 for i in (0, 2, 3))
+    assert rep["completed"] == n_ok and rep["failed"] == 4 - n_ok, rep
+    kept = sum(out[i][2]["device_bytes"] for i in (0, 2, 3))
+    assert rep["resident_bytes"] == kept, (rep, kept, out[1][2]["device_bytes"])
