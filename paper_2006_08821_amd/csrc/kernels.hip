@@ -1648,63 +1648,19 @@ struct MfmaAcc<float> {
 };
 
 // Z blocks of one element (phase A): zr[p * 9 + a * 3 + b] = Z[3c + a][3c' + b]
-// for the pairs p = (0,0) (0,1) (0,2) (1,1) (1,2) (2,2).  The lane computes
-// the entries whose first F coordinate is c (c = 0, 1, 2: three lanes per
-// element share the work; c = 3 computes and stores nothing useful).
-template <typename T, bool kC = false>
-DEV void gram_zblocks(const DevMesh& d, int i, int c, T* zr) {
-  const int m = d.m;
+// for the pairs p = (0,0) (0,1) (0,2) (1,1) (1,2) (2,2), from the element's
+// rotation R and its stored block inverses (Hs: 6x6, Hk: 3x3, packed lower;
+// Hf: the coupled 9x9 inverse, kC only).  The lane computes the entries whose
+// first F coordinate is c (c = 0, 1, 2: three lanes per element share the
+// work; c = 3 computes and stores nothing useful).
+template <typename T, bool kC>
+DEV void gram_zmath(const T* Rp, const T* Hs, const T* Hk, const T* Hf, int c, T* zr) {
+  // the lane picks a row of R below: from a local copy, not from the caller's
+  // array (a pick from that array becomes a load from a chosen address and
+  // keeps the array in scratch memory)
   T R[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) R[k] = (T)d.R[k * m + i];
-  const T* Lf = (const T*)d.Lf;
-  // the stored block inverses D^{-1} (6x6 and 3x3, packed lower)
-  T Hs[21], Hk[6];
-#pragma unroll
-  for (int k = 0; k < 21; ++k) Hs[k] = Lf[k * m + i];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) Hk[k] = Lf[(21 + k) * m + i];
-  // coupled form: the full inverse blockdiag(D^{-1}) - W K^{-1} W^T in the
-  // rotated (y) coordinates, packed lower, W = D^{-1} V
-  [[maybe_unused]] T Hf[kC ? 45 : 1];
-  if constexpr (kC) {
-    T V[9][3], W[9][3];
-    fiber_V<T>(d, i, V);
-#pragma unroll
-    for (int a = 0; a < 9; ++a)
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc) {
-        T v = 0;
-#pragma unroll
-        for (int b = 0; b < 9; ++b) {
-          if ((a < 6) != (b < 6)) continue;
-          T h;
-          if (a < 6) h = Hs[(a > b ? a : b) * ((a > b ? a : b) + 1) / 2 + (a > b ? b : a)];
-          else h = Hk[(a > b ? a - 6 : b - 6) * ((a > b ? a - 6 : b - 6) + 1) / 2 + (a > b ? b - 6 : a - 6)];
-          v += h * V[b][cc];
-        }
-        W[a][cc] = v;
-      }
-    // K^{-1}, stored packed
-    T Ki[3][3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-      for (int cc = 0; cc <= r; ++cc) Ki[r][cc] = Ki[cc][r] = Lf[(kLfSplit + r * (r + 1) / 2 + cc) * m + i];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) {
-      T u0 = W[a][0] * Ki[0][0] + W[a][1] * Ki[1][0] + W[a][2] * Ki[2][0];
-      T u1 = W[a][0] * Ki[0][1] + W[a][1] * Ki[1][1] + W[a][2] * Ki[2][1];
-      T u2 = W[a][0] * Ki[0][2] + W[a][1] * Ki[1][2] + W[a][2] * Ki[2][2];
-#pragma unroll
-      for (int b = 0; b <= a; ++b) {
-        T h = T(0);
-        if (a < 6 && b < 6) h = Hs[a * (a + 1) / 2 + b];
-        else if (a >= 6 && b >= 6) h = Hk[(a - 6) * (a - 5) / 2 + (b - 6)];
-        Hf[a * (a + 1) / 2 + b] = h - (u0 * W[b][0] + u1 * W[b][1] + u2 * W[b][2]);
-      }
-    }
-  }
+  for (int k = 0; k < 9; ++k) R[k] = Rp[k];
   // per gradient-direction pair (dd <= dp): M[e][e'] = (Y H^{-1} Y^T)[(e,dd),(e',dp)],
   // then Z[(c,dd),(c',dp)] = (R M R^T)[c][c'], stored in the block of (min, max)(c, c')
   const int cr = c < 2 ? c : 2;
@@ -1767,6 +1723,188 @@ DEV void gram_zblocks(const DevMesh& d, int i, int c, T* zr) {
     }
 }
 
+// The same for element i, reading R and the block inverses from memory.
+template <typename T, bool kC = false>
+DEV void gram_zblocks(const DevMesh& d, int i, int c, T* zr) {
+  const int m = d.m;
+  T R[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) R[k] = (T)d.R[k * m + i];
+  const T* Lf = (const T*)d.Lf;
+  // the stored block inverses D^{-1} (6x6 and 3x3, packed lower)
+  T Hs[21], Hk[6];
+#pragma unroll
+  for (int k = 0; k < 21; ++k) Hs[k] = Lf[k * m + i];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) Hk[k] = Lf[(21 + k) * m + i];
+  // coupled form: the full inverse blockdiag(D^{-1}) - W K^{-1} W^T in the
+  // rotated (y) coordinates, packed lower, W = D^{-1} V
+  [[maybe_unused]] T Hf[kC ? 45 : 1];
+  if constexpr (kC) {
+    T V[9][3], W[9][3];
+    fiber_V<T>(d, i, V);
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        T v = 0;
+#pragma unroll
+        for (int b = 0; b < 9; ++b) {
+          if ((a < 6) != (b < 6)) continue;
+          T h;
+          if (a < 6) h = Hs[(a > b ? a : b) * ((a > b ? a : b) + 1) / 2 + (a > b ? b : a)];
+          else h = Hk[(a > b ? a - 6 : b - 6) * ((a > b ? a - 6 : b - 6) + 1) / 2 + (a > b ? b - 6 : a - 6)];
+          v += h * V[b][cc];
+        }
+        W[a][cc] = v;
+      }
+    // K^{-1}, stored packed
+    T Ki[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int cc = 0; cc <= r; ++cc) Ki[r][cc] = Ki[cc][r] = Lf[(kLfSplit + r * (r + 1) / 2 + cc) * m + i];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      T u0 = W[a][0] * Ki[0][0] + W[a][1] * Ki[1][0] + W[a][2] * Ki[2][0];
+      T u1 = W[a][0] * Ki[0][1] + W[a][1] * Ki[1][1] + W[a][2] * Ki[2][1];
+      T u2 = W[a][0] * Ki[0][2] + W[a][1] * Ki[1][2] + W[a][2] * Ki[2][2];
+#pragma unroll
+      for (int b = 0; b <= a; ++b) {
+        T h = T(0);
+        if (a < 6 && b < 6) h = Hs[a * (a + 1) / 2 + b];
+        else if (a >= 6 && b >= 6) h = Hk[(a - 6) * (a - 5) / 2 + (b - 6)];
+        Hf[a * (a + 1) / 2 + b] = h - (u0 * W[b][0] + u1 * W[b][1] + u2 * W[b][2]);
+      }
+    }
+  }
+  gram_zmath<T, kC>(R, Hs, Hk, Hf, c, zr);
+}
+
+// Broadcast within a quad of lanes: every lane gets lane K's value.
+template <int K>
+DEV double quad_bcast(double x) {
+  constexpr int ctrl = K * 0x55;  // quad_perm [K, K, K, K]
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, ctrl, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), ctrl, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int K>
+DEV float quad_bcast(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), K * 0x55, 0xF, 0xF, true));
+}
+template <typename U>
+DEV U quad_from(U x, int k) {
+  switch (k) {
+    case 0: return quad_bcast<0>(x);
+    case 1: return quad_bcast<1>(x);
+    case 2: return quad_bcast<2>(x);
+    default: return quad_bcast<3>(x);
+  }
+}
+
+// Phase A inputs of one element (split blocks), loaded one batch ahead of
+// their use and spread over the element's four lanes: lane s holds rows
+// s, s + 4, ... of each per-element array (R, the stored block inverses,
+// gbar, D_m^{-1}); the quad broadcasts them when the batch is formed.  The
+// vertex ids are loaded one batch earlier still, so that the mode-gradient
+// gather that depends on them is issued together with the rest.
+template <typename T>
+struct GramPart {
+  T R[3], Lf[7], gb[3];
+  double bm[3];
+  T w;
+};
+template <typename T>
+DEV void gram_load_part(const DevMesh& d, int i, int s, GramPart<T>& g) {
+  const int m = d.m;
+  const T* Lf = (const T*)d.Lf;
+  const T* gbar = (const T*)d.gbar;
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int r = min(s + 4 * u, 8);  // rows past the end repeat row 8 (unused)
+    g.R[u] = (T)d.R[r * m + i];
+    g.gb[u] = gbar[r * m + i];
+    g.bm[u] = d.dminv[r * m + i];
+  }
+#pragma unroll
+  for (int u = 0; u < 7; ++u) g.Lf[u] = Lf[min(s + 4 * u, 26) * m + i];
+  // affine bone tets enter through their bone's row (k_bone_blocks)
+  g.w = (d.nbones && d.bone_pos[i] >= 0) ? T(0) : (T)d.w[i];
+}
+DEV void gram_load_vid(const DevMesh& d, int i, int32_t (&vid)[4]) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) vid[v] = d.vid[v * d.m + i];
+}
+// modes q4 .. q4 + 3 of the element's four vertices
+DEV void gram_load_phi(const DevMesh& d, const int32_t (&vid)[4], int q4, double (&ph)[4][4]) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double2* p = reinterpret_cast<const double2*>(d.phi + (int64_t)kMaxK1 * vid[v] + q4);
+    const double2 p0 = p[0], p1 = p[1];
+    ph[v][0] = p0.x;
+    ph[v][1] = p0.y;
+    ph[v][2] = p1.x;
+    ph[v][3] = p1.y;
+  }
+}
+// Phase A of one element from the quad's registers: lane sl writes its Z
+// entries and row sl of R D(gbar) (sl < 3) or w (sl = 3), and mode
+// gradients 4 sl .. 4 sl + 3.
+template <typename T>
+DEV void gram_phase_a(const GramPart<T>& g, const double (&ph)[4][4], int sl, int k1, T* zr, T* gr) {
+  T R[9], Hs[21], Hk[6];
+#pragma unroll
+  for (int r = 0; r < 9; ++r) R[r] = quad_from(g.R[r / 4], r % 4);
+#pragma unroll
+  for (int r = 0; r < 27; ++r) {
+    const T v = quad_from(g.Lf[r / 4], r % 4);
+    if (r < 21) Hs[r] = v;
+    else Hk[r - 21] = v;
+  }
+  gram_zmath<T, false>(R, Hs, Hk, nullptr, sl, zr);
+  // gbar and D_m^{-1} after the Z blocks, when their registers are free
+  double gbd[9], bm[9];
+#pragma unroll
+  for (int r = 0; r < 9; ++r) {
+    gbd[r] = (double)quad_from(g.gb[r / 4], r % 4);
+    bm[r] = quad_from(g.bm[r / 4], r % 4);
+  }
+  if (sl < 3) {
+    double D[9];
+    from_y<double>(gbd, D);
+    const double r0 = (double)(sl == 0 ? R[0] : (sl == 1 ? R[3] : R[6]));
+    const double r1 = (double)(sl == 0 ? R[1] : (sl == 1 ? R[4] : R[7]));
+    const double r2 = (double)(sl == 0 ? R[2] : (sl == 1 ? R[5] : R[8]));
+#pragma unroll
+    for (int q = 0; q < 3; ++q) zr[54 + 3 * sl + q] = (T)(r0 * D[q] + r1 * D[3 + q] + r2 * D[6 + q]);
+  } else {
+    zr[63] = g.w;
+  }
+  double b[4][3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) b[v][c] = bm[3 * v + c];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) b[3][c] = -(b[0][c] + b[1][c] + b[2][c]);
+  double gg[4][3];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) gg[q][0] = gg[q][1] = gg[q][2] = 0.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gg[q][c] += ph[v][q] * b[v][c];
+  const int q4 = 4 * sl;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gr[3 * (q4 + q) + c] = q4 + q < k1 ? (T)gg[q][c] : T(0);
+}
+
 template <typename T, bool kC = false>
 DEV void b_gram(const DevMesh& d, int bid) {
   if (d.ctl->done) return;
@@ -1792,14 +1930,30 @@ DEV void b_gram(const DevMesh& d, int bid) {
 #pragma unroll
   for (int p = 0; p < 6; ++p) acc[p] = v4{0, 0, 0, 0};
   T y0 = 0, y1 = 0, y2 = 0;  // y[(c, j)] partials of this lane's K slot
+  const int el = lane >> 2, sl = lane & 3;
+  // split blocks: the next batch's inputs are requested before this batch's
+  // products, so their latency overlaps the matrix-core work
+  [[maybe_unused]] GramPart<T> nxt;
+  [[maybe_unused]] double ph[4][4];
+  [[maybe_unused]] int32_t vid[4];
+  if constexpr (!kC) {
+    if (el < min(kGramBatch, w1 - w0)) {
+      gram_load_vid(d, w0 + el, vid);
+      gram_load_part<T>(d, w0 + el, sl, nxt);
+      gram_load_phi(d, vid, 4 * sl, ph);
+    }
+    if (w0 + kGramBatch < w1 && el < min(kGramBatch, w1 - w0 - kGramBatch)) gram_load_vid(d, w0 + kGramBatch + el, vid);
+  }
   for (int base = w0; base < w1; base += kGramBatch) {
     const int ne = min(kGramBatch, w1 - base);
-    {
-      // four lanes per element: lane s = 0, 1, 2 forms the Z entries and the
-      // row of R D(gbar) of F coordinate s, lane 3 stores w; each lane forms
-      // four of the sixteen mode gradients gphi_j = sum_v phi_j(v) b_v (rows
-      // of phi are zero beyond k1 and at pins)
-      const int el = lane >> 2, sl = lane & 3, q4 = 4 * sl;
+    // four lanes per element: lane s = 0, 1, 2 forms the Z entries and the
+    // row of R D(gbar) of F coordinate s, lane 3 stores w; each lane forms
+    // four of the sixteen mode gradients gphi_j = sum_v phi_j(v) b_v (rows
+    // of phi are zero beyond k1 and at pins)
+    if constexpr (!kC) {
+      if (el < ne) gram_phase_a<T>(nxt, ph, sl, k1, zw[el], gw[el]);
+    } else {
+      const int q4 = 4 * sl;
       if (el < ne) {
         const int i = base + el;
         gram_zblocks<T, kC>(d, i, sl, zw[el]);
@@ -1846,6 +2000,16 @@ DEV void b_gram(const DevMesh& d, int bid) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if constexpr (!kC) {
+      // the next batch's rows and mode gradients (its vertex ids are here
+      // already), then the vertex ids of the batch after it
+      const int nb = base + kGramBatch, nb2 = nb + kGramBatch;
+      if (nb < w1 && el < min(kGramBatch, w1 - nb)) {
+        gram_load_part<T>(d, nb + el, sl, nxt);
+        gram_load_phi(d, vid, 4 * sl, ph);
+      }
+      if (nb2 < w1 && el < min(kGramBatch, w1 - nb2)) gram_load_vid(d, nb2 + el, vid);
+    }
     // The K dimension of each product runs over (element, coordinate) pairs
     // of the batch: step st takes the pairs f = 4 st + ks (ks = lane / 16, the
     // lane's K slot) with element f / 3 and coordinate f % 3, so all four
@@ -1923,8 +2087,11 @@ DEV void b_gram(const DevMesh& d, int bid) {
 // (more element gathers in flight per CU than its caches serve).
 template <typename T>
 constexpr int gram_max_waves() { return sizeof(T) == 4 ? 3 : 8; }
+template <typename T, bool kC>
+constexpr int gram_min_waves() { return sizeof(T) == 8 && !kC ? 2 : 1; }
 template <typename T, bool kC = false>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, gram_max_waves<T>())))
+__global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(gram_min_waves<T, kC>(), gram_max_waves<T>())))
 k_gram(DevMesh d) { b_gram<T, kC>(d, blockIdx.x); }
 
 // Partial Gram sums: 16 threads per entry sum interleaved workgroup partials,
@@ -3117,8 +3284,15 @@ EMU_BATCHED(kb_element64, kBlock, b_element<double>(d, e.y))
 EMU_BATCHED(kb_element32, kBlock, b_element<float>(d, e.y))
 EMU_BATCHED(kb_element_hess64, kBlock, b_element_hess<double>(d, e.y))
 EMU_BATCHED(kb_element_hess32, kBlock, b_element_hess<float>(d, e.y))
-EMU_BATCHED(kb_gram64, kBlock, b_gram<double>(d, e.y))
-EMU_BATCHED(kb_gram32, kBlock, b_gram<float>(d, e.y))
+// the Gram pass with the occupancy bounds of k_gram
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(gram_min_waves<T, false>(), gram_max_waves<T>())))
+kb_gram(const DevMesh* __restrict__ ms, const int2* __restrict__ map) {
+  const int2 e = map[blockIdx.x];
+  const DevMesh d = ms[e.x];
+  b_gram<T>(d, e.y);
+}
 EMU_BATCHED(kb_gram_reduce, kBlock, b_gram_reduce(d, e.y))
 EMU_BATCHED(kb_control_a, kCtlThreads, b_control_a(d, e.y))
 EMU_BATCHED(kb_uz, kBlock, b_uz(d, e.y))
@@ -3385,7 +3559,7 @@ void launch_batch_iteration(const BatchPlan& b, hipStream_t st) {
   if (b.n_meshes == 0) return;
   launch_map(b.mixed ? kb_element32 : kb_element64, b, b.element, kBlock, st);
   launch_map(b.mixed ? kb_element_hess32 : kb_element_hess64, b, b.element, kBlock, st);
-  launch_map(b.mixed ? kb_gram32 : kb_gram64, b, b.gram, kBlock, st);
+  launch_map(b.mixed ? kb_gram<float> : kb_gram<double>, b, b.gram, kBlock, st);
   launch_map(kb_gram_reduce, b, b.gram_reduce, kBlock, st);
   launch_map(kb_control_a, b, b.one, kCtlThreads, st);
   launch_map(kb_uz, b, b.uz, kBlock, st);
