@@ -391,7 +391,7 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
       it.col0 = fac.col0[s];
       it.slotbase = slotbase[s];
       it.nslot = fac.child_ptr[s + 1] - fac.child_ptr[s];
-      it.pad = 0;
+      it.end = 0;
       it.rowoff = fac.rowoff[s];
       return it;
     };
@@ -418,16 +418,30 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
     // smaller load window.
     pl.fwd_narrow.assign(fac.nlevels, 1);
     pl.bwd_narrow.assign(fac.nlevels, 1);
+    pl.fwd_col.assign(fac.nlevels, 1);
+    for (int L = 0; L < fac.nlevels; ++L)
+      for (int s = 0; s < fac.ns; ++s)
+        if (fac.level[s] == L && (fac.w[s] > emu::kColW || fac.parent[s] < 0)) pl.fwd_col[L] = 0;
     for (int L = 0; L < fac.nlevels; ++L) {
+      const size_t n0 = fwd.size();
       for (int s = 0; s < fac.ns; ++s)
         if (fac.level[s] == L) {
+          // rows further down need more of the frontal vector: heaviest first
+          if (pl.fwd_col[L]) {
+            for (int r = (fac.h[s] - 1) / emu::kColRows * emu::kColRows; r >= 0; r -= emu::kColRows)
+              fwd.push_back(item(s, r | emu::kItemColBit));
+            continue;
+          }
           const bool wide = fac.parent[s] < 0 && fac.w[s] >= 256;
           if (wide || fac.w[s] > emu::kNarrowFwdW) pl.fwd_narrow[L] = 0;
           const int step = wide ? 8 : 32;
-          // rows further down need more of the frontal vector: heaviest first
           for (int r = (fac.h[s] - 1) / step * step; r >= 0; r -= step)
             fwd.push_back(item(s, r | (wide ? emu::kItemWideBit : 0)));
         }
+      if (pl.fwd_col[L]) {
+        pl.fwd_narrow[L] = 0;
+        for (size_t k = n0; k < fwd.size(); ++k) fwd[k].end = (int32_t)fwd.size();
+      }
       pl.fwd_ptr[L + 1] = (int)fwd.size();
     }
     for (int L = fac.nlevels - 1, k = 0; L >= 0; --L, ++k) {

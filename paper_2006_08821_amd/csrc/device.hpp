@@ -18,6 +18,12 @@ constexpr int kLsTerms = 6;        // coefficients of the line-search polynomial
 constexpr int kItemWideBit = 1 << 30;
 constexpr int kWideLevelItems = 512;
 constexpr int kWideRowMin = 64;
+// Forward levels whose supernodes are all at most kColW wide run in column
+// form instead: one wave per item of kColRows rows (flag kItemColBit in the
+// first row), one lane per row, walking the columns of the column-major block.
+constexpr int kItemColBit = 1 << 29;
+constexpr int kColW = 128;
+constexpr int kColRows = 64;
 constexpr int kNarrowChunk = 512;     // vector chunk of the narrow sweep variant (12 KB of LDS)
 constexpr int kNarrowFwdW = 64;       // widest supernode of a forward level run narrow
 constexpr int kNarrowBwdH = 256;      // tallest supernode of a backward level run narrow
@@ -50,12 +56,14 @@ struct Ctl {
 // Plain pointers to every device array of a mesh (passed by value).
 // A work item of a triangular sweep with its supernode's metadata, read by
 // the workgroup in one scalar load: first row (forward) or column (backward),
-// with kItemWideBit marking 32 lanes per row; supernode width w, height h,
-// first column col0, first slot row of the children's contributions and the
-// number of children (nslot), row offset, value offset.
+// with kItemWideBit marking 32 lanes per row and kItemColBit a column-form
+// item; supernode width w, height h, first column col0, first slot row of the
+// children's contributions and the number of children (nslot), row offset,
+// value offset; for column-form items, `end` is one past the last item of the
+// level (a workgroup takes four consecutive items, one per wave).
 struct SweepItem {
   int64_t valoff;
-  int32_t first, w, h, col0, slotbase, nslot, rowoff, pad;
+  int32_t first, w, h, col0, slotbase, nslot, rowoff, end;
 };
 
 struct DevMesh {

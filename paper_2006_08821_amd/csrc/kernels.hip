@@ -1196,6 +1196,108 @@ DEV void fwd_item(const DevMesh& d, const SweepItem& it, int r0, double* ft) {
     }
   }
 }
+// Column form (levels of narrow supernodes, w <= kColW): one wave per item of
+// kColRows rows; lane l computes row r = r0 + l from the column-major copy of
+// the block (tvals: column c holds rows c .. h-1), so every column step is one
+// coalesced load across the wave, while the frontal vector, gathered once per
+// item into the wave's LDS slice ft, is read as a broadcast.  The block
+// entries stream in chunks of kColChunk columns, two chunks in flight: the
+// first chunk and the children's updates of the lane's output row are
+// requested before the frontal gather.
+constexpr int kColChunk = 8;
+// columns cb .. cb + kColChunk - 1 of row rr (zero past the lane's nc).  blk
+// is the supernode's column-major block, column c starting at
+// c h - c (c - 1) / 2 with entry r at index r - c; every load is at a column
+// clamped to w - 1 and a row clamped to h - 1 by the caller, so it stays
+// inside the block, and the column base is the same for the whole wave.
+DEV void col_chunk(const double* blk, int h, int w, int rr, int nc, int cb, double (&x)[kColChunk]) {
+#pragma unroll
+  for (int u = 0; u < kColChunk; ++u) {
+    const int c = min(cb + u, w - 1);
+    const double* cp = blk + ((int64_t)c * h - (int64_t)c * (c - 1) / 2 - c);
+    const double v = cp[rr];
+    x[u] = cb + u < nc ? v : 0.0;
+  }
+}
+DEV void col_fma(const double (&x)[kColChunk], const double* ft, int cb, double& a0, double& a1, double& a2) {
+#pragma unroll
+  for (int u = 0; u < kColChunk; ++u) {
+    a0 += x[u] * ft[3 * (cb + u)];
+    a1 += x[u] * ft[3 * (cb + u) + 1];
+    a2 += x[u] * ft[3 * (cb + u) + 2];
+  }
+}
+DEV void fwd_col_item(const DevMesh& d, const SweepItem& it, double* ft) {
+  const int w = it.w, h = it.h, col0 = it.col0, r0 = it.first & ~kItemColBit;
+  const int lane = threadIdx.x & 63;
+  const int r = r0 + lane;
+  const int nc = r < h ? min(r + 1, w) : 0;
+  const int rr = min(r, h - 1);
+  const double* blk = d.tvals + it.valoff;
+  double xa[kColChunk], xb[kColChunk];
+  col_chunk(blk, h, w, rr, nc, 0, xa);
+  double b0 = 0, b1 = 0, b2 = 0;
+  int32_t orow = 0;
+  if (r < h && r >= w) {
+    orow = d.dst[it.rowoff + r - w];
+    gather_updates(d, it, r, b0, b1, b2);
+  }
+  // frontal vector; zero past `need` up to the end of the last chunk, so the
+  // zero entries of a partial chunk multiply zeros
+  const int need = min(w, r0 + kColRows);
+  const int ceil_need = (need + kColChunk - 1) / kColChunk * kColChunk;
+  for (int c = lane; c < ceil_need; c += 64) {
+    double a0 = 0, a1 = 0, a2 = 0;
+    if (c < need) {
+      a0 = d.rhs[3 * (col0 + c)];
+      a1 = d.rhs[3 * (col0 + c) + 1];
+      a2 = d.rhs[3 * (col0 + c) + 2];
+      gather_updates(d, it, c, a0, a1, a2);
+    }
+    ft[3 * c] = a0;
+    ft[3 * c + 1] = a1;
+    ft[3 * c + 2] = a2;
+  }
+  // the wave's own LDS writes, visible to all of its lanes
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (r >= h) return;
+  // the chunk loop runs to `need` for the whole wave (uniform column index;
+  // a lane's entries past its own nc load as zeros)
+  double a0 = 0, a1 = 0, a2 = 0;
+  for (int c = 0;;) {
+    if (c + kColChunk < need) col_chunk(blk, h, w, rr, nc, c + kColChunk, xb);
+    col_fma(xa, ft, c, a0, a1, a2);
+    c += kColChunk;
+    if (c >= need) break;
+    if (c + kColChunk < need) col_chunk(blk, h, w, rr, nc, c + kColChunk, xa);
+    col_fma(xb, ft, c, a0, a1, a2);
+    c += kColChunk;
+    if (c >= need) break;
+  }
+  if (r < w) {
+    d.ybuf[3 * (col0 + r)] = a0;
+    d.ybuf[3 * (col0 + r) + 1] = a1;
+    d.ybuf[3 * (col0 + r) + 2] = a2;
+  } else {
+    double* o = d.slots + 3 * (int64_t)orow;
+    o[0] = b0 - a0;
+    o[1] = b1 - a1;
+    o[2] = b2 - a2;
+  }
+}
+// A workgroup of column-form items: wave k takes item base + k if it is in
+// the level (ft: kColW * 3 doubles per wave).
+DEV void fwd_col_group(const DevMesh& d, int base, int end, double* ft) {
+  // the wave index is uniform across the wave: with readfirstlane the item and
+  // the block base live in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  if (base + wave >= end) return;
+  const SweepItem it = d.fwd_items[base + wave];
+  fwd_col_item(d, it, ft + wave * kColW * 3);
+}
+
 template <int CH>
 DEV void b_fwd_t(const DevMesh& d, int bid, int check_done) {
   // the item and the stop flag are read in the same scalar round trip (the
@@ -1207,6 +1309,13 @@ DEV void b_fwd_t(const DevMesh& d, int bid, int check_done) {
   if (done) return;
   __shared__ double ft[CH * 3];
   if constexpr (CH == kVecChunk) {
+    // column-form items reach this body only through the batched launch,
+    // whose map holds the first item of each group of four
+    static_assert(CH >= 4 * kColW, "column items share the vector chunk");
+    if (it.first & kItemColBit) {
+      fwd_col_group(d, bid, it.end, ft);
+      return;
+    }
     if (it.first & kItemWide) {
       fwd_item<32, CH>(d, it, it.first & ~kItemWide, ft);
       return;
@@ -1222,6 +1331,15 @@ __global__ void __launch_bounds__(kBlock) k_fwd(DevMesh d, int it0, int check_do
 }
 __global__ void __launch_bounds__(kBlock, 8) k_fwd_narrow(DevMesh d, int it0, int check_done) {
   b_fwd_t<kVecChunkNarrow>(d, it0 + xcd_block((int)blockIdx.x, (int)gridDim.x), check_done);
+}
+// column-form level: workgroup b takes items it0 + 4 b .. it0 + 4 b + 3 (two
+// chunks of block entries in flight need more than the 64 registers of eight
+// waves per SIMD)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8)))
+k_fwd_col(DevMesh d, int it0, int it1, int check_done) {
+  if (check_done && d.ctl->done) return;
+  __shared__ double ft[4 * kColW * 3];
+  fwd_col_group(d, it0 + 4 * xcd_block((int)blockIdx.x, (int)gridDim.x), it1, ft);
 }
 
 // Backward sweep of one level with the transposed blocks.  Work item (s, c0):
@@ -1289,7 +1407,8 @@ __global__ void __launch_bounds__(kBlock, 8) k_bwd_narrow(DevMesh d, int it0, do
 static void launch_fwd_level(const DevMesh& d, const SolvePlan& pl, int L, int check_done, hipStream_t st) {
   const int n0 = pl.fwd_ptr[L], n1 = pl.fwd_ptr[L + 1];
   if (n1 <= n0) return;
-  if (pl.fwd_narrow[L]) hipLaunchKernelGGL(k_fwd_narrow, dim3(n1 - n0), dim3(kBlock), 0, st, d, n0, check_done);
+  if (pl.fwd_col[L]) hipLaunchKernelGGL(k_fwd_col, dim3((n1 - n0 + 3) / 4), dim3(kBlock), 0, st, d, n0, n1, check_done);
+  else if (pl.fwd_narrow[L]) hipLaunchKernelGGL(k_fwd_narrow, dim3(n1 - n0), dim3(kBlock), 0, st, d, n0, check_done);
   else hipLaunchKernelGGL(k_fwd, dim3(n1 - n0), dim3(kBlock), 0, st, d, n0, check_done);
 }
 static void launch_bwd_level(const DevMesh& d, const SolvePlan& pl, int k, double* x, int check_done,
@@ -3603,9 +3722,12 @@ void batch_layout(const std::vector<const DevMesh*>& ms, const std::vector<const
   for (int L = 0; L < nl; ++L) {
     BatchClass& c = b.fwd[L];
     c.offset = (int64_t)map.size();
+    // column-form levels: one entry per group of four items
     for (int j = 0; j < nm; ++j)
-      if (L < plans[j]->nlevels)
-        for (int it = plans[j]->fwd_ptr[L]; it < plans[j]->fwd_ptr[L + 1]; ++it) map.push_back(make_int2(j, it));
+      if (L < plans[j]->nlevels) {
+        const int step = plans[j]->fwd_col[L] ? 4 : 1;
+        for (int it = plans[j]->fwd_ptr[L]; it < plans[j]->fwd_ptr[L + 1]; it += step) map.push_back(make_int2(j, it));
+      }
     c.count = (int)((int64_t)map.size() - c.offset);
   }
   for (int L = 0; L < nl; ++L) {

@@ -23,6 +23,8 @@ struct SolvePlan {
   // per level: every item is short (8 lanes per row, one vector chunk of
   // kNarrowChunk), so the level runs the 8-waves-per-SIMD variant
   std::vector<char> fwd_narrow, bwd_narrow;
+  // per forward level: column-form items (kItemColBit), four per workgroup
+  std::vector<char> fwd_col;
 };
 
 // Launch layout of one iteration over several meshes (same precision): for
