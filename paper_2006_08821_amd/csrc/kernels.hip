@@ -507,6 +507,49 @@ DEV void chol_inverse(const T* L, T* P) {
       P[r * (r + 1) / 2 + c] = v;
     }
 }
+// The same inverse stored straight to memory (out[(packed index) * m + i]) with
+// x <- P x on the way, holding only L^{-1} in registers: x = L^{-T} (L^{-1} x),
+// and every entry of P is stored as soon as it is formed.
+template <typename T, int N>
+DEV void chol_inverse_apply_store(const T* L, T* x, T* out, int m, int i) {
+  T Li[N * (N + 1) / 2];
+#pragma unroll
+  for (int c = 0; c < N; ++c) Li[c * (c + 1) / 2 + c] = T(1) / L[c * (c + 1) / 2 + c];
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+#pragma unroll
+    for (int r = c + 1; r < N; ++r) {
+      T v = 0;
+#pragma unroll
+      for (int k = c; k < r; ++k) v += L[r * (r + 1) / 2 + k] * Li[k * (k + 1) / 2 + c];
+      Li[r * (r + 1) / 2 + c] = -v * Li[r * (r + 1) / 2 + r];
+    }
+  }
+  T z[N];
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    T v = 0;
+#pragma unroll
+    for (int k = 0; k <= r; ++k) v += Li[r * (r + 1) / 2 + k] * x[k];
+    z[r] = v;
+  }
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    T v = 0;
+#pragma unroll
+    for (int r = c; r < N; ++r) v += Li[r * (r + 1) / 2 + c] * z[r];
+    x[c] = v;
+  }
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int c = 0; c <= r; ++c) {
+      T v = 0;
+#pragma unroll
+      for (int k = r; k < N; ++k) v += Li[k * (k + 1) / 2 + r] * Li[k * (k + 1) / 2 + c];
+      out[(int64_t)(r * (r + 1) / 2 + c) * m + i] = v;
+    }
+}
 // x <- P x for a packed (lower) symmetric P.
 template <typename T, int N>
 DEV void sym_apply(const T* P, T* x) {
@@ -1655,15 +1698,12 @@ DEV void b_element_hess(const DevMesh& d, int bid) {
         T Ls[21];
         if (chol_packed<T, 6>(Hs, Ls)) {
           add_factor<T, 6>(Hs, beta, Ls);
-          T Ps[21], gs[6];
-          chol_inverse<T, 6>(Ls, Ps);
+          T gs[6];
 #pragma unroll
           for (int k = 0; k < 6; ++k) gs[k] = gbar[k * m + i];
-          sym_apply<T, 6>(Ps, gs);
+          chol_inverse_apply_store<T, 6>(Ls, gs, Lf, m, i);
 #pragma unroll
           for (int k = 0; k < 6; ++k) gbar[k * m + i] = gs[k];
-#pragma unroll
-          for (int k = 0; k < 21; ++k) Lf[k * m + i] = Ps[k];
         } else {
 #pragma unroll
           for (int r = 0; r < 6; ++r)
@@ -1672,17 +1712,14 @@ DEV void b_element_hess(const DevMesh& d, int bid) {
           fix[atomicAdd(&nfix, 1)] = i;
         }
       }
-      T Lk[6], Pk[6];
+      T Lk[6];
       nclamp += clamp_add_factor<T, 3>(Hk, beta, Lk);
-      chol_inverse<T, 3>(Lk, Pk);
       T gk[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) gk[k] = gbar[(6 + k) * m + i];
-      sym_apply<T, 3>(Pk, gk);
+      chol_inverse_apply_store<T, 3>(Lk, gk, Lf + (int64_t)21 * m, m, i);
 #pragma unroll
       for (int k = 0; k < 3; ++k) gbar[(6 + k) * m + i] = gk[k];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) Lf[(21 + k) * m + i] = Pk[k];
     } else if (i < m) {
       // an affine bone tet: identity blocks and gbar = 0, so that the Gram
       // pass (which gives it weight 0) reads finite values; k_bone_blocks
@@ -1729,7 +1766,8 @@ DEV void b_element_hess(const DevMesh& d, int bid) {
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_element(DevMesh d) { b_element<T>(d, blockIdx.x); }
 template <typename T, bool kC = false>
-__global__ void __launch_bounds__(kBlock) k_element_hess(DevMesh d) { b_element_hess<T, kC>(d, blockIdx.x); }
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8)))
+k_element_hess(DevMesh d) { b_element_hess<T, kC>(d, blockIdx.x); }
 
 // --------------------------------------------------------------- Woodbury Gram
 // Per element: Z = T H^{-1} T^T (9x9, F coordinates; T = (R (x) I) Y) and the
