@@ -16,7 +16,7 @@ constexpr int kLsTerms = 6;        // coefficients of the line-search polynomial
 // with fewer than kWideLevelItems 32-row items use the wide form for
 // supernodes whose rows are at least kWideRowMin long.
 constexpr int kItemWideBit = 1 << 30;
-constexpr int kWideLevelItems = 512;
+constexpr int kWideLevelItems = 256;
 constexpr int kWideRowMin = 64;
 // Forward levels whose supernodes are all at most kColW wide run in column
 // form instead: one wave per item of kColRows rows (flag kItemColBit in the
