@@ -178,6 +178,11 @@ typedef struct {
   double mu_ref, alpha, fiber_k;
   double setup_ms;           /* host setup time (ordering, factor, modes, upload) */
   double mode_captured;      /* sum_{j<=k/3} 1/nu_j / trace(L_ff^{-1}) estimate    */
+  /* forward-sweep levels run in column form (one lane per row over the
+     column-major block; levels of many narrow supernodes, or every level
+     whose supernodes are narrow when EMU_FWD_COLUMN=1 is set at creation;
+     none with EMU_FWD_COLUMN=0); 0 for a host-only setup */
+  int32_t fwd_column_levels;
 } emu_mesh_info;
 
 emu_solve_opts emu_solve_opts_default(void);

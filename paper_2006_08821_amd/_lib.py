@@ -59,7 +59,7 @@ class MeshInfo(C.Structure):
                 ("n_modes", C.c_int32), ("n_supernodes", C.c_int32), ("n_levels", C.c_int32),
                 ("factor_nnz", C.c_int64), ("device_bytes", C.c_int64), ("mu_ref", C.c_double),
                 ("alpha", C.c_double), ("fiber_k", C.c_double), ("setup_ms", C.c_double),
-                ("mode_captured", C.c_double)]
+                ("mode_captured", C.c_double), ("fwd_column_levels", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -419,9 +420,19 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
     pl.fwd_narrow.assign(fac.nlevels, 1);
     pl.bwd_narrow.assign(fac.nlevels, 1);
     pl.fwd_col.assign(fac.nlevels, 1);
-    for (int L = 0; L < fac.nlevels; ++L)
-      for (int s = 0; s < fac.ns; ++s)
-        if (fac.level[s] == L && (fac.w[s] > emu::kColW || fac.parent[s] < 0)) pl.fwd_col[L] = 0;
+    {
+      std::vector<int64_t> col_items(fac.nlevels, 0);
+      for (int s = 0; s < fac.ns; ++s) {
+        col_items[fac.level[s]] += (fac.h[s] + emu::kColRows - 1) / emu::kColRows;
+        if (fac.w[s] > emu::kColW || fac.parent[s] < 0) pl.fwd_col[fac.level[s]] = 0;
+      }
+      // EMU_FWD_COLUMN=0: never, =1: wherever the widths allow (both for
+      // tests and tuning); otherwise levels with enough items
+      const char* force = std::getenv("EMU_FWD_COLUMN");
+      const int mode = force && force[0] == '0' ? 0 : (force && force[0] == '1' ? 1 : 2);
+      for (int L = 0; L < fac.nlevels; ++L)
+        if (mode == 0 || (mode == 2 && col_items[L] < emu::kColMinItems)) pl.fwd_col[L] = 0;
+    }
     for (int L = 0; L < fac.nlevels; ++L) {
       const size_t n0 = fwd.size();
       for (int s = 0; s < fac.ns; ++s)
@@ -757,6 +768,7 @@ emu_status emu_mesh_get_info(const emu_mesh* M, emu_mesh_info* info) {
   info->fiber_k = hm.kf;
   info->setup_ms = hm.setup_ms;
   info->mode_captured = hm.mode_captured;
+  for (char c : M->plan.fwd_col) info->fwd_column_levels += c ? 1 : 0;
   return EMU_OK;
 }
 

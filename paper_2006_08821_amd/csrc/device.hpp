@@ -18,12 +18,15 @@ constexpr int kLsTerms = 6;        // coefficients of the line-search polynomial
 constexpr int kItemWideBit = 1 << 30;
 constexpr int kWideLevelItems = 256;
 constexpr int kWideRowMin = 64;
-// Forward levels whose supernodes are all at most kColW wide run in column
-// form instead: one wave per item of kColRows rows (flag kItemColBit in the
-// first row), one lane per row, walking the columns of the column-major block.
+// Forward levels whose supernodes are all at most kColW wide and that have at
+// least kColMinItems such items run in column form instead: one wave per
+// item of kColRows rows (flag kItemColBit in the first row), one lane per
+// row, walking the columns of the column-major block.  With fewer items (two
+// waves per SIMD) the 8-lane rows of the row form spread the work wider.
 constexpr int kItemColBit = 1 << 29;
 constexpr int kColW = 128;
 constexpr int kColRows = 64;
+constexpr int kColMinItems = 2048;
 constexpr int kNarrowChunk = 512;     // vector chunk of the narrow sweep variant (12 KB of LDS)
 constexpr int kNarrowFwdW = 64;       // widest supernode of a forward level run narrow
 constexpr int kNarrowBwdH = 256;      // tallest supernode of a backward level run narrow
