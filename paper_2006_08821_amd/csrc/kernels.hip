@@ -2512,23 +2512,31 @@ DEV void b_control_a(const DevMesh& d, int bid) {
 }
 __global__ void __launch_bounds__(kCtlThreads) k_control_a(DevMesh d) { b_control_a(d, blockIdx.x); }
 
-// uz[v][c] = sum_j z[(c,j)] phi_j(v)  (zero at pinned vertices)
+// uz[v][c] = sum_j z[(c,j)] phi_j(v)  (zero at pinned vertices).  Four lanes
+// per vertex: lane s takes modes 4s .. 4s + 3 (two 16-byte loads, so a wave
+// reads 16 consecutive rows of phi), and the four partial sums are added in a
+// fixed order, (a0 + a1) + (a2 + a3); lanes s = 0, 1, 2 store coordinate s.
+constexpr int kUzLanes = 4;
 DEV void b_uz(const DevMesh& d, int bid) {
-  int v = bid * kBlock + threadIdx.x;
+  const int t = bid * kBlock + threadIdx.x;
+  const int v = t / kUzLanes, s = t % kUzLanes;
   if (stopped(d, v < d.n ? d.phi[(int64_t)kMaxK1 * v] : 0.0)) return;
-  if (v >= d.n) return;
   double a[3] = {0, 0, 0};
-  if (d.k1 > 0) {
-    const double* ph = d.phi + (int64_t)kMaxK1 * v;
+  if (v < d.n && d.k1 > 0) {
+    const double2* ph = reinterpret_cast<const double2*>(d.phi + (int64_t)kMaxK1 * v + 4 * s);
+    const double2 p0 = ph[0], p1 = ph[1];
+    const double p[4] = {p0.x, p0.y, p1.x, p1.y};
 #pragma unroll
-    for (int j = 0; j < kMaxK1; ++j) {
-      double p = ph[j];
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) a[c] += d.zbuf[c * kMaxK1 + j] * p;
-    }
+      for (int c = 0; c < 3; ++c) a[c] += d.zbuf[c * kMaxK1 + 4 * s + q] * p[q];
   }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) d.uz[3 * v + c] = a[c];
+  for (int off = 1; off < kUzLanes; off <<= 1)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a[c] += __shfl_xor(a[c], off);
+  if (v >= d.n || s >= 3) return;
+  d.uz[3 * v + s] = s == 0 ? a[0] : (s == 1 ? a[1] : a[2]);
 }
 __global__ void __launch_bounds__(kBlock) k_uz(DevMesh d) { b_uz(d, blockIdx.x); }
 
@@ -3472,6 +3480,7 @@ __global__ void __launch_bounds__(64) kb_gather_ctl(const DevMesh* __restrict__ 
 
 static inline int blocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 static inline int rhs_blocks(int64_t nf) { return blocks(nf * kRhsLanes); }
+static inline int uz_blocks(int64_t n) { return blocks(n * kUzLanes); }
 
 // Kernel instance for the mesh's precision and block structure.
 typedef void (*MeshKernel)(DevMesh);
@@ -3571,7 +3580,7 @@ void launch_precond(const DevMesh& d, const double* r, double* z, double* ypart,
                     hipStream_t st) {
   hipLaunchKernelGGL(pick_pc1(d), dim3(d.nb), dim3(kBlock), 0, st, d, r, ypart, rbar);
   hipLaunchKernelGGL(k_pc_solve, dim3(1), dim3(64), 0, st, d, ypart);
-  hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_uz, dim3(uz_blocks(d.n)), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(pick_pc2(d), dim3(d.nb), dim3(kBlock), 0, st, d, r, z, part, (const double*)rbar);
 }
 void launch_grad_field(const DevMesh& d, const double* x, double* V, hipStream_t st) {
@@ -3632,7 +3641,7 @@ void launch_iteration(const DevMesh& d, const SolvePlan& pl, hipStream_t st) {
   hipLaunchKernelGGL(pick_gram(d), dim3(d.nbg), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_gram_reduce, dim3((kGramEntries + 15) / 16), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_control_a, dim3(1), dim3(kCtlThreads), 0, st, d);
-  hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_uz, dim3(uz_blocks(d.n)), dim3(kBlock), 0, st, d);
   launch_bone_dir(d, st);
   hipLaunchKernelGGL(pick_direction(d), dim3(d.nb), dim3(kBlock), 0, st, d);
   launch_solve(d, pl, 0, d.dq, 1, st);
@@ -3653,7 +3662,7 @@ void launch_iteration_phased(const DevMesh& d, const SolvePlan& pl, hipStream_t 
   hipLaunchKernelGGL(pick_gram(d), dim3(d.nbg), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_gram_reduce, dim3((kGramEntries + 15) / 16), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_control_a, dim3(1), dim3(kCtlThreads), 0, st, d);
-  hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_uz, dim3(uz_blocks(d.n)), dim3(kBlock), 0, st, d);
   launch_bone_dir(d, st);
   hipLaunchKernelGGL(pick_direction(d), dim3(d.nb), dim3(kBlock), 0, st, d);
   (void)hipEventRecord(ev[2], st);
@@ -3675,7 +3684,7 @@ void launch_class(int k, const DevMesh& d, const SolvePlan& pl, hipStream_t st) 
     case 1: hipLaunchKernelGGL(pick_gram(d), dim3(d.nbg), dim3(kBlock), 0, st, d); break;
     case 2: hipLaunchKernelGGL(k_gram_reduce, dim3((kGramEntries + 15) / 16), dim3(kBlock), 0, st, d); break;
     case 3: hipLaunchKernelGGL(k_control_a, dim3(1), dim3(kCtlThreads), 0, st, d); break;
-    case 4: hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d); break;
+    case 4: hipLaunchKernelGGL(k_uz, dim3(uz_blocks(d.n)), dim3(kBlock), 0, st, d); break;
     case 5:
       launch_bone_dir(d, st);
       hipLaunchKernelGGL(pick_direction(d), dim3(d.nb), dim3(kBlock), 0, st, d);
@@ -3702,7 +3711,7 @@ void launch_evaluate(const DevMesh& d, hipStream_t st) {
   hipLaunchKernelGGL(pick_gram(d), dim3(d.nbg), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_gram_reduce, dim3((kGramEntries + 15) / 16), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_control_a, dim3(1), dim3(kCtlThreads), 0, st, d);
-  hipLaunchKernelGGL(k_uz, dim3(blocks(d.n)), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(k_uz, dim3(uz_blocks(d.n)), dim3(kBlock), 0, st, d);
   launch_bone_dir(d, st);
   hipLaunchKernelGGL(pick_direction(d), dim3(d.nb), dim3(kBlock), 0, st, d);
 }
@@ -3750,7 +3759,7 @@ void batch_layout(const std::vector<const DevMesh*>& ms, const std::vector<const
   add(b.gram, [&](int j) { return ms[j]->nbg; });
   add(b.gram_reduce, [&](int) { return (kGramEntries + 15) / 16; });
   add(b.one, [&](int) { return 1; });
-  add(b.uz, [&](int j) { return blocks(ms[j]->n); });
+  add(b.uz, [&](int j) { return uz_blocks(ms[j]->n); });
   add(b.rhs, [&](int j) { return rhs_blocks(ms[j]->nf); });
   add(b.add_q, [&](int j) { return blocks(3 * (int64_t)ms[j]->nf); });
   int nl = 0;
