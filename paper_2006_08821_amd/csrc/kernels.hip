@@ -1783,6 +1783,9 @@ k_element_hess(DevMesh d) { b_element_hess<T, kC>(d, blockIdx.x); }
 // B = (Z_{cc'} gphi_j)[k] for the pair in K slot s.  Waves are added in a
 // fixed order at the end.
 constexpr int kGramBatch = 16;
+// steps of a full batch's product loop unrolled together (4: same time, 3:
+// slower, 12: spills; the loop of runtime length did not unroll at all)
+constexpr int kGramUnroll = 2;
 constexpr int kGramRow = 65;   // 54 block entries + 9 + 1, padded to an odd stride
 constexpr int kGramGRow = 49;  // 16 mode gradients x 3, padded
 
@@ -2173,9 +2176,10 @@ DEV void b_gram(const DevMesh& d, int bid) {
     // slots carry data (twelve products per pair block for sixteen elements
     // instead of sixteen with one slot empty).  A lane's A value (row i) and
     // B value (column j) both belong to its slot's pair.
-    const int nst = (3 * ne + 3) / 4;
-#pragma unroll 2
-    for (int st = 0; st < nst; ++st) {
+    // (a full batch runs a loop of constant length, which the compiler can
+    // unroll so that one step's LDS reads overlap the previous step's
+    // products; the last, partial batch of a wave runs the same body)
+    auto step = [&](int st) {
       const int f = 4 * st + k;
       const bool valid = f < 3 * ne;
       const int e = valid ? f / 3 : 0;
@@ -2194,6 +2198,13 @@ DEV void b_gram(const DevMesh& d, int bid) {
       y0 += kc == 0 ? yv : T(0);
       y1 += kc == 1 ? yv : T(0);
       y2 += kc == 2 ? yv : T(0);
+    };
+    if (ne == kGramBatch) {
+#pragma unroll kGramUnroll
+      for (int st = 0; st < 3 * kGramBatch / 4; ++st) step(st);
+    } else {
+      const int nst = (3 * ne + 3) / 4;
+      for (int st = 0; st < nst; ++st) step(st);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -111,21 +111,27 @@ def test_box_beam_solve_matches_oracle(torch):
 def test_tiny_meshes_match_oracle(torch, kind):
     # the degenerate end: one tet with a single free vertex (no modes, k = 0),
     # two tets (one mode triple), one and two cubes, a 2x2x4 grid; each is a
-    # single supernode.  Converged to |g| <= 1e-11 against the oracle's EMU
-    # iteration (same modes) and its Moreau-envelope minimizer (O2), which
-    # agree with each other to about 1e-8 at this tolerance.
+    # single supernode.  The oracle's EMU iteration (same modes) takes the
+    # same number of steps to |g| <= 1e-8 (near 1e-11 the slow tail makes the
+    # count depend on rounding: the oracle alone varies by several steps
+    # between machines there).  Converged to |g| <= 1e-11, the positions match
+    # the oracle's EMU result and its Moreau-envelope minimizer (O2), which
+    # agree with each other to about 1e-8 at that tolerance.
     p = wl.tiny(kind, activation=0.4)
     M = omesh.build(p)
     mesh = _mesh(p)
     if M.nu is not None:
         _share_modes(mesh, M)
     assert mesh.info()["n_modes"] == (0 if M.nu is None else 3 * len(M.nu))
-    q, st = mesh.solve(grad_tol=1e-11, max_iters=5000)
+    _, st8 = mesh.solve(grad_tol=1e-8, max_iters=5000)
+    o8 = oemu.solve(M, p.activation, tol=1e-8, max_iters=5000, hessian="split", trials="affine")
+    assert st8["status"] == 0 and o8["stats"]["converged"]
+    assert abs(st8["iters"] - o8["stats"]["iters"]) <= 2, (st8["iters"], o8["stats"]["iters"])
+    q, st = mesh.solve(grad_tol=1e-11, max_iters=5000)  # on from the 1e-8 state
     assert st["status"] == 0 and st["grad_norm"] <= 1e-11, st
     qg = q.cpu().numpy()
     o1 = oemu.solve(M, p.activation, tol=1e-11, max_iters=5000, hessian="split", trials="affine")
     assert o1["stats"]["converged"]
-    assert abs(st["iters"] - o1["stats"]["iters"]) <= 3, (st["iters"], o1["stats"]["iters"])
     assert _disp_err(qg, o1["q"], M.rest) <= 1e-7
     o2 = ofem.moreau_solve(M, p.activation, tol=1e-12)
     assert _disp_err(qg, o2["q"], M.rest) <= 1e-6
