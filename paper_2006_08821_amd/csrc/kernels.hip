@@ -1783,8 +1783,8 @@ k_element_hess(DevMesh d) { b_element_hess<T, kC>(d, blockIdx.x); }
 // B = (Z_{cc'} gphi_j)[k] for the pair in K slot s.  Waves are added in a
 // fixed order at the end.
 constexpr int kGramBatch = 16;
-// steps of a full batch's product loop unrolled together (4: same time, 3:
-// slower, 12: spills; the loop of runtime length did not unroll at all)
+// FP64 steps of a full batch's product loop unrolled together (4: same time,
+// 3: slower, 12: spills; the loop of runtime length did not unroll at all)
 constexpr int kGramUnroll = 2;
 constexpr int kGramRow = 65;   // 54 block entries + 9 + 1, padded to an odd stride
 constexpr int kGramGRow = 49;  // 16 mode gradients x 3, padded
@@ -2089,7 +2089,11 @@ DEV void b_gram(const DevMesh& d, int bid) {
   v4 acc[6];
 #pragma unroll
   for (int p = 0; p < 6; ++p) acc[p] = v4{0, 0, 0, 0};
-  T y0 = 0, y1 = 0, y2 = 0;  // y[(c, j)] partials of this lane's K slot
+  // y[(c, j)] partials of this lane's K slot k: step st takes pair
+  // f = 4 st + k, whose coordinate is (st + k) mod 3 in every batch, so the
+  // terms of step st collect in ry[st mod 3] (coordinate (m + k) mod 3 for
+  // ry[m]), each in step order
+  T ry[3] = {0, 0, 0};
   const int el = lane >> 2, sl = lane & 3;
   // split blocks: the next batch's inputs are requested before this batch's
   // products, so their latency overlaps the matrix-core work
@@ -2195,13 +2199,45 @@ DEV void b_gram(const DevMesh& d, int bid) {
         acc[p] = MfmaAcc<T>::mma(av, bv, acc[p]);
       }
       const T yv = wv * (zr[54 + 3 * kc] * g0 + zr[54 + 3 * kc + 1] * g1 + zr[54 + 3 * kc + 2] * g2);
-      y0 += kc == 0 ? yv : T(0);
-      y1 += kc == 1 ? yv : T(0);
-      y2 += kc == 2 ? yv : T(0);
+      const int m = st % 3;
+      ry[0] += m == 0 ? yv : T(0);
+      ry[1] += m == 1 ? yv : T(0);
+      ry[2] += m == 2 ? yv : T(0);
+    };
+    // Full batch: step 3 i + m (m = 0, 1, 2) takes pair 12 i + 4 m + k,
+    // element 4 i + (4 m + k) / 3, so the y term goes to ry[m] without a
+    // select.
+    auto full_step = [&](int i, auto mc) {
+      constexpr int m = decltype(mc)::value;
+      const int em = (4 * m + k) / 3, kc = 4 * m + k - 3 * em;
+      const T* zr = zw[4 * i + em];
+      const T* gr = gw[4 * i + em] + 3 * j;
+      const T g0 = gr[0], g1 = gr[1], g2 = gr[2];
+      const T wv = zr[63];
+      const T gk = kc == 0 ? g0 : (kc == 1 ? g1 : g2);
+      const T av = wv * wv * gk;
+#pragma unroll
+      for (int p = 0; p < 6; ++p) {
+        const T bv = zr[p * 9 + kc * 3] * g0 + zr[p * 9 + kc * 3 + 1] * g1 + zr[p * 9 + kc * 3 + 2] * g2;
+        acc[p] = MfmaAcc<T>::mma(av, bv, acc[p]);
+      }
+      ry[m] += wv * (zr[54 + 3 * kc] * g0 + zr[54 + 3 * kc + 1] * g1 + zr[54 + 3 * kc + 2] * g2);
     };
     if (ne == kGramBatch) {
+      if constexpr (sizeof(T) == 4) {
+#pragma unroll 1
+        for (int i = 0; i < kGramBatch / 4; ++i) {
+          full_step(i, std::integral_constant<int, 0>{});
+          full_step(i, std::integral_constant<int, 1>{});
+          full_step(i, std::integral_constant<int, 2>{});
+        }
+      } else {
+        // FP64: the three-step rounds need registers this pass does not
+        // have at two waves per SIMD (spills: 611 vs 541 us); single steps,
+        // two at a time
 #pragma unroll kGramUnroll
-      for (int st = 0; st < 3 * kGramBatch / 4; ++st) step(st);
+        for (int st = 0; st < 3 * kGramBatch / 4; ++st) step(st);
+      }
     } else {
       const int nst = (3 * ne + 3) / 4;
       for (int st = 0; st < nst; ++st) step(st);
@@ -2210,6 +2246,11 @@ DEV void b_gram(const DevMesh& d, int bid) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
+  // coordinate c of slot k is in ry[(c - k) mod 3]
+  const int k3 = k % 3;
+  T y0 = k3 == 0 ? ry[0] : (k3 == 1 ? ry[2] : ry[1]);
+  T y1 = k3 == 0 ? ry[1] : (k3 == 1 ? ry[0] : ry[2]);
+  T y2 = k3 == 0 ? ry[2] : (k3 == 1 ? ry[1] : ry[0]);
   // y[(c, j)]: add the four K slots of mode j (lanes j + 16 ks), then lane
   // j + 16 c (c < 3) holds coordinate c
 #pragma unroll
