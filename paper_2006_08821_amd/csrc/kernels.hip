@@ -1668,8 +1668,17 @@ DEV void hess_blocks(const DevMesh& d, int i, T (&Hs)[6][6], T (&Hk)[3][3], bool
 // added and the results inverted; gbar = H^{-1} g in place.  The elements of
 // a workgroup are taken in rounds of kBlock; a 6x6 block that is not positive
 // definite (rare) is parked, lower triangle, in its inverse's place and
-// finished by thread 0 after the round with an LDS-resident Jacobi, so that
-// the eigen-decomposition holds no registers in the main loop.
+// finished after the round by lane 0 of its wave with an LDS-resident Jacobi,
+// so that the eigen-decomposition holds no registers in the main loop.  The
+// fix lists are per wave, so the rounds need no workgroup barrier and a
+// wave's next loads are not held up by the other waves' arithmetic.
+// Between the waves' own steps: their stores (the parked blocks in Lf)
+// visible to lane 0, whose loads come after.
+DEV void wave_sync_mem() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 template <typename T, bool kC = false>
 DEV void b_element_hess(const DevMesh& d, int bid) {
   const int lb = xcd_block(bid, d.nb);
@@ -1677,17 +1686,23 @@ DEV void b_element_hess(const DevMesh& d, int bid) {
     const int i0 = lb * kBlock + threadIdx.x;
     if (stopped(d, i0 < d.m ? d.vol[i0] : 0.0)) return;
   }
+  constexpr int kW = kBlock / 64;
   __shared__ int shc[kBlock];
-  __shared__ int fix[kBlock];
-  __shared__ int nfix;
-  __shared__ T fixW[6][6], fixV[6][6];
+  __shared__ int fixl[kW][64];
+  __shared__ int nfixw[kW];
+  __shared__ T fixWw[kW][6][6], fixVw[kW][6][6];
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
+  int* fix = fixl[wave];
+  int& nfix = nfixw[wave];
+  T(&fixW)[6][6] = fixWw[wave];
+  T(&fixV)[6][6] = fixVw[wave];
   int nclamp = 0;
   const int m = d.m;
   T* gbar = (T*)d.gbar;
   T* Lf = (T*)d.Lf;
   for (int base = lb * kBlock; base < m; base += d.nb * kBlock) {
-    if (threadIdx.x == 0) nfix = 0;
-    __syncthreads();
+    if (lane == 0) nfix = 0;
+    wave_sync_mem();
     const int i = base + threadIdx.x;
     const bool own = i < m && !(d.nbones && d.bone_pos[i] >= 0);  // bone tets: k_bone_blocks
     if (own) {
@@ -1730,8 +1745,8 @@ DEV void b_element_hess(const DevMesh& d, int bid) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) gbar[k * m + i] = T(0);
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
+    wave_sync_mem();
+    if (lane == 0) {
       for (int q = 0; q < nfix; ++q) {
         const int j = fix[q];
 #pragma unroll 1
@@ -1754,11 +1769,11 @@ DEV void b_element_hess(const DevMesh& d, int bid) {
       }
     }
     if constexpr (kC) {
-      __syncthreads();
+      wave_sync_mem();
       if (own) coupled_finish<T>(d, i);
     }
     // nfix and fix are reused by the next round
-    __syncthreads();
+    wave_sync_mem();
   }
   const int nclamp_sum = block_sum_int(nclamp, shc);
   if (threadIdx.x == 0) d.part_cnt[2 * bid] = nclamp_sum;
@@ -3499,8 +3514,14 @@ __global__ void __launch_bounds__(kBlock) k_scale_free(DevMesh d, const double* 
   }
 EMU_BATCHED(kb_element64, kBlock, b_element<double>(d, e.y))
 EMU_BATCHED(kb_element32, kBlock, b_element<float>(d, e.y))
-EMU_BATCHED(kb_element_hess64, kBlock, b_element_hess<double>(d, e.y))
-EMU_BATCHED(kb_element_hess32, kBlock, b_element_hess<float>(d, e.y))
+// the Hessian pass with the occupancy bounds of k_element_hess
+template <typename T>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8)))
+kb_element_hess(const DevMesh* __restrict__ ms, const int2* __restrict__ map) {
+  const int2 e = map[blockIdx.x];
+  const DevMesh d = ms[e.x];
+  b_element_hess<T>(d, e.y);
+}
 // the Gram pass with the occupancy bounds of k_gram
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
@@ -3776,7 +3797,7 @@ static inline void launch_map(void (*k)(const DevMesh*, const int2*), const Batc
 void launch_batch_iteration(const BatchPlan& b, hipStream_t st) {
   if (b.n_meshes == 0) return;
   launch_map(b.mixed ? kb_element32 : kb_element64, b, b.element, kBlock, st);
-  launch_map(b.mixed ? kb_element_hess32 : kb_element_hess64, b, b.element, kBlock, st);
+  launch_map(b.mixed ? kb_element_hess<float> : kb_element_hess<double>, b, b.element, kBlock, st);
   launch_map(b.mixed ? kb_gram<float> : kb_gram<double>, b, b.gram, kBlock, st);
   launch_map(kb_gram_reduce, b, b.gram_reduce, kBlock, st);
   launch_map(kb_control_a, b, b.one, kCtlThreads, st);
