@@ -648,10 +648,26 @@ DEV void clamp_psd_jacobi_lds(T (*W)[N], T (*V)[N]) {
     }
 }
 
-DEV double acs(double x) { return acos(x); }
-DEV float acs(float x) { return acosf(x); }
-DEV double cs(double x) { return cos(x); }
-DEV float cs(float x) { return cosf(x); }
+// cos(acos(r) / 3) for r in [-1, 1]: the root c in [1/2, 1] of
+// 4 c^3 - 3 c = r (cos 3t = 4 cos^3 t - 3 cos t).  With c = 1/2 + u this is
+// 6 u^2 + 4 u^3 = 1 + r, a simple root u >= 0 for every r > -1 (at r = -1
+// the cubic in c has a double root, so Newton on c would stall there).
+// Double precision: a single-precision start (u ~ sqrt((1 + r) / 6) when
+// 1 + r is small), then three Newton steps; as accurate as acos and cos in
+// double (checked against a symmetric eigensolver on random and nearly
+// degenerate 3x3 matrices), without their cost.
+DEV float cos_third_acos(float r) { return cosf(acosf(r) * (1.0f / 3.0f)); }
+DEV double cos_third_acos(double r) {
+  const double t = 1.0 + r;
+  double u = (double)cosf(acosf((float)r) * (1.0f / 3.0f)) - 0.5;
+  if (t < 1e-2) u = sqrt(t * (1.0 / 6.0));
+#pragma unroll
+  for (int it = 0; it < 3; ++it) {
+    const double dg = 12.0 * u * (1.0 + u);
+    if (dg > 0.0) u -= ((6.0 + 4.0 * u) * u * u - t) / dg;
+  }
+  return 0.5 + u;
+}
 
 // Unit eigenvector of the symmetric 3x3 A for its simple eigenvalue lam: the
 // longest of the cross products of two rows of A - lam I, normalized.
@@ -707,9 +723,11 @@ DEV bool clamp_psd3_closed(T (&A)[3][3]) {
   const T c00 = b00 * ip, c11 = b11 * ip, c22 = b22 * ip, c01 = a01 * ip, c02 = a02 * ip, c12 = a12 * ip;
   T r = T(0.5) * (c00 * (c11 * c22 - c12 * c12) - c01 * (c01 * c22 - c12 * c02) + c02 * (c01 * c12 - c11 * c02));
   r = r < T(-1) ? T(-1) : (r > T(1) ? T(1) : r);
-  const T phi = acs(r) * T(1.0 / 3.0);
-  const T e1 = q + T(2) * p * cs(phi);
-  const T e3 = q + T(2) * p * cs(phi + T(2.0943951023931954923));  // + 2 pi / 3
+  // eigenvalues q + 2 p cos(phi + 2 pi k / 3), phi = acos(r) / 3
+  const T c = cos_third_acos(r);
+  const T sn = sqrt(c < T(1) ? T(1) - c * c : T(0));  // sin(phi), phi in [0, pi/3]
+  const T e1 = q + T(2) * p * c;
+  const T e3 = q - p * (c + T(1.7320508075688772935) * sn);  // 2 p cos(phi + 2 pi / 3)
   const T e2 = T(3) * q - e1 - e3;
   const T scale = fabs(e1) > fabs(e3) ? fabs(e1) : fabs(e3);
   if (!(e1 > T(0))) {
