@@ -441,8 +441,9 @@ DEV T hproj(int y, int z, const T* S, T mu, T kappa, T phi, const T* u) {
 }
 
 // Packed lower Cholesky of a full N x N matrix; false if not positive definite.
+// rdiag (optional) receives the reciprocals of the diagonal.
 template <typename T, int N>
-DEV bool chol_packed(const T (&A)[N][N], T* L) {
+DEV bool chol_packed(const T (&A)[N][N], T* L, T* rdiag = nullptr) {
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     T s = A[j][j];
@@ -451,6 +452,7 @@ DEV bool chol_packed(const T (&A)[N][N], T* L) {
     if (!(s > T(0))) return false;
     const T rd = rsq(s);  // 1 / sqrt(s) without a division
     L[j * (j + 1) / 2 + j] = s * rd;
+    if (rdiag) rdiag[j] = rd;
 #pragma unroll
     for (int i = j + 1; i < N; ++i) {
       T t = A[i][j];
@@ -509,12 +511,13 @@ DEV void chol_inverse(const T* L, T* P) {
 }
 // The same inverse stored straight to memory (out[(packed index) * m + i]) with
 // x <- P x on the way, holding only L^{-1} in registers: x = L^{-T} (L^{-1} x),
-// and every entry of P is stored as soon as it is formed.
+// and every entry of P is stored as soon as it is formed.  rdiag: the
+// reciprocals of L's diagonal from the factorization.
 template <typename T, int N>
-DEV void chol_inverse_apply_store(const T* L, T* x, T* out, int m, int i) {
+DEV void chol_inverse_apply_store(const T* L, const T* rdiag, T* x, T* out, int m, int i) {
   T Li[N * (N + 1) / 2];
 #pragma unroll
-  for (int c = 0; c < N; ++c) Li[c * (c + 1) / 2 + c] = T(1) / L[c * (c + 1) / 2 + c];
+  for (int c = 0; c < N; ++c) Li[c * (c + 1) / 2 + c] = rdiag[c];
 #pragma unroll
   for (int c = 0; c < N; ++c) {
 #pragma unroll
@@ -762,22 +765,22 @@ DEV bool clamp_psd3_closed(T (&A)[3][3]) {
 // the clamp changed A.  3x3 blocks take the closed form where it is accurate.
 // L = chol(A + beta I) for a positive semi-definite A (A is modified).
 template <typename T, int N>
-DEV void add_factor(T (&A)[N][N], T beta, T* L) {
+DEV void add_factor(T (&A)[N][N], T beta, T* L, T* rdiag = nullptr) {
 #pragma unroll
   for (int k = 0; k < N; ++k) A[k][k] += beta;
-  if (!chol_packed<T, N>(A, L)) {
+  if (!chol_packed<T, N>(A, L, rdiag)) {
     // beta > 0 makes this positive definite; guard against beta == 0 with a tiny shift
     T sc = 0;
 #pragma unroll
     for (int k = 0; k < N; ++k) sc = A[k][k] > sc ? A[k][k] : sc;
 #pragma unroll
     for (int k = 0; k < N; ++k) A[k][k] += T(1e-12) * sc + T(1e-300);
-    chol_packed<T, N>(A, L);
+    chol_packed<T, N>(A, L, rdiag);
   }
 }
 
 template <typename T, int N>
-DEV int clamp_add_factor(T (&A)[N][N], T beta, T* L) {
+DEV int clamp_add_factor(T (&A)[N][N], T beta, T* L, T* rdiag = nullptr) {
   int clamped = 0;
   if (!chol_packed<T, N>(A, L)) {
     if constexpr (N == 3) {
@@ -787,7 +790,7 @@ DEV int clamp_add_factor(T (&A)[N][N], T beta, T* L) {
     }
     clamped = 1;
   }
-  add_factor<T, N>(A, beta, L);
+  add_factor<T, N>(A, beta, L, rdiag);
   return clamped;
 }
 
@@ -1730,11 +1733,12 @@ DEV void b_element_hess(const DevMesh& d, int bid) {
       {
         T Ls[21];
         if (chol_packed<T, 6>(Hs, Ls)) {
-          add_factor<T, 6>(Hs, beta, Ls);
+          T rds[6];
+          add_factor<T, 6>(Hs, beta, Ls, rds);
           T gs[6];
 #pragma unroll
           for (int k = 0; k < 6; ++k) gs[k] = gbar[k * m + i];
-          chol_inverse_apply_store<T, 6>(Ls, gs, Lf, m, i);
+          chol_inverse_apply_store<T, 6>(Ls, rds, gs, Lf, m, i);
 #pragma unroll
           for (int k = 0; k < 6; ++k) gbar[k * m + i] = gs[k];
         } else {
@@ -1745,12 +1749,12 @@ DEV void b_element_hess(const DevMesh& d, int bid) {
           fix[atomicAdd(&nfix, 1)] = i;
         }
       }
-      T Lk[6];
-      nclamp += clamp_add_factor<T, 3>(Hk, beta, Lk);
+      T Lk[6], rdk[3];
+      nclamp += clamp_add_factor<T, 3>(Hk, beta, Lk, rdk);
       T gk[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) gk[k] = gbar[(6 + k) * m + i];
-      chol_inverse_apply_store<T, 3>(Lk, gk, Lf + (int64_t)21 * m, m, i);
+      chol_inverse_apply_store<T, 3>(Lk, rdk, gk, Lf + (int64_t)21 * m, m, i);
 #pragma unroll
       for (int k = 0; k < 3; ++k) gbar[(6 + k) * m + i] = gk[k];
     } else if (i < m) {
