@@ -1541,6 +1541,68 @@ DEV void accept_elem(const DevMesh& d, int i, double sigma, const double* zc, do
 }
 
 // --------------------------------------------------------------- element pass
+// The element pass at element i: the accept of the pending step (sigma > 0),
+// then at the new state the energy term (added to acc[0]), inverted-tet
+// count, and the exact gradient in y coordinates gy with its squared norm gn.
+// S is the stretch after the accept.
+DEV void element_core(const DevMesh& d, int i, double sigma, Elem& e, double (&S)[9], double (&gy)[9], double& gn,
+                      DD (&acc)[2], int& ninv) {
+  load_elem(d, i, e);
+  double R[9];
+  load_R(d, i, R);
+  load_S(d, i, S);
+  if (sigma != 0.0) accept_elem<false>(d, i, sigma, nullptr, R, S);
+  double A[9], At[9];
+  gather_grad(d.q, e, A);
+  matTmul3(R, A, At);
+  const double beta = d.alpha * e.w;
+  const double J = det3(S);
+  double C[9];
+  cof3<double>(S, C);
+  double Su[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) Su[c] = S[3 * c] * e.u[0] + S[3 * c + 1] * e.u[1] + S[3 * c + 2] * e.u[2];
+  double trSS = 0, dres = 0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    trSS += S[k] * S[k];
+    dres += (At[k] - S[k]) * (At[k] - S[k]);
+  }
+  const double afk = e.a * d.kf;
+  const double psi = 0.5 * e.mu * (trSS - 3.0) - e.mu * (J - 1.0) + 0.5 * e.lhat * (J - 1.0) * (J - 1.0) +
+                     afk * (Su[0] * Su[0] + Su[1] * Su[1] + Su[2] * Su[2]);
+  // external work (Sec. 3.4): f . q*(F) = sum_i nu_i . F_i + const with
+  // nu_i = w_i G_i L_ff^{-1} f; in the rotated frame nu_rot = R^T nu
+  double nur[9];
+  if (d.has_ext) {
+    double nu[9];
+    gather_grad(d.vext, e, nu);
+    matTmul3(R, nu, nur);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) nur[k] *= e.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) nur[k] = 0.0;
+  }
+  double wext = 0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) wext += nur[k] * S[k];
+  acc[0] = dd_add_d(acc[0], e.vol * psi + 0.5 * beta * dres - wext);
+  ninv += (J <= 0.0);
+  const double kap = e.lhat * (J - 1.0) - e.mu;
+  double G[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      G[3 * a + b] = e.vol * (e.mu * S[3 * a + b] + kap * C[3 * a + b] + 2.0 * afk * Su[a] * e.u[b]) +
+                     beta * (S[3 * a + b] - At[3 * a + b]) - nur[3 * a + b];
+  gn = 0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) gn += G[k] * G[k];
+  to_y<double, double>(G, gy);
+}
+
 // Accept the previous step (if sigma > 0): X = S + sigma D(p), R <- R polar(X),
 // S <- sym(polar(X)^T X).  Then at the new state: energy, exact gradient
 // G = vol P(F) + beta (F - A) (eq. gradient), the two clamped Hessian blocks
@@ -1560,61 +1622,8 @@ DEV void b_element(const DevMesh& d, int bid) {
   const int m = d.m;
   for (int i = xcd_block(bid, d.nb) * kBlock + threadIdx.x; i < m; i += d.nb * kBlock) {
     Elem e;
-    load_elem(d, i, e);
-    double R[9], S[9];
-    load_R(d, i, R);
-    load_S(d, i, S);
-    if (sigma != 0.0) accept_elem<false>(d, i, sigma, nullptr, R, S);
-    double A[9], At[9];
-    gather_grad(d.q, e, A);
-    matTmul3(R, A, At);
-    const double beta = d.alpha * e.w;
-    const double J = det3(S);
-    double C[9];
-    cof3<double>(S, C);
-    double Su[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) Su[c] = S[3 * c] * e.u[0] + S[3 * c + 1] * e.u[1] + S[3 * c + 2] * e.u[2];
-    double trSS = 0, dres = 0;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      trSS += S[k] * S[k];
-      dres += (At[k] - S[k]) * (At[k] - S[k]);
-    }
-    const double afk = e.a * d.kf;
-    const double psi = 0.5 * e.mu * (trSS - 3.0) - e.mu * (J - 1.0) + 0.5 * e.lhat * (J - 1.0) * (J - 1.0) +
-                       afk * (Su[0] * Su[0] + Su[1] * Su[1] + Su[2] * Su[2]);
-    // external work (Sec. 3.4): f . q*(F) = sum_i nu_i . F_i + const with
-    // nu_i = w_i G_i L_ff^{-1} f; in the rotated frame nu_rot = R^T nu
-    double nur[9];
-    if (d.has_ext) {
-      double nu[9];
-      gather_grad(d.vext, e, nu);
-      matTmul3(R, nu, nur);
-#pragma unroll
-      for (int k = 0; k < 9; ++k) nur[k] *= e.w;
-    } else {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) nur[k] = 0.0;
-    }
-    double wext = 0;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) wext += nur[k] * S[k];
-    acc[0] = dd_add_d(acc[0], e.vol * psi + 0.5 * beta * dres - wext);
-    ninv += (J <= 0.0);
-    const double kap = e.lhat * (J - 1.0) - e.mu;
-    double G[9];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b)
-        G[3 * a + b] = e.vol * (e.mu * S[3 * a + b] + kap * C[3 * a + b] + 2.0 * afk * Su[a] * e.u[b]) +
-                       beta * (S[3 * a + b] - At[3 * a + b]) - nur[3 * a + b];
-    double gn = 0;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) gn += G[k] * G[k];
-    double gy[9];
-    to_y<double, double>(G, gy);
+    double S[9], gy[9], gn;
+    element_core(d, i, sigma, e, S, gy, gn, acc, ninv);
     const int bpos = d.nbones ? d.bone_pos[i] : -1;
     if (bpos < 0) {
       acc[1] = dd_add_d(acc[1], gn);
@@ -1685,6 +1694,92 @@ DEV void hess_blocks(const DevMesh& d, int i, T (&Hs)[6][6], T (&Hk)[3][3], bool
   hess_blocks_s<T>(S, vol * d.mu[i], vol * d.lhat[i], vol * afk, u, Hs, Hk);
 }
 
+// The two blocks of element i clamped to their positive semi-definite part,
+// beta I added, factored and inverted into Lf, with gbar = H^{-1} g.  g: the
+// gradient in y coordinates (precision T), or null to read it from gbar.  A
+// 6x6 block that is not positive definite (rare) is parked, lower triangle,
+// in its inverse's place with its part of g in gbar, and listed in fix for
+// lane 0 of the wave.
+template <typename T>
+DEV void hess_finish(const DevMesh& d, int i, T (&Hs)[6][6], T (&Hk)[3][3], T beta, const T* g, int* fix, int& nfix,
+                     int& nclamp) {
+  const int m = d.m;
+  T* gbar = (T*)d.gbar;
+  T* Lf = (T*)d.Lf;
+  {
+    T Ls[21];
+    if (chol_packed<T, 6>(Hs, Ls)) {
+      T rds[6];
+      add_factor<T, 6>(Hs, beta, Ls, rds);
+      T gs[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) gs[k] = g ? g[k] : gbar[k * m + i];
+      chol_inverse_apply_store<T, 6>(Ls, rds, gs, Lf, m, i);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) gbar[k * m + i] = gs[k];
+    } else {
+#pragma unroll
+      for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int c = 0; c <= r; ++c) Lf[(r * (r + 1) / 2 + c) * m + i] = Hs[r][c];
+      if (g)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) gbar[k * m + i] = g[k];
+      fix[atomicAdd(&nfix, 1)] = i;
+    }
+  }
+  T Lk[6], rdk[3];
+  nclamp += clamp_add_factor<T, 3>(Hk, beta, Lk, rdk);
+  T gk[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gk[k] = g ? g[6 + k] : gbar[(6 + k) * m + i];
+  chol_inverse_apply_store<T, 3>(Lk, rdk, gk, Lf + (int64_t)21 * m, m, i);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) gbar[(6 + k) * m + i] = gk[k];
+}
+// An affine bone tet: identity blocks and gbar = 0, so that the Gram pass
+// (which gives it weight 0) reads finite values; k_bone_blocks then stores
+// the bone's own block at its first tet.
+template <typename T>
+DEV void hess_bone_tet(const DevMesh& d, int i) {
+  const int m = d.m;
+  T* gbar = (T*)d.gbar;
+  T* Lf = (T*)d.Lf;
+#pragma unroll
+  for (int k = 0; k < 27; ++k) Lf[k * m + i] = (k < 21 ? (k == 0 || k == 2 || k == 5 || k == 9 || k == 14 || k == 20)
+                                                        : (k == 21 || k == 23 || k == 26)) ? T(1) : T(0);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) gbar[k * m + i] = T(0);
+}
+// Lane 0 of a wave finishes its wave's indefinite 6x6 blocks: the Jacobi
+// clamp in LDS, beta I, the inverse, and gbar = H^{-1} g.
+template <typename T>
+DEV void hess_fix_list(const DevMesh& d, const int* fix, int nfix, T (&fixW)[6][6], T (&fixV)[6][6], int& nclamp) {
+  const int m = d.m;
+  T* gbar = (T*)d.gbar;
+  T* Lf = (T*)d.Lf;
+  for (int q = 0; q < nfix; ++q) {
+    const int j = fix[q];
+#pragma unroll 1
+    for (int r = 0; r < 6; ++r)
+#pragma unroll 1
+      for (int c = 0; c <= r; ++c) fixW[r][c] = fixW[c][r] = Lf[(r * (r + 1) / 2 + c) * m + j];
+    clamp_psd_jacobi_lds<T, 6>(fixW, fixV);
+    T Ls[21], Ps[21];
+    add_factor<T, 6>(fixW, (T)(d.alpha * d.w[j]), Ls);
+    chol_inverse<T, 6>(Ls, Ps);
+    T gs[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) gs[k] = gbar[k * m + j];
+    sym_apply<T, 6>(Ps, gs);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) gbar[k * m + j] = gs[k];
+#pragma unroll
+    for (int k = 0; k < 21; ++k) Lf[k * m + j] = Ps[k];
+    ++nclamp;
+  }
+}
+
 // Both blocks are clamped to their positive semi-definite part, beta I is
 // added and the results inverted; gbar = H^{-1} g in place.  The elements of
 // a workgroup are taken in rounds of kBlock; a 6x6 block that is not positive
@@ -1719,8 +1814,6 @@ DEV void b_element_hess(const DevMesh& d, int bid) {
   T(&fixV)[6][6] = fixVw[wave];
   int nclamp = 0;
   const int m = d.m;
-  T* gbar = (T*)d.gbar;
-  T* Lf = (T*)d.Lf;
   for (int base = lb * kBlock; base < m; base += d.nb * kBlock) {
     if (lane == 0) nfix = 0;
     wave_sync_mem();
@@ -1729,67 +1822,12 @@ DEV void b_element_hess(const DevMesh& d, int bid) {
     if (own) {
       T Hs[6][6], Hk[3][3];
       hess_blocks<T>(d, i, Hs, Hk, !kC);
-      const T beta = (T)(d.alpha * d.w[i]);
-      {
-        T Ls[21];
-        if (chol_packed<T, 6>(Hs, Ls)) {
-          T rds[6];
-          add_factor<T, 6>(Hs, beta, Ls, rds);
-          T gs[6];
-#pragma unroll
-          for (int k = 0; k < 6; ++k) gs[k] = gbar[k * m + i];
-          chol_inverse_apply_store<T, 6>(Ls, rds, gs, Lf, m, i);
-#pragma unroll
-          for (int k = 0; k < 6; ++k) gbar[k * m + i] = gs[k];
-        } else {
-#pragma unroll
-          for (int r = 0; r < 6; ++r)
-#pragma unroll
-            for (int c = 0; c <= r; ++c) Lf[(r * (r + 1) / 2 + c) * m + i] = Hs[r][c];
-          fix[atomicAdd(&nfix, 1)] = i;
-        }
-      }
-      T Lk[6], rdk[3];
-      nclamp += clamp_add_factor<T, 3>(Hk, beta, Lk, rdk);
-      T gk[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) gk[k] = gbar[(6 + k) * m + i];
-      chol_inverse_apply_store<T, 3>(Lk, rdk, gk, Lf + (int64_t)21 * m, m, i);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) gbar[(6 + k) * m + i] = gk[k];
+      hess_finish<T>(d, i, Hs, Hk, (T)(d.alpha * d.w[i]), nullptr, fix, nfix, nclamp);
     } else if (i < m) {
-      // an affine bone tet: identity blocks and gbar = 0, so that the Gram
-      // pass (which gives it weight 0) reads finite values; k_bone_blocks
-      // then stores the bone's own block at its first tet
-#pragma unroll
-      for (int k = 0; k < 27; ++k) Lf[k * m + i] = (k < 21 ? (k == 0 || k == 2 || k == 5 || k == 9 || k == 14 || k == 20)
-                                                            : (k == 21 || k == 23 || k == 26)) ? T(1) : T(0);
-#pragma unroll
-      for (int k = 0; k < 9; ++k) gbar[k * m + i] = T(0);
+      hess_bone_tet<T>(d, i);
     }
     wave_sync_mem();
-    if (lane == 0) {
-      for (int q = 0; q < nfix; ++q) {
-        const int j = fix[q];
-#pragma unroll 1
-        for (int r = 0; r < 6; ++r)
-#pragma unroll 1
-          for (int c = 0; c <= r; ++c) fixW[r][c] = fixW[c][r] = Lf[(r * (r + 1) / 2 + c) * m + j];
-        clamp_psd_jacobi_lds<T, 6>(fixW, fixV);
-        T Ls[21], Ps[21];
-        add_factor<T, 6>(fixW, (T)(d.alpha * d.w[j]), Ls);
-        chol_inverse<T, 6>(Ls, Ps);
-        T gs[6];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) gs[k] = gbar[k * m + j];
-        sym_apply<T, 6>(Ps, gs);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) gbar[k * m + j] = gs[k];
-#pragma unroll
-        for (int k = 0; k < 21; ++k) Lf[k * m + j] = Ps[k];
-        ++nclamp;
-      }
-    }
+    if (lane == 0) hess_fix_list<T>(d, fix, nfix, fixW, fixV, nclamp);
     if constexpr (kC) {
       wave_sync_mem();
       if (own) coupled_finish<T>(d, i);
@@ -1805,6 +1843,7 @@ __global__ void __launch_bounds__(kBlock) k_element(DevMesh d) { b_element<T>(d,
 template <typename T, bool kC = false>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2, 8)))
 k_element_hess(DevMesh d) { b_element_hess<T, kC>(d, blockIdx.x); }
+
 
 // --------------------------------------------------------------- Woodbury Gram
 // Per element: Z = T H^{-1} T^T (9x9, F coordinates; T = (R (x) I) Y) and the
@@ -3592,6 +3631,13 @@ static MeshKernel pick_direction(const DevMesh& d) {
                  : (d.coupled ? k_direction<double, true> : k_direction<double, false>);
 }
 static MeshKernel pick_element(const DevMesh& d) { return d.mixed ? k_element<float> : k_element<double>; }
+// The element pass and its Hessian blocks.  (One fused kernel was tried: at
+// two waves per SIMD it spilled about 300 bytes per lane, and the pair ran
+// 456 vs 331 us on the 1.5M-tet hinge limb.)
+static void launch_element_pass(const DevMesh& d, hipStream_t st) {
+  hipLaunchKernelGGL(pick_element(d), dim3(d.nb), dim3(kBlock), 0, st, d);
+  hipLaunchKernelGGL(pick_hess(d), dim3(d.nb), dim3(kBlock), 0, st, d);
+}
 static void launch_bone_blocks(const DevMesh& d, hipStream_t st) {
   if (d.nbones > 0)
     hipLaunchKernelGGL(d.mixed ? k_bone_blocks<float> : k_bone_blocks<double>, dim3(d.nbones), dim3(kBlock), 0, st, d);
@@ -3730,8 +3776,7 @@ void launch_set_pins(const DevMesh& d, hipStream_t st) {
 }
 
 void launch_iteration(const DevMesh& d, const SolvePlan& pl, hipStream_t st) {
-  hipLaunchKernelGGL(pick_element(d), dim3(d.nb), dim3(kBlock), 0, st, d);
-  hipLaunchKernelGGL(pick_hess(d), dim3(d.nb), dim3(kBlock), 0, st, d);
+  launch_element_pass(d, st);
   launch_bone_blocks(d, st);
   hipLaunchKernelGGL(pick_gram(d), dim3(d.nbg), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_gram_reduce, dim3((kGramEntries + 15) / 16), dim3(kBlock), 0, st, d);
@@ -3750,8 +3795,7 @@ void launch_iteration(const DevMesh& d, const SolvePlan& pl, hipStream_t st) {
 // ev[4] end.
 void launch_iteration_phased(const DevMesh& d, const SolvePlan& pl, hipStream_t st, hipEvent_t* ev) {
   (void)hipEventRecord(ev[0], st);
-  hipLaunchKernelGGL(pick_element(d), dim3(d.nb), dim3(kBlock), 0, st, d);
-  hipLaunchKernelGGL(pick_hess(d), dim3(d.nb), dim3(kBlock), 0, st, d);
+  launch_element_pass(d, st);
   (void)hipEventRecord(ev[1], st);
   launch_bone_blocks(d, st);
   hipLaunchKernelGGL(pick_gram(d), dim3(d.nbg), dim3(kBlock), 0, st, d);
@@ -3772,8 +3816,7 @@ void launch_iteration_phased(const DevMesh& d, const SolvePlan& pl, hipStream_t 
 void launch_class(int k, const DevMesh& d, const SolvePlan& pl, hipStream_t st) {
   switch (k) {
     case 0:
-      hipLaunchKernelGGL(pick_element(d), dim3(d.nb), dim3(kBlock), 0, st, d);
-      hipLaunchKernelGGL(pick_hess(d), dim3(d.nb), dim3(kBlock), 0, st, d);
+      launch_element_pass(d, st);
       launch_bone_blocks(d, st);
       break;
     case 1: hipLaunchKernelGGL(pick_gram(d), dim3(d.nbg), dim3(kBlock), 0, st, d); break;
@@ -3800,8 +3843,7 @@ void launch_class(int k, const DevMesh& d, const SolvePlan& pl, hipStream_t st) 
 
 // evaluation at the current state: element pass, Woodbury system, direction
 void launch_evaluate(const DevMesh& d, hipStream_t st) {
-  hipLaunchKernelGGL(pick_element(d), dim3(d.nb), dim3(kBlock), 0, st, d);
-  hipLaunchKernelGGL(pick_hess(d), dim3(d.nb), dim3(kBlock), 0, st, d);
+  launch_element_pass(d, st);
   launch_bone_blocks(d, st);
   hipLaunchKernelGGL(pick_gram(d), dim3(d.nbg), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(k_gram_reduce, dim3((kGramEntries + 15) / 16), dim3(kBlock), 0, st, d);
