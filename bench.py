@@ -230,6 +230,8 @@ def run(args):
         out["serving"] = serving(args)
     if args.alpha_search:
         out["alpha_search"] = alpha_search_leg()
+    if args.adjoint:
+        out["adjoint"] = adjoint_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args)
     return out
@@ -253,6 +255,42 @@ def limb_leg(args):
         print(f"[bench] limb ramp {prec}: {fr['converged']}/{fr['count']} converged, {fr['iterations']} iterations, "
               f"{fr['wall_s']:.1f} s", file=sys.stderr, flush=True)
         ln["mesh"].close()
+    return out
+
+
+def adjoint_leg():
+    """The adjoint of the 8-group marker limb (16x16x64, 98,304 tets): a
+    forward solve from rest to |g| <= 1e-8, then dL/da for the marker loss
+    L = 1/2 sum_markers |q_v - X_v|^2 (X: rest positions), and the adjoint's
+    wall time against the forward solve's."""
+    import torch
+    from paper_2006_08821_amd import workloads as wl
+    from paper_2006_08821_amd.emu import Mesh
+    p = wl.adjoint_case()
+    mesh = Mesh(p)
+    mesh.solve(grad_tol=1e-8, max_iters=20000, warm_start=0)  # first call: graph capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    q, st = mesh.solve(grad_tol=1e-8, max_iters=20000, warm_start=0)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    mk = p.extra["markers"]
+    dLdq = torch.zeros_like(q)
+    dLdq[mk] = q[mk] - torch.as_tensor(p.rest_xyz[mk], dtype=q.dtype, device=q.device)
+    mesh.solve_grad(dLdq)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g, sta = mesh.solve_grad(dLdq, stats=True)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    mesh.close()
+    out = {"workload": "adjoint limb 16x16x64 (98,304 tets), 8 groups, 64 markers",
+           "forward": {"status": st["status"], "iters": st["iters"], "s": t_fwd},
+           "adjoint": {"status": sta["status"], "cg_steps": sta["iters"], "s": t_adj,
+                       "ms_per_cg_step": t_adj / max(1, sta["iters"]) * 1e3},
+           "adjoint_over_forward": t_adj / t_fwd}
+    print(f"[bench] adjoint: forward {st['iters']} iterations {t_fwd:.3f} s, adjoint {sta['iters']} CG steps "
+          f"{t_adj:.3f} s", file=sys.stderr, flush=True)
     return out
 
 
@@ -425,6 +463,7 @@ def main():
     ap.add_argument("--serve-max-iters", type=int, default=20000)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--alpha-search", type=int, default=1, help="run the alpha-search leg (0: skip)")
+    ap.add_argument("--adjoint", type=int, default=1, help="run the adjoint leg (0: skip)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (for scaling HBM counters)")
     args = ap.parse_args()
