@@ -1228,26 +1228,6 @@ emu_status emu_profile_kernels(emu_mesh* M, int32_t reps, double* ms_out, void* 
 
 }  // extern "C"
 
-// Sum of the nb double-double block partials (fixed order) on the host.
-// nb <= 1024 (the element passes' workgroup count), so the partials fit in a
-// fixed buffer on the stack.
-static double host_dd_sum(emu_mesh* M, const double* dpart, int nb) {
-  double h[2 * 1024];
-  HIPCHK(hipMemcpyAsync(h, dpart, 2 * (size_t)nb * 8, hipMemcpyDeviceToHost, M->st));
-  HIPCHK(hipStreamSynchronize(M->st));
-  double hi = 0, lo = 0;
-  for (int b = 0; b < nb; ++b) {
-    // two-sum of (hi, lo) + (h[2b], h[2b+1])
-    double s = hi + h[2 * b];
-    double bb = s - hi;
-    double e = (hi - (s - bb)) + (h[2 * b] - bb);
-    e += lo + h[2 * b + 1];
-    hi = s + e;
-    lo = e - (hi - s);
-  }
-  return hi + lo;
-}
-
 namespace {
 
 // Device work arrays of the adjoint (F-space vectors [9][m], vertex vectors
@@ -1307,38 +1287,28 @@ emu_status adjoint_run(emu_mesh* M, const AdjWork& w, const double* dL_dq, doubl
   emu::launch_weighted_grad(d, w.vx, w.r, M->st);
   HIPCHK(hipMemsetAsync(w.lam, 0, 9 * m * 8, M->st));
   HIPCHK(hipMemsetAsync(w.hp, 0, 9 * m * 8, M->st));
-  // preconditioned conjugate gradients on d2E/dF2 lam = b
-  emu::launch_precond(d, w.r, w.z, w.ypart, w.part, d.p, M->st);
-  double rz = host_dd_sum(M, w.part, d.nb);
+  // preconditioned conjugate gradients on d2E/dF2 lam = b.  alpha, beta, r.z
+  // and the stop test are computed on the device (k_cg_scalar); the host
+  // launches kCgPerCheck steps at a time and then reads the stop flag, and the
+  // steps after the stop return at once.
+  constexpr int kMaxSteps = 20000, kCgPerCheck = 8;
+  const emu::CgWork cw{w.lam, w.r, w.z, w.p, w.hp, w.ypart, w.part, w.vx, d.p};
+  emu::launch_cg_begin(d, kMaxSteps, M->st);
+  emu::launch_precond(d, w.r, w.z, w.ypart, w.part, d.p, M->st, 1);
+  emu::launch_cg_scalar(d, w.part, emu::kCgInitRz, M->st);
   HIPCHK(hipMemcpyAsync(w.p, w.z, 9 * m * 8, hipMemcpyDeviceToDevice, M->st));
-  // |b| for the relative stopping test
-  emu::launch_cg_update(d, 0.0, w.p, w.hp, w.lam, w.r, w.part, M->st);
-  const double bnorm = std::sqrt(std::max(0.0, host_dd_sum(M, w.part, d.nb)));
-  const double tol = 1e-10 * bnorm;
-  int it = 0;
-  double rnorm = bnorm;
-  const int max_it = 20000;
-  int status = EMU_OK;
-  while (rnorm > tol && it < max_it) {
-    emu::launch_field_solve(d, M->plan, w.p, w.vx, M->st);
-    emu::launch_hvp(d, w.p, w.vx, w.hp, w.part, M->st);
-    const double php = host_dd_sum(M, w.part, d.nb);
-    if (!(php > 0) || !std::isfinite(php)) {
-      status = EMU_E_NONFINITE;
-      break;
-    }
-    const double alpha = rz / php;
-    emu::launch_cg_update(d, alpha, w.p, w.hp, w.lam, w.r, w.part, M->st);
-    rnorm = std::sqrt(std::max(0.0, host_dd_sum(M, w.part, d.nb)));
-    ++it;
-    if (rnorm <= tol) break;
-    emu::launch_precond(d, w.r, w.z, w.ypart, w.part, d.p, M->st);
-    const double rz2 = host_dd_sum(M, w.part, d.nb);
-    const double beta = rz2 / rz;
-    rz = rz2;
-    emu::launch_cg_dir(d, beta, w.z, w.p, M->st);
+  // alpha = 0: the update only measures |b|^2
+  emu::launch_cg_update(d, w.p, w.hp, w.lam, w.r, w.part, M->st);
+  emu::launch_cg_scalar(d, w.part, emu::kCgInitR, M->st);
+  for (int k = 0; k <= kMaxSteps / kCgPerCheck; ++k) {
+    for (int j = 0; j < kCgPerCheck; ++j) emu::launch_cg_step(d, M->plan, cw, M->st);
+    read_ctl(M);
+    if (M->h_ctl->done) break;
   }
-  if (status == EMU_OK && rnorm > tol) status = EMU_E_NOT_CONVERGED;
+  const emu::Ctl& c = *M->h_ctl;
+  const int it = c.cg_it;
+  const double rnorm = c.cg_rnorm, bnorm = c.cg_bnorm;
+  const int status = c.done ? c.status : EMU_E_NOT_CONVERGED;
   // dL/da_g = -2 kf sum_{i in g} vol (lam_i u).(F_i u)
   emu::launch_adj_da(d, w.lam, w.el, M->st);
   emu::launch_group_sum(d, w.el, -2.0 * M->hm.kf, w.da, M->st);
@@ -1359,7 +1329,8 @@ emu_status adjoint_run(emu_mesh* M, const AdjWork& w, const double* dL_dq, doubl
     stats->ms_total = ms;
   }
   release_user_stream(M, stream);
-  if (status != EMU_OK) emu::set_error("adjoint conjugate gradients did not converge");
+  if (status == EMU_E_NONFINITE) emu::set_error("adjoint conjugate gradients: p.Hp or |b| not positive and finite");
+  else if (status != EMU_OK) emu::set_error("adjoint conjugate gradients did not converge");
   return (emu_status)status;
 }
 

@@ -54,6 +54,11 @@ struct Ctl {
   double sigma0, armijo_c, rho;
   double stall_rel;
   double rtol2;        // relative stop: |g|^2 <= rtol2 |g_0|^2
+  // conjugate gradients of the adjoint (set and read by k_cg_scalar)
+  double cg_rz;        // r . z of the current residual
+  double cg_alpha, cg_beta;
+  double cg_rnorm, cg_bnorm, cg_tol;  // |r|, |b|, stop at |r| <= cg_tol
+  int32_t cg_it, cg_max;  // steps taken, step cap
 };
 
 // Plain pointers to every device array of a mesh (passed by value).

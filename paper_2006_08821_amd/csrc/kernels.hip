@@ -3078,9 +3078,9 @@ DEV void write_partial(DD (&acc)[NV], DD* sh, double* out) {
 }
 
 // ACAP right-hand-side contributions of a field V ([9][m])
-__global__ void __launch_bounds__(kBlock) k_contrib_field(DevMesh d, const double* V) {
+__global__ void __launch_bounds__(kBlock) k_contrib_field(DevMesh d, const double* V, int check_done) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= d.m) return;
+  if (i >= d.m || (check_done && d.ctl->done)) return;
   Elem e;
   load_elem(d, i, e);
   double F[9];
@@ -3285,6 +3285,7 @@ __global__ void k_clear_step(DevMesh d) {
 // with dcof(S)[X] = cof(S + X) - cof(S) - cof(X).  Block partial of v . out.
 __global__ void __launch_bounds__(kBlock) k_hvp(DevMesh d, const double* V, const double* x, double* out,
                                                 double* part) {
+  if (d.ctl->done) return;
   __shared__ DD sh[kBlock];
   DD acc[1] = {DD{0, 0}};
   const int m = d.m;
@@ -3335,9 +3336,12 @@ __global__ void __launch_bounds__(kBlock) k_hvp(DevMesh d, const double* V, cons
   write_partial<1>(acc, sh, part + 2 * blockIdx.x);
 }
 
-// lam += alpha p, r -= alpha Hp; block partial of |r|^2
-__global__ void __launch_bounds__(kBlock) k_cg_update(DevMesh d, double alpha, const double* P, const double* HP,
-                                                      double* lam, double* r, double* part) {
+// lam += alpha p, r -= alpha Hp (alpha from the control block); block
+// partial of |r|^2
+__global__ void __launch_bounds__(kBlock) k_cg_update(DevMesh d, const double* P, const double* HP, double* lam,
+                                                      double* r, double* part) {
+  if (d.ctl->done) return;
+  const double alpha = d.ctl->cg_alpha;
   __shared__ DD sh[kBlock];
   DD acc[1] = {DD{0, 0}};
   const int64_t n9 = 9 * (int64_t)d.m;
@@ -3350,17 +3354,88 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(DevMesh d, double alpha, c
   write_partial<1>(acc, sh, part + 2 * blockIdx.x);
 }
 
-// p = z + beta p
-__global__ void __launch_bounds__(kBlock) k_cg_dir(DevMesh d, double beta, const double* Z, double* P) {
+// p = z + beta p (beta from the control block)
+__global__ void __launch_bounds__(kBlock) k_cg_dir(DevMesh d, const double* Z, double* P) {
+  if (d.ctl->done) return;
+  const double beta = d.ctl->cg_beta;
   const int64_t n9 = 9 * (int64_t)d.m;
   for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n9; k += (int64_t)d.nb * kBlock)
     P[k] = Z[k] + beta * P[k];
 }
 
+// Conjugate-gradient scalars of the adjoint, on the device so that the steps
+// run without host round trips.  One workgroup: s = the fixed-order
+// double-double sum of the nb block partials, then
+//   kCgInitRz  rz = s (r . z of the first residual)
+//   kCgInitR   |b| = sqrt(s), tol = 1e-10 |b|; stop at once if |b| <= tol
+//   kCgAlpha   alpha = rz / s with s = p . Hp; stop with EMU_E_NONFINITE unless
+//              0 < s < inf
+//   kCgResid   |r| = sqrt(s) after the update, one more step; stop at
+//              |r| <= tol, or with EMU_E_NOT_CONVERGED at the step cap
+//   kCgBeta    beta = s / rz, rz = s (s = r . z of the new residual)
+__global__ void __launch_bounds__(kBlock) k_cg_scalar(DevMesh d, const double* part, int what) {
+  Ctl* ctl = d.ctl;
+  if (ctl->done) return;
+  __shared__ DD sh[kBlock];
+  DD acc[1] = {DD{0, 0}};
+  for (int b = threadIdx.x; b < d.nb; b += kBlock) acc[0] = dd_add(acc[0], DD{part[2 * b], part[2 * b + 1]});
+  block_reduce_dd<1>(acc, sh);
+  if (threadIdx.x != 0) return;
+  const double s = acc[0].hi + acc[0].lo;
+  if (what == kCgInitRz) {
+    ctl->cg_rz = s;
+  } else if (what == kCgInitR) {
+    const double b = sqrt(fmax(0.0, s));
+    ctl->cg_bnorm = b;
+    ctl->cg_rnorm = b;
+    ctl->cg_tol = 1e-10 * b;
+    if (!isfinite(b)) {
+      ctl->status = EMU_E_NONFINITE_CODE;
+      ctl->done = 1;
+    } else if (!(b > ctl->cg_tol)) {
+      ctl->done = 1;
+    }
+  } else if (what == kCgAlpha) {
+    if (!(s > 0.0) || !isfinite(s)) {
+      ctl->status = EMU_E_NONFINITE_CODE;
+      ctl->done = 1;
+    } else {
+      ctl->cg_alpha = ctl->cg_rz / s;
+    }
+  } else if (what == kCgResid) {
+    const double r = sqrt(fmax(0.0, s));
+    ctl->cg_rnorm = r;
+    ctl->cg_it += 1;
+    if (!(r > ctl->cg_tol)) {
+      ctl->done = 1;
+    } else if (ctl->cg_it >= ctl->cg_max) {
+      ctl->status = EMU_E_NOT_CONVERGED_CODE;
+      ctl->done = 1;
+    }
+  } else {
+    ctl->cg_beta = s / ctl->cg_rz;
+    ctl->cg_rz = s;
+  }
+}
+// Start of the adjoint's conjugate gradients: clear the stop flag and status
+// the element pass may have left, zero alpha (the first update only measures
+// |b|), no steps yet, cap max_steps.
+__global__ void k_cg_begin(DevMesh d, int max_steps) {
+  Ctl* ctl = d.ctl;
+  ctl->done = 0;
+  ctl->status = 0;
+  ctl->cg_alpha = 0.0;
+  ctl->cg_beta = 0.0;
+  ctl->cg_it = 0;
+  ctl->cg_max = max_steps;
+}
+
 // Preconditioner, part 1: rbar = H^{-1} Y^T vec(R^T r) (blocks), stored in rbar
 // ([9][m]), and block partials of y[(c,j)] = sum_i w_i (R D(rbar) gphi_j)[c].
 template <typename T, bool kC = false>
-__global__ void __launch_bounds__(kBlock) k_pc1(DevMesh d, const double* r, double* ypart, double* rbar) {
+__global__ void __launch_bounds__(kBlock) k_pc1(DevMesh d, const double* r, double* ypart, double* rbar,
+                                                int check_done) {
+  if (check_done && d.ctl->done) return;
   __shared__ double red[kBlock / 64][48];
   const int m = d.m;
   const T* Lf = (const T*)d.Lf;
@@ -3429,7 +3504,8 @@ __global__ void __launch_bounds__(kBlock) k_pc1(DevMesh d, const double* r, doub
 
 // Preconditioner, part 2 (one workgroup): y = sum of partials, z = C^{-1} y with
 // the Cholesky factor of C kept by the last element/Gram pass.
-__global__ void __launch_bounds__(64) k_pc_solve(DevMesh d, const double* ypart) {
+__global__ void __launch_bounds__(64) k_pc_solve(DevMesh d, const double* ypart, int check_done) {
+  if (check_done && d.ctl->done) return;
   __shared__ double yv[48];
   const int t = threadIdx.x;
   const int k1 = d.k1, K = 3 * k1;
@@ -3474,7 +3550,8 @@ __global__ void __launch_bounds__(64) k_pc_solve(DevMesh d, const double* ypart)
 // (F coordinates); block partials of r . z.
 template <typename T, bool kC = false>
 __global__ void __launch_bounds__(kBlock) k_pc2(DevMesh d, const double* r, double* zout, double* part,
-                                                const double* rbar) {
+                                                const double* rbar, int check_done) {
+  if (check_done && d.ctl->done) return;
   __shared__ DD sh[kBlock];
   DD acc[1] = {DD{0, 0}};
   const int m = d.m;
@@ -3646,8 +3723,8 @@ static void launch_bone_dir(const DevMesh& d, hipStream_t st) {
   if (d.nbones > 0)
     hipLaunchKernelGGL(d.mixed ? k_bone_dir<float> : k_bone_dir<double>, dim3(d.nbones), dim3(kBlock), 0, st, d);
 }
-typedef void (*Pc1Kernel)(DevMesh, const double*, double*, double*);
-typedef void (*Pc2Kernel)(DevMesh, const double*, double*, double*, const double*);
+typedef void (*Pc1Kernel)(DevMesh, const double*, double*, double*, int);
+typedef void (*Pc2Kernel)(DevMesh, const double*, double*, double*, const double*, int);
 static Pc1Kernel pick_pc1(const DevMesh& d) {
   return d.mixed ? (d.coupled ? k_pc1<float, true> : k_pc1<float, false>)
                  : (d.coupled ? k_pc1<double, true> : k_pc1<double, false>);
@@ -3695,14 +3772,15 @@ void launch_solve(const DevMesh& d, const SolvePlan& pl, int add_pin, double* x,
   for (int L = 0; L < pl.nlevels; ++L) launch_fwd_level(d, pl, L, check_done, st);
   for (int L = 0; L < pl.nlevels; ++L) launch_bwd_level(d, pl, L, x, check_done, st);
 }
-void launch_sweeps(const DevMesh& d, const SolvePlan& pl, double* x, hipStream_t st) {
-  for (int L = 0; L < pl.nlevels; ++L) launch_fwd_level(d, pl, L, 0, st);
-  for (int L = 0; L < pl.nlevels; ++L) launch_bwd_level(d, pl, L, x, 0, st);
+void launch_sweeps(const DevMesh& d, const SolvePlan& pl, double* x, hipStream_t st, int check_done) {
+  for (int L = 0; L < pl.nlevels; ++L) launch_fwd_level(d, pl, L, check_done, st);
+  for (int L = 0; L < pl.nlevels; ++L) launch_bwd_level(d, pl, L, x, check_done, st);
 }
-void launch_field_solve(const DevMesh& d, const SolvePlan& pl, const double* V, double* x, hipStream_t st) {
-  hipLaunchKernelGGL(k_contrib_field, dim3(blocks(d.m)), dim3(kBlock), 0, st, d, V);
-  hipLaunchKernelGGL(k_rhs, dim3(rhs_blocks(d.nf)), dim3(kBlock), 0, st, d, 0, 0);
-  launch_sweeps(d, pl, x, st);
+void launch_field_solve(const DevMesh& d, const SolvePlan& pl, const double* V, double* x, hipStream_t st,
+                        int check_done) {
+  hipLaunchKernelGGL(k_contrib_field, dim3(blocks(d.m)), dim3(kBlock), 0, st, d, V, check_done);
+  hipLaunchKernelGGL(k_rhs, dim3(rhs_blocks(d.nf)), dim3(kBlock), 0, st, d, 0, check_done);
+  launch_sweeps(d, pl, x, st, check_done);
 }
 void launch_weighted_grad(const DevMesh& d, const double* x, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_weighted_grad, dim3(blocks(d.m)), dim3(kBlock), 0, st, d, x, out);
@@ -3710,26 +3788,42 @@ void launch_weighted_grad(const DevMesh& d, const double* x, double* out, hipStr
 void launch_hvp(const DevMesh& d, const double* V, const double* x, double* out, double* part, hipStream_t st) {
   hipLaunchKernelGGL(k_hvp, dim3(d.nb), dim3(kBlock), 0, st, d, V, x, out, part);
 }
-void launch_cg_update(const DevMesh& d, double alpha, const double* P, const double* HP, double* lam, double* r,
-                      double* part, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_update, dim3(d.nb), dim3(kBlock), 0, st, d, alpha, P, HP, lam, r, part);
+void launch_cg_update(const DevMesh& d, const double* P, const double* HP, double* lam, double* r, double* part,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_update, dim3(d.nb), dim3(kBlock), 0, st, d, P, HP, lam, r, part);
 }
-void launch_cg_dir(const DevMesh& d, double beta, const double* Z, double* P, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_dir, dim3(d.nb), dim3(kBlock), 0, st, d, beta, Z, P);
+void launch_cg_dir(const DevMesh& d, const double* Z, double* P, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_dir, dim3(d.nb), dim3(kBlock), 0, st, d, Z, P);
+}
+void launch_cg_scalar(const DevMesh& d, const double* part, int what, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kBlock), 0, st, d, part, what);
+}
+void launch_cg_begin(const DevMesh& d, int max_steps, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_begin, dim3(1), dim3(1), 0, st, d, max_steps);
 }
 void launch_precond(const DevMesh& d, const double* r, double* z, double* ypart, double* part, double* rbar,
-                    hipStream_t st) {
-  hipLaunchKernelGGL(pick_pc1(d), dim3(d.nb), dim3(kBlock), 0, st, d, r, ypart, rbar);
-  hipLaunchKernelGGL(k_pc_solve, dim3(1), dim3(64), 0, st, d, ypart);
+                    hipStream_t st, int check_done) {
+  hipLaunchKernelGGL(pick_pc1(d), dim3(d.nb), dim3(kBlock), 0, st, d, r, ypart, rbar, check_done);
+  hipLaunchKernelGGL(k_pc_solve, dim3(1), dim3(64), 0, st, d, ypart, check_done);
   hipLaunchKernelGGL(k_uz, dim3(uz_blocks(d.n)), dim3(kBlock), 0, st, d);
-  hipLaunchKernelGGL(pick_pc2(d), dim3(d.nb), dim3(kBlock), 0, st, d, r, z, part, (const double*)rbar);
+  hipLaunchKernelGGL(pick_pc2(d), dim3(d.nb), dim3(kBlock), 0, st, d, r, z, part, (const double*)rbar, check_done);
+}
+void launch_cg_step(const DevMesh& d, const SolvePlan& pl, const CgWork& w, hipStream_t st) {
+  launch_field_solve(d, pl, w.p, w.vx, st, 1);  // vx = L^{-1} G^T W p
+  launch_hvp(d, w.p, w.vx, w.hp, w.part, st);
+  launch_cg_scalar(d, w.part, kCgAlpha, st);
+  launch_cg_update(d, w.p, w.hp, w.lam, w.r, w.part, st);
+  launch_cg_scalar(d, w.part, kCgResid, st);
+  launch_precond(d, w.r, w.z, w.ypart, w.part, w.rbar, st, 1);
+  launch_cg_scalar(d, w.part, kCgBeta, st);
+  launch_cg_dir(d, w.z, w.p, st);
 }
 void launch_grad_field(const DevMesh& d, const double* x, double* V, hipStream_t st) {
   hipLaunchKernelGGL(k_grad_field, dim3(blocks(d.m)), dim3(kBlock), 0, st, d, x, V);
 }
 void launch_lff_apply(const DevMesh& d, const double* x, double* V, hipStream_t st) {
   hipLaunchKernelGGL(k_grad_field, dim3(blocks(d.m)), dim3(kBlock), 0, st, d, x, V);
-  hipLaunchKernelGGL(k_contrib_field, dim3(blocks(d.m)), dim3(kBlock), 0, st, d, (const double*)V);
+  hipLaunchKernelGGL(k_contrib_field, dim3(blocks(d.m)), dim3(kBlock), 0, st, d, (const double*)V, 0);
   hipLaunchKernelGGL(k_rhs, dim3(rhs_blocks(d.nf)), dim3(kBlock), 0, st, d, 0, 0);
 }
 int eig_gram_blocks(int nf) { return std::max(1, std::min(512, (nf + 255) / 256)); }

@@ -62,17 +62,30 @@ void launch_iteration_phased(const DevMesh& d, const SolvePlan& pl, hipStream_t 
 void launch_evaluate(const DevMesh& d, hipStream_t st);
 void launch_class(int k, const DevMesh& d, const SolvePlan& pl, hipStream_t st);
 // adjoint building blocks
-void launch_sweeps(const DevMesh& d, const SolvePlan& pl, double* x, hipStream_t st);
-void launch_field_solve(const DevMesh& d, const SolvePlan& pl, const double* V, double* x, hipStream_t st);
+// check_done 1: every kernel returns at once while ctl->done is set
+void launch_sweeps(const DevMesh& d, const SolvePlan& pl, double* x, hipStream_t st, int check_done = 0);
+void launch_field_solve(const DevMesh& d, const SolvePlan& pl, const double* V, double* x, hipStream_t st,
+                        int check_done = 0);
 void launch_weighted_grad(const DevMesh& d, const double* x, double* out, hipStream_t st);
 void launch_hvp(const DevMesh& d, const double* V, const double* x, double* out, double* part, hipStream_t st);
-void launch_cg_update(const DevMesh& d, double alpha, const double* P, const double* HP, double* lam, double* r,
-                      double* part, hipStream_t st);
-void launch_cg_dir(const DevMesh& d, double beta, const double* Z, double* P, hipStream_t st);
+// adjoint conjugate gradients; alpha, beta, r.z and the stop test live in the
+// control block (k_cg_scalar), so the steps need no host round trip
+enum { kCgInitRz, kCgInitR, kCgAlpha, kCgResid, kCgBeta };
+struct CgWork {
+  double *lam, *r, *z, *p, *hp, *ypart, *part, *vx, *rbar;
+};
+void launch_cg_update(const DevMesh& d, const double* P, const double* HP, double* lam, double* r, double* part,
+                      hipStream_t st);
+void launch_cg_dir(const DevMesh& d, const double* Z, double* P, hipStream_t st);
+void launch_cg_scalar(const DevMesh& d, const double* part, int what, hipStream_t st);
+void launch_cg_begin(const DevMesh& d, int max_steps, hipStream_t st);
+// one step (field solve, Hp, alpha, update, |r|, preconditioner, beta, p);
+// every kernel returns at once once ctl->done is set
+void launch_cg_step(const DevMesh& d, const SolvePlan& pl, const CgWork& w, hipStream_t st);
 // z = Htilde^{-1} r (world-frame F fields [9][m]) with the iteration's blocks and
 // Woodbury factor; rbar ([9][m]) is scratch.
 void launch_precond(const DevMesh& d, const double* r, double* z, double* ypart, double* part, double* rbar,
-                    hipStream_t st);
+                    hipStream_t st, int check_done = 0);
 // contact loop: penalty forces of the free vertices into d.rhs (block partials
 // of |f|^2, contact_blocks(d) of them); q += x2, zc += z; the pending step
 // together with zc (then none is pending)
