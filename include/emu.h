@@ -262,7 +262,12 @@ emu_status emu_solve(emu_mesh* mesh, const emu_solve_opts* opts, double* q_out,
 /* Adjoint of the equilibrium w.r.t. the group activations at the current
    (converged) state: given dL/dq (device [n][3]), write dL/da (host
    [n_groups]).  Requires a converged emu_solve at the current activations
-   (EMU_E_STATE otherwise). */
+   (EMU_E_STATE otherwise).  The adjoint system is solved by preconditioned
+   conjugate gradients to |r| <= 1e-10 |b|; stats (may be NULL) gets the steps
+   in iters, |b| in grad_norm0 and the final |r| in grad_norm.  Errors:
+   EMU_E_NONFINITE when |b| or |r| is not finite (for instance a NaN in dL/dq)
+   or p.Hp <= 0; EMU_E_NOT_CONVERGED after 20000 steps.  The state is never
+   changed. */
 emu_status emu_solve_grad(emu_mesh* mesh, const double* dL_dq, double* dL_da,
                           emu_solve_stats* stats, void* stream);
 

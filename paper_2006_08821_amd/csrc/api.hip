@@ -1329,7 +1329,7 @@ emu_status adjoint_run(emu_mesh* M, const AdjWork& w, const double* dL_dq, doubl
     stats->ms_total = ms;
   }
   release_user_stream(M, stream);
-  if (status == EMU_E_NONFINITE) emu::set_error("adjoint conjugate gradients: p.Hp or |b| not positive and finite");
+  if (status == EMU_E_NONFINITE) emu::set_error("adjoint conjugate gradients: |b|, |r| or p.Hp not finite, or p.Hp <= 0");
   else if (status != EMU_OK) emu::set_error("adjoint conjugate gradients did not converge");
   return (emu_status)status;
 }

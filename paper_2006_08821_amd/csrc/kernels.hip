@@ -3367,11 +3367,13 @@ __global__ void __launch_bounds__(kBlock) k_cg_dir(DevMesh d, const double* Z, d
 // run without host round trips.  One workgroup: s = the fixed-order
 // double-double sum of the nb block partials, then
 //   kCgInitRz  rz = s (r . z of the first residual)
-//   kCgInitR   |b| = sqrt(s), tol = 1e-10 |b|; stop at once if |b| <= tol
+//   kCgInitR   |b| = sqrt(s), tol = 1e-10 |b|; stop at once if |b| <= tol,
+//              with EMU_E_NONFINITE if |b| is not finite
 //   kCgAlpha   alpha = rz / s with s = p . Hp; stop with EMU_E_NONFINITE unless
 //              0 < s < inf
 //   kCgResid   |r| = sqrt(s) after the update, one more step; stop at
-//              |r| <= tol, or with EMU_E_NOT_CONVERGED at the step cap
+//              |r| <= tol, with EMU_E_NONFINITE if |r| is not finite, or with
+//              EMU_E_NOT_CONVERGED at the step cap
 //   kCgBeta    beta = s / rz, rz = s (s = r . z of the new residual)
 __global__ void __launch_bounds__(kBlock) k_cg_scalar(DevMesh d, const double* part, int what) {
   Ctl* ctl = d.ctl;
@@ -3385,7 +3387,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_scalar(DevMesh d, const double* p
   if (what == kCgInitRz) {
     ctl->cg_rz = s;
   } else if (what == kCgInitR) {
-    const double b = sqrt(fmax(0.0, s));
+    // (fmax would turn a NaN sum into 0, a false convergence)
+    const double b = isfinite(s) ? sqrt(fmax(0.0, s)) : s;
     ctl->cg_bnorm = b;
     ctl->cg_rnorm = b;
     ctl->cg_tol = 1e-10 * b;
@@ -3403,10 +3406,13 @@ __global__ void __launch_bounds__(kBlock) k_cg_scalar(DevMesh d, const double* p
       ctl->cg_alpha = ctl->cg_rz / s;
     }
   } else if (what == kCgResid) {
-    const double r = sqrt(fmax(0.0, s));
+    const double r = isfinite(s) ? sqrt(fmax(0.0, s)) : s;
     ctl->cg_rnorm = r;
     ctl->cg_it += 1;
-    if (!(r > ctl->cg_tol)) {
+    if (!isfinite(r)) {
+      ctl->status = EMU_E_NONFINITE_CODE;
+      ctl->done = 1;
+    } else if (!(r > ctl->cg_tol)) {
       ctl->done = 1;
     } else if (ctl->cg_it >= ctl->cg_max) {
       ctl->status = EMU_E_NOT_CONVERGED_CODE;

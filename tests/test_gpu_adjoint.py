@@ -92,3 +92,33 @@ def test_solve_grad_requires_converged_state(torch):
     with pytest.raises(_lib.EmuError) as e:
         mesh.solve_grad(torch.zeros((p.n_vertices, 3), dtype=torch.float64, device="cuda"))
     assert e.value.code == 8
+
+
+def test_adjoint_degenerate_right_hand_sides(torch):
+    # the conjugate-gradient scalars and the stop test run on the device:
+    # a zero dL/dq stops before the first step with dL/da = 0, a NaN in dL/dq
+    # stops with EMU_E_NONFINITE (|b| not finite), and a repeated call gives
+    # the same bits
+    from paper_2006_08821_amd import _lib
+    from paper_2006_08821_amd.emu import Mesh
+    p, markers, target = _problem()
+    mesh = Mesh(p)
+    q, st = mesh.solve(grad_tol=1e-11)
+    assert st["status"] == 0
+    zero = torch.zeros((p.n_vertices, 3), dtype=torch.float64, device="cuda")
+    g0, s0 = mesh.solve_grad(zero, stats=True)
+    assert s0["status"] == 0 and s0["iters"] == 0, s0
+    assert np.array_equal(g0, np.zeros_like(g0))
+    _, dq = _loss_and_grad(torch, q, markers, target)
+    g1, s1 = mesh.solve_grad(dq, stats=True)
+    g2, s2 = mesh.solve_grad(dq, stats=True)
+    assert s1["status"] == 0 and s1["iters"] > 0 and s1["iters"] == s2["iters"]
+    assert np.array_equal(g1, g2)
+    bad = dq.clone()
+    bad[int(markers[0]), 0] = float("nan")
+    with pytest.raises(_lib.EmuError) as e:
+        mesh.solve_grad(bad)
+    assert e.value.code == 5
+    # the mesh state is unchanged: the next adjoint gives the same bits again
+    g3 = mesh.solve_grad(dq)
+    assert np.array_equal(g1, g3)
