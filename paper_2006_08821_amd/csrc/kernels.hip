@@ -2250,6 +2250,12 @@ DEV void b_gram(const DevMesh& d, int bid) {
       }
       if (nb2 < w1 && el < min(kGramBatch, w1 - nb2)) gram_load_vid(d, nb2 + el, vid);
     }
+    // The product loop runs at a raised wave priority: with two waves per
+    // SIMD, the wave in its matrix-core loop is issued first and keeps the
+    // matrix cores fed, while the other wave's phase A fills the vector ALU
+    // in between (alternating runs on one box: FP64 pass 561 -> 546 us, FP32
+    // 348 -> 331 us).
+    __builtin_amdgcn_s_setprio(1);
     // The K dimension of each product runs over (element, coordinate) pairs
     // of the batch: step st takes the pairs f = 4 st + ks (ks = lane / 16, the
     // lane's K slot) with element f / 3 and coordinate f % 3, so all four
@@ -2321,6 +2327,7 @@ DEV void b_gram(const DevMesh& d, int bid) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __builtin_amdgcn_s_setprio(0);
   }
   // coordinate c of slot k is in ry[(c - k) mod 3]
   const int k3 = k % 3;
