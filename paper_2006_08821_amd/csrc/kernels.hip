@@ -3479,21 +3479,34 @@ __global__ void __launch_bounds__(kBlock) k_pc1(DevMesh d, const double* r, doub
     }
     from_y<double>(rb, D);
     matmul3(R, D, RD);
-    for (int j = 0; j < d.k1; ++j) {
-      double g0 = 0, g1 = 0, g2 = 0;
+    // mode gradients gphi_j = sum_v phi_j(v) b_v, four modes of the four
+    // vertices per round (16-byte loads of the vertex rows); the mode index
+    // is a compile-time constant, so y stays in registers
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const double ph = d.phi[(int64_t)kMaxK1 * e.v[k] + j];
-        g0 += ph * e.b[k][0];
-        g1 += ph * e.b[k][1];
-        g2 += ph * e.b[k][2];
+    for (int q4 = 0; q4 < kMaxK1; q4 += 4) {
+      double ph[4][4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double2* pr = reinterpret_cast<const double2*>(d.phi + (int64_t)kMaxK1 * e.v[v] + q4);
+        const double2 p0 = pr[0], p1 = pr[1];
+        ph[v][0] = p0.x;
+        ph[v][1] = p0.y;
+        ph[v][2] = p1.x;
+        ph[v][3] = p1.y;
       }
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const double contrib = e.w * (RD[3 * c] * g0 + RD[3 * c + 1] * g1 + RD[3 * c + 2] * g2);
+      for (int q = 0; q < 4; ++q) {
+        if (q4 + q >= d.k1) break;  // uniform
+        double g0 = 0, g1 = 0, g2 = 0;
 #pragma unroll
-        for (int jj = 0; jj < kMaxK1; ++jj)
-          if (jj == j) y[c * kMaxK1 + jj] += contrib;
+        for (int v = 0; v < 4; ++v) {
+          g0 += ph[v][q] * e.b[v][0];
+          g1 += ph[v][q] * e.b[v][1];
+          g2 += ph[v][q] * e.b[v][2];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          y[c * kMaxK1 + q4 + q] += e.w * (RD[3 * c] * g0 + RD[3 * c + 1] * g1 + RD[3 * c + 2] * g2);
       }
     }
   }
@@ -3515,44 +3528,65 @@ __global__ void __launch_bounds__(kBlock) k_pc1(DevMesh d, const double* r, doub
   }
 }
 
-// Preconditioner, part 2 (one workgroup): y = sum of partials, z = C^{-1} y with
-// the Cholesky factor of C kept by the last element/Gram pass.
-__global__ void __launch_bounds__(64) k_pc_solve(DevMesh d, const double* ypart, int check_done) {
+// Preconditioner, part 2 (one workgroup of kPcThreads): y = sum of partials,
+// z = C^{-1} y with the Cholesky factor of C kept by the last element/Gram
+// pass.  Wave g adds the partials of workgroups g, g + W, ... (four loads in
+// flight) while the workgroup stages the factor in LDS; the W wave sums are
+// added in order, then wave 0 runs the two substitutions from LDS.
+constexpr int kPcThreads = 1024;
+__global__ void __launch_bounds__(kPcThreads) k_pc_solve(DevMesh d, const double* ypart, int check_done) {
   if (check_done && d.ctl->done) return;
+  constexpr int W = kPcThreads / 64;
+  __shared__ double wsum[W][48];
+  __shared__ double Lsh[48 * 48];
   __shared__ double yv[48];
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, q = t & 63, g = t >> 6;
   const int k1 = d.k1, K = 3 * k1;
+  if (q < 48) {
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    int b = g;
+    for (; b + 3 * W < d.nb; b += 4 * W) {
+      s0 += ypart[48 * b + q];
+      s1 += ypart[48 * (b + W) + q];
+      s2 += ypart[48 * (b + 2 * W) + q];
+      s3 += ypart[48 * (b + 3 * W) + q];
+    }
+    for (; b < d.nb; b += W) s0 += ypart[48 * b + q];
+    wsum[g][q] = (s0 + s1) + (s2 + s3);
+  }
+  for (int k = t; k < 48 * 48; k += kPcThreads) Lsh[k] = d.cfac[k];
+  __syncthreads();
   if (t < 48) {
-    double s0 = 0;
-    for (int b = 0; b < d.nb; ++b) s0 += ypart[48 * b + t];
-    yv[t] = s0;
+    double s = wsum[0][t];
+#pragma unroll
+    for (int w = 1; w < W; ++w) s += wsum[w][t];
+    yv[t] = s;
   }
   __syncthreads();
   if (K == 0) {
     if (t < 48) d.zbuf[t] = 0.0;
     return;
   }
-  // compact index c*k1+j
+  if (g != 0) return;
+  // wave 0 alone from here: its lanes run in lockstep, so every read of yv
+  // below precedes the writes after the substitutions.  Lane t holds entry t
+  // (compact index c*k1+j); step i takes entry i from lane i with a lane read
+  // (no LDS round trip on the dependent chain) and scales it by 1 / L_ii.
   double yt = 0.0;
   if (t < K) yt = yv[(t / k1) * kMaxK1 + (t % k1)];
-  const double* L = d.cfac;
+  const double rd = t < K ? 1.0 / Lsh[t * 49] : 0.0;
   for (int i = 0; i < K; ++i) {
-    const double lti = (t < K) ? L[t * 48 + i] : 1.0;
-    double ui = (t == i) ? yt / lti : 0.0;
-    ui = __shfl(ui, i);
+    const double ui = bcast_lane(yt, i) * bcast_lane(rd, i);
     if (t == i) yt = ui;
-    else if (t > i && t < K) yt -= lti * ui;
+    else if (t > i && t < K) yt -= Lsh[t * 48 + i] * ui;
   }
   for (int i = K - 1; i >= 0; --i) {
-    const double lit = (t < K) ? L[i * 48 + t] : 0.0;
-    const double lii = L[i * 48 + i];
-    double zi = (t == i) ? yt / lii : 0.0;
-    zi = __shfl(zi, i);
+    const double zi = bcast_lane(yt, i) * bcast_lane(rd, i);
     if (t == i) yt = zi;
-    else if (t < i) yt -= lit * zi;
+    else if (t < i) yt -= Lsh[i * 48 + t] * zi;
   }
   if (t < K) yv[t] = yt;
-  __syncthreads();
+  wave_sync_mem();
   if (t < 48) {
     const int c = t / kMaxK1, j = t % kMaxK1;
     d.zbuf[t] = (j < k1 && d.cfac_ok[0]) ? yv[c * k1 + j] : 0.0;
@@ -3817,7 +3851,7 @@ void launch_cg_begin(const DevMesh& d, int max_steps, hipStream_t st) {
 void launch_precond(const DevMesh& d, const double* r, double* z, double* ypart, double* part, double* rbar,
                     hipStream_t st, int check_done) {
   hipLaunchKernelGGL(pick_pc1(d), dim3(d.nb), dim3(kBlock), 0, st, d, r, ypart, rbar, check_done);
-  hipLaunchKernelGGL(k_pc_solve, dim3(1), dim3(64), 0, st, d, ypart, check_done);
+  hipLaunchKernelGGL(k_pc_solve, dim3(1), dim3(kPcThreads), 0, st, d, ypart, check_done);
   hipLaunchKernelGGL(k_uz, dim3(uz_blocks(d.n)), dim3(kBlock), 0, st, d);
   hipLaunchKernelGGL(pick_pc2(d), dim3(d.nb), dim3(kBlock), 0, st, d, r, z, part, (const double*)rbar, check_done);
 }
