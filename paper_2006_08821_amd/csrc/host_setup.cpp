@@ -517,24 +517,52 @@ static void front_factor(Factor& fac, int s, std::vector<double>& Fm, int h,
   if (!dense_chol(w, F, ld, par)) fail(EMU_E_SINGULAR, "ACAP operator is not positive definite "
                                   "(a connected part of the mesh has no pinned vertex)");
   const int hb = h - w;
-  // TRSM: rows r >= w:  L_od[r] = F[r] L_dd^{-T}
-  auto trsm_row = [&](int64_t rr) {
-    double* ri = F + (w + rr) * ld;
+  // The dense products below keep every dot product a single sum in
+  // ascending k (the same rounding as one product at a time) and interleave
+  // four or eight independent ones, so that the additions do not wait on
+  // each other.
+  // TRSM: rows r >= w:  L_od[r] = F[r] L_dd^{-T}, four rows at a time
+  auto trsm_rows = [&](int64_t blk) {
+    const int64_t r0 = 4 * blk, nr = std::min<int64_t>(4, hb - r0);
+    double* ri[4];
+    for (int q = 0; q < 4; ++q) ri[q] = F + (w + r0 + std::min<int64_t>(q, nr - 1)) * ld;
     for (int j = 0; j < w; ++j) {
       const double* rj = F + j * ld;
-      double t = ri[j];
-      for (int k = 0; k < j; ++k) t -= ri[k] * rj[k];
-      ri[j] = t / rj[j];
+      double t0 = ri[0][j], t1 = ri[1][j], t2 = ri[2][j], t3 = ri[3][j];
+      for (int k = 0; k < j; ++k) {
+        const double x = rj[k];
+        t0 -= ri[0][k] * x;
+        t1 -= ri[1][k] * x;
+        t2 -= ri[2][k] * x;
+        t3 -= ri[3][k] * x;
+      }
+      // rows past hb alias the last row; it is written last with its own value
+      ri[3][j] = t3 / rj[j];
+      ri[2][j] = t2 / rj[j];
+      ri[1][j] = t1 / rj[j];
+      ri[0][j] = t0 / rj[j];
     }
   };
-  if (par) parallel_for(hb, trsm_row, 4); else for (int r = 0; r < hb; ++r) trsm_row(r);
-  // SYRK: U = F_bb - L_od L_od^T (lower, row-major hb x hb)
+  const int64_t hb4 = (hb + 3) / 4;
+  if (par) parallel_for(hb4, trsm_rows, 1); else for (int64_t r = 0; r < hb4; ++r) trsm_rows(r);
+  // SYRK: U = F_bb - L_od L_od^T (lower, row-major hb x hb), eight entries of
+  // a row at a time
   U.assign((size_t)hb * hb, 0.0);
   auto syrk_row = [&](int64_t a) {
     const double* la = F + (w + a) * ld;
     double* ua = U.data() + a * hb;
     const double* fa = F + (w + a) * ld + w;
-    for (int b = 0; b <= a; ++b) {
+    int b = 0;
+    for (; b + 7 <= a; b += 8) {
+      const double* lb = F + (w + b) * ld;
+      double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int k = 0; k < w; ++k) {
+        const double x = la[k];
+        for (int q = 0; q < 8; ++q) t[q] += x * lb[q * ld + k];
+      }
+      for (int q = 0; q < 8; ++q) ua[b + q] = fa[b + q] - t[q];
+    }
+    for (; b <= a; ++b) {
       const double* lb = F + (w + b) * ld;
       double t = 0;
       for (int k = 0; k < w; ++k) t += la[k] * lb[k];
@@ -542,36 +570,50 @@ static void front_factor(Factor& fac, int s, std::vector<double>& Fm, int h,
     }
   };
   if (par) parallel_for(hb, syrk_row, 4); else for (int a = 0; a < hb; ++a) syrk_row(a);
-  // Linv = L_dd^{-1} (lower, packed rows) and M = L_od Linv
+  // Linv = L_dd^{-1} (lower, packed rows) and M = L_od Linv.  The inverse is
+  // built column by column into the rows of LinvT (LinvT[c][k] = Linv[k][c]),
+  // so that both the substitutions and the rows of M are contiguous dot
+  // products (the same terms in the same order as over the columns of Linv).
   double* out = fac.vals.data() + fac.valoff[s];
-  std::vector<double> Linv((size_t)w * w, 0.0);
+  std::vector<double> LinvT((size_t)w * w, 0.0);
   auto inv_col = [&](int64_t cc) {
     // column c of the inverse: forward substitution L x = e_c
     const int c = (int)cc;
-    Linv[(size_t)c * w + c] = 1.0 / F[c * ld + c];
+    double* x = LinvT.data() + (size_t)c * w;
+    x[c] = 1.0 / F[c * ld + c];
     for (int r = c + 1; r < w; ++r) {
       const double* rr = F + r * ld;
       double t = 0;
-      for (int k = c; k < r; ++k) t += rr[k] * Linv[(size_t)k * w + c];
-      Linv[(size_t)r * w + c] = -t / rr[r];
+      for (int k = c; k < r; ++k) t += rr[k] * x[k];
+      x[r] = -t / rr[r];
     }
   };
   if (par && w > 128) parallel_for(w, inv_col, 8);
   else for (int c = 0; c < w; ++c) inv_col(c);
   int64_t o = 0;
   for (int r = 0; r < w; ++r)
-    for (int c = 0; c <= r; ++c) out[o++] = Linv[(size_t)r * w + c];
+    for (int c = 0; c <= r; ++c) out[o++] = LinvT[(size_t)c * w + r];
   double* Mo = out + o;
-  auto m_row = [&](int64_t a) {
-    const double* la = F + (w + a) * ld;
-    double* ma = Mo + a * w;
+  // rows of M four at a time (rows past hb repeat the last row, stored once)
+  auto m_rows = [&](int64_t blk) {
+    const int64_t a0 = 4 * blk, na = std::min<int64_t>(4, hb - a0);
+    const double* la[4];
+    for (int q = 0; q < 4; ++q) la[q] = F + (w + a0 + std::min<int64_t>(q, na - 1)) * ld;
     for (int c = 0; c < w; ++c) {
-      double t = 0;
-      for (int k = c; k < w; ++k) t += la[k] * Linv[(size_t)k * w + c];
-      ma[c] = t;
+      const double* xc = LinvT.data() + (size_t)c * w;
+      double t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+      for (int k = c; k < w; ++k) {
+        const double x = xc[k];
+        t0 += la[0][k] * x;
+        t1 += la[1][k] * x;
+        t2 += la[2][k] * x;
+        t3 += la[3][k] * x;
+      }
+      const double tq[4] = {t0, t1, t2, t3};
+      for (int q = 0; q < na; ++q) Mo[(a0 + q) * w + c] = tq[q];
     }
   };
-  if (par) parallel_for(hb, m_row, 4); else for (int a = 0; a < hb; ++a) m_row(a);
+  if (par) parallel_for(hb4, m_rows, 1); else for (int64_t r = 0; r < hb4; ++r) m_rows(r);
 }
 
 static void order_and_factor(HostMesh& hm) {
