@@ -122,3 +122,28 @@ def test_adjoint_degenerate_right_hand_sides(torch):
     # the mesh state is unchanged: the next adjoint gives the same bits again
     g3 = mesh.solve_grad(dq)
     assert np.array_equal(g1, g3)
+
+
+def test_adjoint_on_a_mixed_precision_mesh(torch):
+    # form (1) with the adjoint: on a mixed-precision mesh the Hessian-vector
+    # products stay FP64 and only the preconditioner (the stored FP32 block
+    # inverses) changes, so dL/da matches the FP64 mesh's and the oracle's
+    # q-space adjoint within the mixed path's state accuracy
+    from paper_2006_08821_amd.emu import Mesh
+    p, markers, target = _problem()
+    g = {}
+    for prec in ("fp64", "mixed"):
+        mesh = Mesh(p, precision=prec)
+        q, st = mesh.solve(grad_tol=1e-11, max_iters=5000)
+        assert st["status"] == 0, (prec, st)
+        _, dq = _loss_and_grad(torch, q, markers, target)
+        g[prec], ast = mesh.solve_grad(dq, stats=True)
+        assert ast["status"] == 0 and ast["iters"] > 0, (prec, ast)
+        print(prec, "adjoint steps", ast["iters"], flush=True)
+        mesh.close()
+    M = omesh.build(p, modes=False)
+    qo = ofem.moreau_solve(M, p.activation, tol=1e-13)["q"]
+    _, go = oadj.activation_gradient(M, p.activation, qo, markers, target)
+    scale = np.abs(go).max()
+    assert np.abs(g["mixed"] - g["fp64"]).max() <= 1e-5 * scale, (g, go)
+    assert np.abs(g["mixed"] - go).max() <= 1e-5 * scale, (g, go)
