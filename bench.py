@@ -34,7 +34,7 @@ FP64_PEAK_TFLOPS = 78.6
 
 # Algorithmic bytes per element of each HBM-bound kernel (FP64 path; unique
 # bytes: static element data, state and intermediates, vertex gathers counted
-# once per vertex with n/m from the mesh).  See the design notes.
+# once per vertex with n/m from the mesh).
 STATIC_B = 148          # 4 ids, D_m^-1, vol, mu, lhat, w, fiber, group
 
 
@@ -470,8 +470,10 @@ def main():
                     help="also run a plain device copy of this many MiB (for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only; multi-GPU runs are not supported "
-              "(the sharded design is described in the design notes).", file=sys.stderr)
+        print("bench.py: measures one GPU only; runs on more than one GPU are not supported "
+              "(the path would split each mesh's elements over the GPUs and all-reduce the Woodbury "
+              "Gram and the line-search sums; not implemented here).",
+              file=sys.stderr)
         sys.exit(2)
     out = run(args)
     if args.calibrate_copy_mib > 0:
