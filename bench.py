@@ -334,7 +334,8 @@ def serving(args):
     probs = [wl.serving_problem(r["dims"], r["activation"], r["pin_mode"]) for r in trace]
     opts = dict(grad_tol=args.serve_tol, max_iters=args.serve_max_iters, warm_start=0)
 
-    srv = Server(max_slots=args.serve_slots, setup_threads=args.serve_setup_threads)
+    srv = Server(max_slots=args.serve_slots, setup_threads=args.serve_setup_threads,
+                 iters_per_round=args.serve_iters_per_round)
     tickets = [None] * len(probs)
     t_start = time.perf_counter()
 
@@ -464,6 +465,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-setup-threads", type=int, default=0,
                     help="host threads for mesh setups (0: the library default)")
+    ap.add_argument("--serve-iters-per-round", type=int, default=0,
+                    help="iterations per scheduler round (0: the library default)")
     ap.add_argument("--alpha-search", type=int, default=1, help="run the alpha-search leg (0: skip)")
     ap.add_argument("--adjoint", type=int, default=1, help="run the adjoint leg (0: skip)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
