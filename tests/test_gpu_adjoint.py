@@ -147,3 +147,27 @@ def test_adjoint_on_a_mixed_precision_mesh(torch):
     scale = np.abs(go).max()
     assert np.abs(g["mixed"] - g["fp64"]).max() <= 1e-5 * scale, (g, go)
     assert np.abs(g["mixed"] - go).max() <= 1e-5 * scale, (g, go)
+
+
+def test_solve_and_adjoint_without_modes(torch):
+    # the degenerate case k = 0 (no low-rank correction: the quasi-Newton
+    # Hessian is the block-diagonal part alone, and the adjoint's
+    # preconditioner the block inverses): the solve still reaches the
+    # oracle's minimizer and dL/da its q-space adjoint
+    from paper_2006_08821_amd.emu import Mesh
+    p, markers, target = _problem()
+    mesh = Mesh(p, n_modes=0)
+    assert mesh.info()["n_modes"] == 0
+    q, st = mesh.solve(grad_tol=1e-11, max_iters=20000)
+    assert st["status"] == 0, st
+    _, dq = _loss_and_grad(torch, q, markers, target)
+    g, ast = mesh.solve_grad(dq, stats=True)
+    assert ast["status"] == 0 and ast["iters"] > 0, ast
+    print("k = 0: iterations", st["iters"], "adjoint steps", ast["iters"], flush=True)
+    mesh.close()
+    M = omesh.build(p, modes=False)
+    qo = ofem.moreau_solve(M, p.activation, tol=1e-13)["q"]
+    qn = q.cpu().numpy()
+    assert np.abs(qn - qo).max() <= 1e-6 * np.abs(qo - M.rest).max()
+    _, go = oadj.activation_gradient(M, p.activation, qo, markers, target)
+    assert np.abs(g - go).max() <= 1e-6 * np.abs(go).max(), (g, go)
