@@ -271,8 +271,10 @@ emu_status emu_solve(emu_mesh* mesh, const emu_solve_opts* opts, double* q_out,
 emu_status emu_solve_grad(emu_mesh* mesh, const double* dL_dq, double* dL_da,
                           emu_solve_stats* stats, void* stream);
 
-/* emu_solve_grad for callers that cannot allocate device memory (code under
-   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+/* emu_solve_grad for callers that cannot allocate device memory (tight
+   serving loops, harnesses that forbid hipMalloc, processes that must not
+   allocate while other work is captured into HIP graphs; the call itself
+   waits on the mesh stream between groups of steps, so it cannot be captured):
    same arguments, result and errors, but its conjugate-gradient vectors and
    partial sums live in one fixed device scratch array of the library
    (48 MiB per GPU, held until the process ends) instead of memory the mesh
