@@ -57,6 +57,23 @@ def test_factor_solve_matches_superlu(name, make):
     assert np.abs(M.L @ x - y).max() <= 1e-12 * np.abs(y).max()
 
 
+def test_factor_solve_matches_superlu_with_wide_fronts():
+    # a mesh whose top fronts run the factorization's multi-threaded dense
+    # kernels (diagonal blocks over 128 wide, hundreds of off-diagonal rows,
+    # row counts that are not multiples of the four- and eight-wide blocks)
+    p = wl.limb(14, 14, 56)
+    hs = HostSetup(p, n_modes=0)
+    info = hs.info()
+    assert info["n_supernodes"] > 100
+    M = msh.build(p, modes=False)
+    rng = np.random.default_rng(1)
+    b = rng.normal(size=(p.n_vertices, 3))
+    x = hs.solve(b)
+    xr = np.zeros_like(b)
+    xr[M.free] = M.lu.solve(b[M.free])
+    assert np.abs(x - xr).max() <= 1e-11 * np.abs(xr).max()
+
+
 @pytest.mark.parametrize("name,make", CASES)
 def test_geometry_matches_oracle(name, make):
     p = make()
