@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <chrono>
 #include <cmath>
@@ -10,6 +11,7 @@
 #include <new>
 #include <random>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "mesh_impl.hpp"
@@ -472,17 +474,37 @@ std::shared_ptr<const emu::DevImage> emu::prepare_image(const emu::HostMesh& hm)
       // transposed blocks for the backward sweep: row c holds column c of
       // [Linv; M] from row c down (entries r = c .. h-1)
       std::vector<double> tv(fac.vals.size());
-      for (int s = 0; s < fac.ns; ++s) {
+      // in tiles of 64 rows (each column's 64 entries are written together
+      // while the 64 source rows are read side by side), supernodes spread
+      // over the host's threads, largest first
+      auto transpose_sn = [&](int s) {
         const int64_t w = fac.w[s], h = fac.h[s];
         const double* A = fac.vals.data() + fac.valoff[s];
         double* T = tv.data() + fac.valoff[s];
         const int64_t tri = w * (w + 1) / 2;
-        for (int64_t c = 0; c < w; ++c) {
-          double* row = T + c * h - c * (c - 1) / 2;
-          for (int64_t r = c; r < h; ++r)
-            row[r - c] = r < w ? A[r * (r + 1) / 2 + c] : A[tri + (r - w) * w + c];
+        for (int64_t r0 = 0; r0 < h; r0 += 64) {
+          const int64_t r1 = std::min(h, r0 + 64), cmax = std::min(w, r1);
+          for (int64_t c = 0; c < cmax; ++c) {
+            double* row = T + c * h - c * (c - 1) / 2 - c;  // row[r]: entry r >= c
+            for (int64_t r = std::max(r0, c); r < r1; ++r)
+              row[r] = r < w ? A[r * (r + 1) / 2 + c] : A[tri + (r - w) * w + c];
+          }
         }
-      }
+      };
+      std::vector<int> order(fac.ns);
+      for (int s = 0; s < fac.ns; ++s) order[s] = s;
+      std::sort(order.begin(), order.end(), [&](int a, int b) {
+        return (int64_t)fac.w[a] * fac.h[a] > (int64_t)fac.w[b] * fac.h[b];
+      });
+      std::atomic<int> next(0);
+      auto worker = [&]() {
+        for (int k; (k = next.fetch_add(1)) < fac.ns;) transpose_sn(order[k]);
+      };
+      const int nt = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
+      std::vector<std::thread> th;
+      for (int t = 1; t < nt; ++t) th.emplace_back(worker);
+      worker();
+      for (auto& t : th) t.join();
       B.put(SLOT(tvals), tv);
     }
     B.put(SLOT(dst), dst);
